@@ -1,0 +1,256 @@
+#!/usr/bin/env python
+"""Benchmark of the LGDM hot path on one MI355X.
+
+A step is one Newton iteration of Algorithm 2 along the load path of the
+workload: compute and assemble K and F (Gauss-point kernel + node-row
+assembly kernel), the per-field residual test, the linear solve (BiCGSTAB +
+block-Jacobi) and the update of the primary fields; converged increments
+are committed (Eq. A.2) and the next increment begins, inside the timed
+region.  Inputs are resident in HBM before timing starts.
+
+Metric: assembled Gauss points per second (nGP x assemblies / device time
+of the assembly kernels, HIP events on the library's stream) and Newton-step
+ms, in the FP32-mixed precision the workload names, with the plain FP64 path
+run beside it on the same GPU; Newton converges to ||R||/||F|| < 1e-8 per
+field.
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "assembled Gauss pts/s + Newton-step ms, FP32-mixed vs FP64, ||R||/||F||<1e-8"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "c3": "3D notched beam, three-point bending, 256x64x32 hex8 (524,288 elements, 4,194,304 "
+          "Gauss points, 2,205,060 dofs), notch E x 0.01, 150 increments to 0.5 mm",
+    "c2": "3D notched beam, three-point bending, 128x32x16 hex8 (65,536 elements, 524,288 Gauss "
+          "points, 289,476 dofs), notch E x 0.01, 150 increments to 0.5 mm",
+    "c1": "2D plane-stress single-edge-notched plate 200x100 Q4 (80,000 Gauss points, 60,903 "
+          "dofs), 200 increments to 0.1 mm",
+    "c0": "1D bar, 100 line2 elements, 100 increments to 0.02 mm",
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+class PathRunner:
+    """Drives Newton iterations along the load path through the C ABI."""
+
+    def __init__(self, ctx, prob, opts, binding):
+        self.ctx, self.prob, self.opts, self.b = ctx, prob, opts, binding
+        self.inc = 0                  # committed increments
+        self.in_inc = False
+        self.rep = None
+        self.newton_in_inc = 0
+        self.verbose = True
+
+    def step(self, acc):
+        """Run until one linear solve has happened (one Newton iteration);
+        accumulate the device-time split in acc."""
+        while True:
+            if not self.in_inc:
+                lam = (self.inc + 1) / self.prob.n_increments
+                self.ctx.begin_increment(lam)
+                self.in_inc = True
+                self.rep = self.b.IncrementReport()
+                self.newton_in_inc = 0
+            before = (self.rep.t_assembly_ms, self.rep.t_solve_ms, self.rep.t_update_ms,
+                      self.rep.n_assemblies, self.rep.krylov_iters)
+            conv, r = self.ctx.newton_iteration(self.opts, self.rep)
+            if self.verbose:
+                log("  inc %d it %d |R_u|/|F_u|=%.3e |R_e|/|F_e|=%.3e krylov=%d restarts=%d "
+                    "asm=%.3fms solve=%.1fms" % (
+                        self.inc + 1, self.newton_in_inc, r.res_u / max(r.ref_u, 1e-300),
+                        r.res_e / max(r.ref_e, 1e-300), r.krylov_iters - before[4], r.restarts,
+                        r.t_assembly_ms - before[0], r.t_solve_ms - before[1]))
+            acc["t_asm"] += r.t_assembly_ms - before[0]
+            acc["t_sol"] += r.t_solve_ms - before[1]
+            acc["t_upd"] += r.t_update_ms - before[2]
+            acc["n_asm"] += r.n_assemblies - before[3]
+            acc["krylov"] += r.krylov_iters - before[4]
+            if conv:
+                self.ctx.commit_increment()
+                self.inc += 1
+                self.in_inc = False
+                acc["increments"] += 1
+                acc["last_rel_u"] = r.res_u / max(r.ref_u, 1e-300)
+                acc["last_rel_e"] = r.res_e / max(r.ref_e, 1e-300)
+                continue
+            self.newton_in_inc += 1
+            if self.newton_in_inc > self.opts.max_newton:
+                raise RuntimeError("Newton did not converge in increment %d" % (self.inc + 1))
+            return
+
+
+def new_acc():
+    return dict(t_asm=0.0, t_sol=0.0, t_upd=0.0, n_asm=0, krylov=0, increments=0,
+                last_rel_u=None, last_rel_e=None)
+
+
+def algorithmic_bytes(prob, nnz, npairs, s_val):
+    """Per launch: assembly (reads x, coords, conn, kappa_n, E-scale; writes
+    CSR values and R) and SpMV (values, node-graph columns, offsets, x, y)."""
+    ndof, nn, ne, ng = prob.ndof, prob.n_nodes, prob.n_elems, prob.n_elems * prob.ngp
+    asm = (ndof * 8 + nn * prob.dim * 8 + ne * prob.nen * 4 + ng * 8 + ne * 8
+           + nnz * s_val + ndof * 8)
+    spmv = nnz * s_val + npairs * 4 + (ndof + 1) * 4 + (nn + 1) * 4 + ndof * s_val * 2
+    return asm, spmv
+
+
+def run_precision(prob, precision, args, binding):
+    import torch
+    ctx = binding.Context(device=0, precision=precision)
+    t0 = time.time()
+    ctx.setup_problem(prob)
+    torch.cuda.synchronize()
+    log("setup %.2fs precision=%s ndof=%d nGP=%d" % (time.time() - t0, precision, ctx.ndof, ctx.ngauss))
+    opts = binding.solver_opts(max_newton=30, tol_newton=1e-8, tol_krylov=args.tol_krylov,
+                               max_krylov=args.max_krylov, check_every=32)
+    runner = PathRunner(ctx, prob, opts, binding)
+    warm = new_acc()
+    for i in range(args.warmup):
+        runner.step(warm)
+        log("warmup step %d done (increment %d, krylov %d)" % (i + 1, runner.inc + 1, warm["krylov"]))
+    acc = new_acc()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        runner.step(acc)
+        log("step %d done (increment %d, krylov so far %d)" % (i + 1, runner.inc + 1, acc["krylov"]))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    view, _ = ctx.assemble(-1.0, want_R=False)
+    kt = ctx.kernel_times(args.kernel_reps)
+    nnz = view.nnz
+    npairs = nnz // (prob.ndpn ** 2)
+    s_val = 4 if precision == binding.MIXED else 8
+    asm_b, spmv_b = algorithmic_bytes(prob, nnz, npairs, s_val)
+    ng = ctx.ngauss
+    res = {
+        "gp_per_s": ng * acc["n_asm"] / (acc["t_asm"] / 1e3) if acc["t_asm"] > 0 else None,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "phase_ms_per_step": {"assembly": acc["t_asm"] / args.steps, "solve": acc["t_sol"] / args.steps,
+                              "update": acc["t_upd"] / args.steps},
+        "assemblies": acc["n_asm"], "krylov_iters": acc["krylov"],
+        "krylov_iters_per_step": acc["krylov"] / args.steps,
+        "increments_committed": runner.inc, "increments_in_timed_region": acc["increments"],
+        "kernel_ms": {"gauss_point": kt[0], "node_assembly": kt[1], "spmv": kt[2], "block_jacobi": kt[3]},
+        "assembly_bytes": asm_b, "spmv_bytes": spmv_b,
+        "assembly_gbs": asm_b / ((kt[0] + kt[1]) * 1e-3) / 1e9,
+        "spmv_gbs": spmv_b / (kt[2] * 1e-3) / 1e9,
+        "footprint_gb": ctx.footprint() / 1e9,
+    }
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(prob, budget_s=20.0):
+    """The oracle on the host cores: assembled Gauss points per second on a
+    bounded slab of the same mesh (element evaluation + triplet assembly)."""
+    import numpy as np
+    from oracle.lgdm import eval_elements, assemble
+    import lgdm_workloads as W
+    x, kn = W.injected_state(prob, seed=0, noise=0.02, kappa_spread=1.5)
+    mat = prob.material.as_dict()
+    n_el = min(prob.n_elems, 2048)
+    done_el = 0
+    t0 = time.perf_counter()
+    while True:
+        sl = np.arange(done_el, done_el + n_el) % prob.n_elems
+        ev = eval_elements(prob.dim, prob.coords, prob.conn, prob.e_scale, mat, x, kn, elems=sl)
+        assemble(prob.dim, prob.conn[sl], prob.n_nodes, ev["fint"], ev["Ke"])
+        done_el += n_el
+        if time.perf_counter() - t0 > budget_s or done_el >= prob.n_elems:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": done_el * prob.ngp / dt, "unit": "GP/s", "cores": 1, "kind": "oracle",
+            "sample": "oracle element evaluation + triplet assembly of %d of %d elements "
+                      "(%.1f s, numpy einsum, single thread; host has %d cores)"
+                      % (done_el, prob.n_elems, dt, os.cpu_count())}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tol-krylov", type=float, default=1e-6)
+    ap.add_argument("--max-krylov", type=int, default=20000)
+    ap.add_argument("--kernel-reps", type=int, default=5)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU: the LGDM hot path here is built and measured on a single "
+              "MI355X; multi-GPU runs are not part of this build (requested --gpus %d)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    import lgdm_workloads as W
+    from paper_2301_06503_amd import binding
+    prob = W.config(args.config)
+    prec = binding.MIXED if args.precision == "mixed" else binding.FP64
+    main_res = run_precision(prob, prec, args, binding)
+    fp64_res = None
+    if prec == binding.MIXED and not args.no_fp64_compare:
+        fp64_res = run_precision(prob, binding.FP64, args, binding)
+    # dominant kernel of a Newton step: SpMV (2 per Krylov iteration) vs assembly
+    kt = main_res["kernel_ms"]
+    spmv_share = 2 * main_res["krylov_iters_per_step"] * kt["spmv"]
+    asm_share = kt["gauss_point"] + kt["node_assembly"]
+    if spmv_share >= asm_share:
+        achieved = main_res["spmv_gbs"]
+        kern = "spmv"
+    else:
+        achieved = main_res["assembly_gbs"]
+        kern = "assembly"
+    roofline = {"bound": "hbm", "kernel": kern, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+    roof_asm = {"bound": "hbm", "kernel": "gauss_point+node_assembly",
+                "achieved": round(main_res["assembly_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(main_res["assembly_gbs"] / HBM_PEAK_GBS, 4)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(prob)
+    out = {
+        "metric": METRIC,
+        "value": main_res["gp_per_s"],
+        "unit": "GP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if prec == binding.MIXED else "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.config], "name": args.config,
+                   "precision": args.precision, "ndof": prob.ndof, "gauss_points": prob.n_elems * prob.ngp,
+                   "tol_newton": 1e-8, "tol_krylov": args.tol_krylov},
+        "roofline": roofline,
+        "roofline_assembly": roof_asm,
+        "cpu_baseline": cpu,
+        "detail": main_res,
+        "fp64": fp64_res,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

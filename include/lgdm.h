@@ -1,0 +1,251 @@
+/*
+ * lgdm.h -- C ABI of the MI355X localizing-gradient-damage (LGDM) hot path.
+ *
+ * The library solves the coupled displacement / micro-equivalent-strain
+ * problem of the localizing gradient damage method by the incremental-
+ * iterative Newton procedure of the paper's Algorithm 2: each Newton
+ * iteration evaluates every Gauss point (Appendix A, Eqs. A.1-A.4), forms the
+ * element tangent blocks and internal forces (Eqs. 11a-11f), assembles them
+ * into a sparse unsymmetric CSR tangent and residual, solves Eq. 11 and
+ * updates the primary fields; converged increments commit the history
+ * variable (Eq. A.2).  The calls follow the paper's statement of the
+ * problem (Algorithms 1-2, "Input: Geometry, Material properties, Loads and
+ * boundary conditions; Output: Damage and Structural response").
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Every call returns an lgdm_status; no exception crosses the ABI.
+ *    lgdm_last_error(ctx) returns a message for the last failing call.
+ *  - Host input arrays are copied; the caller keeps ownership.  Pointer
+ *    arguments marked "host or device" may point to either (HIP unified
+ *    addressing decides the copy direction).
+ *  - Device arrays returned by the library are owned by the context and stay
+ *    valid until the next call that changes the mesh or lgdm_destroy.
+ *  - All device work is enqueued on the stream given to lgdm_create; calls
+ *    that return host values synchronise that stream.
+ *  - Indices are 0-based.  Counts in the ABI are int64; the library's CSR
+ *    uses int32 indices and rejects meshes with nnz >= 2^31.
+ *  - dofs are node-interleaved: dof = node * (dim + 1) + comp, with comp in
+ *    [0, dim) the displacement components and comp = dim the
+ *    micro-equivalent strain (ebar).
+ *  - Gauss-point arrays are indexed element * 2^dim + g with
+ *    g = i_xi + 2 i_eta + 4 i_zeta (2-point Gauss-Legendre per direction).
+ *  - One context per host thread.
+ */
+#ifndef LGDM_H
+#define LGDM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lgdm_status;
+enum {
+  LGDM_OK = 0,
+  LGDM_ERR_INVALID_ARG = 1,  /* bad argument or call order; nothing changed   */
+  LGDM_ERR_OOM = 2,          /* device allocation failed                       */
+  LGDM_ERR_DEVICE = 3,       /* HIP runtime error                              */
+  LGDM_ERR_NOT_CONVERGED = 4,/* Newton did not converge; committed state kept  */
+  LGDM_ERR_NAN = 5,          /* non-finite residual or solver scalar           */
+  LGDM_ERR_BREAKDOWN = 6,    /* Krylov breakdown that restarts did not cure    */
+  LGDM_ERR_STATE = 7         /* call needs a mesh / material / state first     */
+};
+
+enum { LGDM_FP64 = 0, LGDM_MIXED = 1 };          /* precision of a context      */
+enum { LGDM_LINE2 = 1, LGDM_QUAD4 = 2, LGDM_HEX8 = 3 };
+enum { LGDM_PLANE_STRESS = 0, LGDM_PLANE_STRAIN = 1 };
+
+/* fields for lgdm_query_state */
+enum {
+  LGDM_FIELD_X = 0,        /* [ndof]  primary vector (u and ebar, interleaved)    */
+  LGDM_FIELD_KAPPA = 1,    /* [nGP]   committed history variable kappa_n (A.2)    */
+  LGDM_FIELD_DAMAGE = 2,   /* [nGP]   committed damage D(kappa_n) (A.1)           */
+  LGDM_FIELD_KAPPA_TRIAL = 3, /* [nGP] kappa at the last assembly (A.2 update)    */
+  LGDM_FIELD_DAMAGE_TRIAL = 4,/* [nGP] D at the last assembly                     */
+  LGDM_FIELD_RESIDUAL = 5, /* [ndof]  R = -f_int of the last assembly, R_c = 0    */
+  LGDM_FIELD_REACTION = 6  /* [1]     sum of f_int,u over loaded dofs (last asm.) */
+};
+
+/* Material and numerical parameters (Eq. 1 and Appendix A).
+ *  E        undamaged Young's modulus            nu     Poisson's ratio
+ *  kappa0   damage threshold (A.1)               alpha, beta  damage law (A.1)
+ *  c        gradient parameter (Eq. 1)           R, eta interaction function (A.4)
+ *  k        compressive / tensile strength ratio (A.3)
+ *  h        coupling modulus (Eq. 1)
+ *  tol_hist, tol_dmg  bands of the vectorised history / damage update (Fig. 8b):
+ *           kappa <- ebar where ebar - kappa_n > tol_hist; D = 0 where
+ *           kappa - kappa0 < tol_dmg.  0 reproduces A.1 / A.2 literally.
+ *  plane    LGDM_PLANE_STRESS or LGDM_PLANE_STRAIN (2D only)
+ *  thickness  out-of-plane thickness (2D) or cross-section area (1D); 3D ignores it. */
+typedef struct lgdm_material {
+  double E, nu, kappa0, alpha, beta, c, R, eta, k, h, tol_hist, tol_dmg;
+  int32_t plane;
+  int32_t reserved;
+  double thickness;
+} lgdm_material;
+
+/* Newton / Krylov options.  Zero-initialised fields take the defaults shown. */
+typedef struct lgdm_solver_opts {
+  int32_t max_newton;      /* 30     Newton iterations per increment                */
+  int32_t max_krylov;      /* 20000  BiCGSTAB iterations per linear solve           */
+  double tol_newton;       /* 1e-8   per-field ||R|| <= tol * max(||F||, tiny)      */
+  double tol_krylov;       /* 1e-10  per-field ||r|| <= tol * ||b||                 */
+  int32_t check_every;     /* 16     Krylov iterations between host convergence reads */
+  int32_t max_restarts;    /* 8      BiCGSTAB restarts after breakdown              */
+} lgdm_solver_opts;
+
+/* Per-increment / per-iteration report (the paper's time-per-iteration split
+ * into assembly, solve and variable update, Sec. 3.1). */
+typedef struct lgdm_increment_report {
+  int32_t converged;
+  int32_t newton_iters;    /* linear solves performed                              */
+  int64_t krylov_iters;    /* BiCGSTAB iterations, summed over the solves          */
+  double res_u, res_e;     /* ||R_u||, ||R_ebar|| at the last assembly             */
+  double ref_u, ref_e;     /* ||f_int,u||, ||int N h eeq|| at the last assembly     */
+  double du_norm, de_norm; /* ||delta u||, ||delta ebar|| of the last solve        */
+  double reaction;         /* sum of f_int,u over loaded dofs                      */
+  double max_damage;       /* max over Gauss points of D at the last assembly      */
+  double t_assembly_ms;    /* device time in assembly (H1-H5) over the increment   */
+  double t_solve_ms;       /* device time in the linear solves                      */
+  double t_update_ms;      /* device time in update / norms / commit               */
+  int32_t n_assemblies;
+  int32_t restarts;
+} lgdm_increment_report;
+
+/* View of the assembled tangent.  Device pointers owned by the context. */
+typedef struct lgdm_csr_view {
+  int64_t nrows, nnz;
+  const int32_t* row_ptr;  /* [nrows + 1]                                     */
+  const int32_t* col_idx;  /* [nnz], ascending within each row                */
+  const double* vals;      /* [nnz] FP64 values (FP64 contexts; else NULL)    */
+  const float* vals32;     /* [nnz] FP32 values (mixed contexts; else NULL)   */
+} lgdm_csr_view;
+
+typedef struct lgdm_ctx lgdm_ctx;
+
+/* Create a context on HIP device `device`, enqueueing on `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  precision: LGDM_FP64 or
+ * LGDM_MIXED (FP32 tangent, preconditioner and inner SpMV; FP64 residual,
+ * history/damage update, Krylov dot products and Newton update). */
+lgdm_status lgdm_create(lgdm_ctx** out, int32_t device, void* hip_stream, int32_t precision);
+lgdm_status lgdm_destroy(lgdm_ctx* ctx);
+const char* lgdm_last_error(const lgdm_ctx* ctx);
+
+/* Route the context's device allocations through a caller allocator (e.g.
+ * PyTorch's caching allocator).  alloc(bytes, user) returns a device pointer
+ * or NULL; free(ptr, user) releases it.  Must be called before
+ * lgdm_upload_mesh.  Without it the library uses hipMalloc / hipFree. */
+lgdm_status lgdm_set_allocator(lgdm_ctx* ctx, void* (*alloc)(size_t, void*),
+                               void (*free_fn)(void*, void*), void* user);
+
+/* Geometry and connectivity (the "Geometry" input of Algorithm 2) and the
+ * once-per-mesh work: dof numbering, node graph, CSR pattern of all
+ * element-coupled dof pairs (structural zeros kept), node-to-element lists
+ * (Fig. 2 assembly hoisted out of the Newton loop).
+ *  dim        1, 2 or 3; elem_type LGDM_LINE2 / LGDM_QUAD4 / LGDM_HEX8 matching dim
+ *  coords     host, [n_nodes * dim] FP64, node-major
+ *  conn       host, [n_elems * 2^dim] int32, local node order line2 (x0, x1),
+ *             quad4 counter-clockwise, hex8 bottom face then top face
+ *  e_scale    host, [n_elems] factor on the elasticity tensor only, or NULL (1)
+ * Resets the state (x = 0, kappa_n = 0, increment 0).  INVALID_ARG for bad
+ * sizes, out-of-range node ids, a node shared by more elements or neighbours
+ * than the kernels handle (see lgdm_last_error), or nnz >= 2^31. */
+lgdm_status lgdm_upload_mesh(lgdm_ctx* ctx, int32_t dim, int32_t elem_type, int64_t n_nodes,
+                             const double* coords, int64_t n_elems, const int32_t* conn,
+                             const double* e_scale);
+
+/* Material parameters ("Material properties" input).  INVALID_ARG if
+ * E <= 0, nu outside (-1, 0.5), kappa0 <= 0, k <= 0, h <= 0, eta <= 0 or c < 0. */
+lgdm_status lgdm_set_material(lgdm_ctx* ctx, const lgdm_material* m);
+
+/* Dirichlet conditions on displacement dofs ("Loads and boundary
+ * conditions"): u[dofs[i]] = lambda * ref_values[i] during the increment
+ * with load factor lambda.  dofs, ref_values: host, [n].  Constrained rows and
+ * columns of the tangent are identity, their residual entries zero.  Dofs
+ * with a nonzero ref value are the loaded dofs whose internal forces sum to
+ * the reaction.  INVALID_ARG for an ebar dof or an out-of-range dof. */
+lgdm_status lgdm_set_dirichlet(lgdm_ctx* ctx, int64_t n, const int64_t* dofs,
+                               const double* ref_values);
+
+/* Algorithm 2 "Compute and Assemble K" and "Compute and Assemble F" at the
+ * current state (x, kappa_n): Gauss-point update (Eqs. A.1-A.4), element
+ * tangents (Eqs. 11a-d) and residual R = -f_int (Eqs. 11e-f), deterministic
+ * assembly, Dirichlet rows/columns.  If lambda >= 0 the constrained dofs are
+ * first set to lambda * ref.  K_out (nullable) receives a view of the CSR
+ * tangent; R_out (nullable, host or device, [ndof]) receives R.  Stores the
+ * trial kappa / D and the residual norms of this assembly. */
+lgdm_status lgdm_assemble_tangent_residual(lgdm_ctx* ctx, double lambda, lgdm_csr_view* K_out,
+                                           double* R_out);
+
+/* Solve the assembled tangent K delta = b with right-preconditioned
+ * BiCGSTAB and per-node block-Jacobi (Eq. 11, Algorithm 2 "Solve").
+ * b, delta: host or device, [ndof].  delta receives the solution; rep
+ * (nullable) receives krylov_iters and restarts.  Needs a prior assembly. */
+lgdm_status lgdm_solve_linear(lgdm_ctx* ctx, const double* b, double* delta,
+                              const lgdm_solver_opts* o, lgdm_increment_report* rep);
+
+/* One load increment of Algorithm 2 with load factor lambda: set the
+ * constrained dofs, iterate {assemble, convergence test, solve, update}
+ * until the per-field residual test holds, then commit the history variable
+ * (Eq. A.2).  On LGDM_ERR_NOT_CONVERGED / NAN / BREAKDOWN the state returns to
+ * the last committed increment.  o, rep nullable. */
+lgdm_status lgdm_solve_increment(lgdm_ctx* ctx, double lambda, const lgdm_solver_opts* o,
+                                 lgdm_increment_report* rep);
+
+/* The same increment split into steps, so one Newton iteration can be
+ * driven and timed on its own:
+ *  lgdm_begin_increment   saves the committed state, sets u_c = lambda * ref;
+ *  lgdm_newton_iteration  assembles; if the residual test holds sets
+ *                         *converged = 1 and returns, else solves and
+ *                         updates x (Algorithm 2 update of primary variables);
+ *  lgdm_commit_increment  commits kappa_n and D from the last assembly;
+ *  lgdm_abort_increment   restores the saved committed state. */
+lgdm_status lgdm_begin_increment(lgdm_ctx* ctx, double lambda);
+lgdm_status lgdm_newton_iteration(lgdm_ctx* ctx, const lgdm_solver_opts* o, int32_t* converged,
+                                  lgdm_increment_report* rep);
+lgdm_status lgdm_commit_increment(lgdm_ctx* ctx);
+lgdm_status lgdm_abort_increment(lgdm_ctx* ctx);
+
+/* Device views of the CSR pattern and connectivity (owned by ctx). */
+lgdm_status lgdm_get_csr(lgdm_ctx* ctx, int64_t* nrows, int64_t* nnz, const int32_t** row_ptr,
+                         const int32_t** col_idx);
+lgdm_status lgdm_get_connectivity(lgdm_ctx* ctx, const int32_t** conn, int64_t* n_elems,
+                                  int32_t* nen);
+/* Sizes: ndof, number of Gauss points, committed increment count. */
+lgdm_status lgdm_get_sizes(lgdm_ctx* ctx, int64_t* ndof, int64_t* n_gauss, int64_t* increment);
+
+/* Copy a field (LGDM_FIELD_*) into out (host or device) of n entries; n must
+ * equal the field's size. */
+lgdm_status lgdm_query_state(lgdm_ctx* ctx, int32_t field, double* out, int64_t n);
+
+/* Inject a state: x (host or device, [ndof]) and kappa_n (host or device,
+ * [nGP]); either may be NULL to keep the current one.  D_n is recomputed
+ * from kappa_n (A.1).  increment sets the committed increment counter. */
+lgdm_status lgdm_set_state(lgdm_ctx* ctx, const double* x, const double* kappa_n,
+                           int64_t increment);
+
+/* Parity aid: element tangents and internal forces of elements [e0, e1) at
+ * the last assembled state, in the node-interleaved local order
+ * (local dof a * (dim + 1) + comp).  Ke_out: host or device,
+ * [(e1 - e0) * (nen (dim+1))^2], row-major; fe_out: [(e1 - e0) * nen (dim+1)].
+ * Either may be NULL.  Values are FP64 in both precisions. */
+lgdm_status lgdm_debug_element_blocks(lgdm_ctx* ctx, int64_t e0, int64_t e1, double* Ke_out,
+                                      double* fe_out);
+
+/* Measurement aid: average device time (ms, HIP events on the context's
+ * stream) of `reps` back-to-back launches of each hot kernel at the last
+ * assembled state: avg_ms[0] Gauss-point kernel, [1] node-row assembly
+ * kernel, [2] one SpMV with the assembled tangent, [3] block-Jacobi setup.
+ * Leaves the assembled matrix and state unchanged. */
+lgdm_status lgdm_kernel_times(lgdm_ctx* ctx, int32_t reps, double* avg_ms);
+
+/* Device bytes held by the context (mesh, pattern, state, matrix, solver). */
+lgdm_status lgdm_footprint(lgdm_ctx* ctx, int64_t* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LGDM_H */

@@ -315,14 +315,16 @@ def serving_stream(n_requests: int = 256, rate_per_s: float = 20.0, seed: int = 
 # --------------------------------------------------------------------------
 
 def injected_state(prob: Problem, seed: int, load: float = 1.0, noise: float = 0.25,
-                   kappa_spread: float = 3.0):
+                   kappa_spread: float = 3.0, ebar_scale: float = 1.0):
     """A seeded state (x, kappa_n) shaped like a mid-load-path state.
 
     x: the prescribed boundary displacement at load factor `load`
     interpolated linearly through the body, times (1 + noise * U[-1, 1]) per
     dof, plus an ebar field in the same magnitude range as the strains.
     kappa_n: U[0, kappa_spread * kappa0] per Gauss point, so that points fall
-    below and above the damage threshold.  Returns (x [ndof], kappa_n [nel*ngp]).
+    below and above the damage threshold.  ebar_scale scales the ebar field
+    (small values keep every point below the threshold).  Returns
+    (x [ndof], kappa_n [nel*ngp]).
     """
     rng = np.random.default_rng(seed)
     nd = prob.ndpn
@@ -337,8 +339,8 @@ def injected_state(prob: Problem, seed: int, load: float = 1.0, noise: float = 0
         x[c::nd] = base * (1.0 + noise * rng.uniform(-1, 1, prob.n_nodes)) \
             + noise * umax * rng.uniform(-1, 1, prob.n_nodes) * 0.1
     strain_scale = umax / lref
-    x[prob.dim::nd] = strain_scale * rng.uniform(0.2, 2.5, prob.n_nodes) \
-        + prob.material.kappa0 * rng.uniform(0.0, 2.0, prob.n_nodes)
+    x[prob.dim::nd] = ebar_scale * (strain_scale * rng.uniform(0.2, 2.5, prob.n_nodes)
+                                    + prob.material.kappa0 * rng.uniform(0.0, 2.0, prob.n_nodes))
     dofs = prob.bc_dofs()
     x[dofs] = prob.bc_values * load
     kappa_n = prob.material.kappa0 * kappa_spread * rng.uniform(0.0, 1.0, prob.n_elems * prob.ngp)

@@ -1,0 +1,796 @@
+// Gauss-point evaluation (H1-H2) and deterministic node-row assembly of the
+// element tangents and internal forces (H3-H5) of the localizing gradient
+// damage method.
+//
+// Kernel 1 (gp_kernel): one thread per Gauss point.  Gathers the element's
+//   coordinates and nodal (u, ebar), evaluates the Jacobian, the strain, the
+//   modified von Mises equivalent strain and its gradient (Eq. A.3), the
+//   micro-equivalent strain and its gradient, the history update (Eq. A.2 as
+//   the vectorised condition of Fig. 8b), damage (Eq. A.1) and interaction
+//   function (Eq. A.4), and writes a compact record of the Gauss point (J^-1
+//   and the scalar / tensor coefficients of Eqs. 11a-11f).
+//
+// Kernel 2 (node_kernel): one lane group per node a.  Lane (k, b) takes the
+//   k-th element adjacent to a (ascending element id) and the element's local
+//   node b and sums over the Gauss points the (dim+1)x(dim+1) block
+//   d f_a / d x_b of Eqs. 11a-11d; the lane of b = 0 also sums the element's
+//   internal force on node a (Eqs. 11e-11f).  The blocks are reduced per
+//   neighbour position in ascending element order through LDS and written
+//   once into the CSR row block of node a (no atomics, bitwise repeatable),
+//   with identity rows / zero columns for Dirichlet dofs.  Per-workgroup
+//   partial sums of the residual norms follow in a fixed order.
+//
+// Element law (readings of the paper shared with its executed code, Fig. 2):
+//   sigma = (1 - D) s_e C : eps, f_u = int B^T sigma,
+//   f_ebar = int N h (ebar - eeq) + grad N . (g h c grad ebar),
+//   K^uu = int (1-D) s_e [lam dN_a (x) dN_b + mu dN_b (x) dN_a + mu (dN_a.dN_b) I],
+//   K^ue = -int (s_e C:eps dN_a) D' chi N_b,   K^eu = -int N_a h (G dN_b),
+//   K^ee = int h N_a N_b + h c g' D' chi (dN_a . grad ebar) N_b + g h c dN_a . dN_b.
+#include <cmath>
+
+#include "lgdm_internal.h"
+
+namespace lgdm {
+
+namespace {
+
+template <int DIM> struct Elem {
+  static constexpr int NEN = 1 << DIM;
+  static constexpr int NGP = 1 << DIM;
+  static constexpr int ND = DIM + 1;
+};
+
+// reference node coordinate xi_a,d of the local node order: line2 (x0, x1);
+// quad4 counter-clockwise; hex8 bottom face then top face
+__device__ __forceinline__ double xi_node(int a, int d) {
+  if (d == 0) return ((a & 3) == 1 || (a & 3) == 2) ? 1.0 : -1.0;
+  if (d == 1) return ((a & 3) >= 2) ? 1.0 : -1.0;
+  return (a >= 4) ? 1.0 : -1.0;
+}
+
+// Gauss point coordinate: g = i_xi + 2 i_eta + 4 i_zeta, +-1/sqrt(3)
+__device__ __forceinline__ double xi_gp(int g, int d) {
+  const double s = 0.57735026918962576451;  // 1/sqrt(3)
+  return ((g >> d) & 1) ? s : -s;
+}
+
+// N_a and dN_a/dxi_j at Gauss point g (multilinear Lagrange functions)
+template <int DIM>
+__device__ __forceinline__ void shape_at(int a, int g, double& N, double dN[DIM]) {
+  double f[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) f[d] = 0.5 * (1.0 + xi_node(a, d) * xi_gp(g, d));
+  N = 1.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) N *= f[d];
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) {
+    double p = 0.5 * xi_node(a, j);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d)
+      if (d != j) p *= f[d];
+    dN[j] = p;
+  }
+}
+
+// index of the symmetric tensor entry (i, j) in the record ordering
+template <int DIM> __device__ __forceinline__ constexpr int sym_idx(int i, int j) {
+  if (DIM == 1) return 0;
+  if (DIM == 2) return (i == j) ? i : 2;
+  if (i == j) return i;
+  const int lo = i < j ? i : j, hi = i < j ? j : i;
+  return (lo == 0 && hi == 1) ? 3 : ((lo == 1 && hi == 2) ? 4 : 5);
+}
+
+// ---------------------------------------------------------------------------
+// Kernel 1: Gauss-point state and record
+// ---------------------------------------------------------------------------
+template <int DIM>
+__global__ void __launch_bounds__(256) gp_kernel(int64_t ngauss, const double* __restrict__ coords,
+                                                 const int32_t* __restrict__ conn,
+                                                 const double* __restrict__ e_scale,
+                                                 const double* __restrict__ x,
+                                                 const double* __restrict__ kappa_n, MatParams mp,
+                                                 double* __restrict__ rec,
+                                                 double* __restrict__ kappa_t,
+                                                 double* __restrict__ D_t) {
+  using E = Elem<DIM>;
+  using RC = Rec<DIM>;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= ngauss) return;
+  const int64_t e = gid / E::NGP;
+  const int g = (int)(gid - e * E::NGP);
+
+  double xe[E::NEN][DIM], ue[E::NEN][DIM], eb[E::NEN];
+#pragma unroll
+  for (int a = 0; a < E::NEN; ++a) {
+    const int64_t n = conn[e * E::NEN + a];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) xe[a][d] = coords[n * DIM + d];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) ue[a][i] = x[n * E::ND + i];
+    eb[a] = x[n * E::ND + DIM];
+  }
+  double N[E::NEN], dNx[E::NEN][DIM];
+  double J[DIM][DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d)
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) J[d][j] = 0.0;
+#pragma unroll
+  for (int a = 0; a < E::NEN; ++a) {
+    double dN[DIM];
+    shape_at<DIM>(a, g, N[a], dN);
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) dNx[a][j] = dN[j];  // reference gradient for now
+#pragma unroll
+    for (int d = 0; d < DIM; ++d)
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) J[d][j] += xe[a][d] * dN[j];
+  }
+  // J^-1 with (J^-1)_{j d} = d xi_j / d x_d
+  double Ji[DIM][DIM];
+  double detJ;
+  if (DIM == 1) {
+    detJ = J[0][0];
+    Ji[0][0] = 1.0 / detJ;
+  } else if (DIM == 2) {
+    detJ = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    const double r = 1.0 / detJ;
+    Ji[0][0] = J[1][1] * r;
+    Ji[0][1] = -J[0][1] * r;
+    Ji[1][0] = -J[1][0] * r;
+    Ji[1][1] = J[0][0] * r;
+  } else {
+    const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    detJ = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+    const double r = 1.0 / detJ;
+    // inverse of J (rows j = xi index, cols d = x index)
+    Ji[0][0] = c00 * r;
+    Ji[1][0] = c01 * r;
+    Ji[2][0] = c02 * r;
+    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * r;
+    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * r;
+    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * r;
+    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * r;
+    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * r;
+    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * r;
+  }
+  // physical gradients dN_a/dx_d = sum_j dN_a/dxi_j (J^-1)_{j d}
+#pragma unroll
+  for (int a = 0; a < E::NEN; ++a) {
+    double t[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) s += dNx[a][j] * Ji[j][d];
+      t[d] = s;
+    }
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) dNx[a][d] = t[d];
+  }
+  // displacement gradient, small strain tensor
+  double gu[DIM][DIM];
+#pragma unroll
+  for (int i = 0; i < DIM; ++i)
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      double s = 0.0;
+#pragma unroll
+      for (int a = 0; a < E::NEN; ++a) s += ue[a][i] * dNx[a][d];
+      gu[i][d] = s;
+    }
+  double eps[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+  for (int i = 0; i < DIM; ++i)
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) eps[i][j] = 0.5 * (gu[i][j] + gu[j][i]);
+  if (DIM == 2) eps[2][2] = mp.ezz_fac * (eps[0][0] + eps[1][1]);
+
+  // modified von Mises equivalent strain (A.3) and its gradient G = d eeq / d eps
+  double eeq;
+  double G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  if (DIM == 1) {
+    eeq = eps[0][0];
+    G[0][0] = 1.0;
+  } else {
+    const double I1 = eps[0][0] + eps[1][1] + eps[2][2];
+    double dev[3][3];
+    double J2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        dev[i][j] = eps[i][j] - (i == j ? I1 / 3.0 : 0.0);
+        J2 += dev[i][j] * dev[i][j];
+      }
+    J2 *= 0.5;
+    const double s = mp.c2 * mp.c2 * I1 * I1 + mp.c3 * J2;
+    if (s > 0.0) {
+      const double sq = sqrt(s);
+      eeq = mp.c1 * I1 + sq / (2.0 * mp.k);
+      const double f = 1.0 / (4.0 * mp.k * sq);
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          G[i][j] = (i == j ? mp.c1 + f * 2.0 * mp.c2 * mp.c2 * I1 : 0.0) + f * mp.c3 * dev[i][j];
+    } else {  // minimum-norm subgradient where the root argument vanishes
+      eeq = mp.c1 * I1;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) G[i][i] = mp.c1;
+    }
+    if (DIM == 2) {  // plane stress: eps_zz depends on the in-plane strains
+      G[0][0] += mp.ezz_fac * G[2][2];
+      G[1][1] += mp.ezz_fac * G[2][2];
+    }
+  }
+  // micro-equivalent strain and its gradient at the Gauss point
+  double ebar = 0.0, gb[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) gb[d] = 0.0;
+#pragma unroll
+  for (int a = 0; a < E::NEN; ++a) {
+    ebar += N[a] * eb[a];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) gb[d] += eb[a] * dNx[a][d];
+  }
+  // history (A.2, condition vector cond1 of Fig. 8b)
+  const double kn = kappa_n[gid];
+  const bool chi = (ebar - kn) > mp.tol_hist;
+  const double kap = chi ? ebar : kn;
+  // damage (A.1, condition vector cond2 of Fig. 8b)
+  double D = 0.0, dD = 0.0;
+  if (!((kap - mp.kappa0) < mp.tol_dmg)) {
+    const double ex = exp(-mp.beta * (kap - mp.kappa0));
+    const double br = 1.0 - mp.alpha + mp.alpha * ex;
+    const double q = mp.kappa0 / kap;
+    D = 1.0 - q * br;
+    dD = q / kap * br + q * mp.alpha * mp.beta * ex;
+  }
+  // interaction function (A.4)
+  const double en = exp(-mp.eta * D);
+  const double gv = ((1.0 - mp.R) * en + mp.R - exp(-mp.eta)) / mp.g_den;
+  const double dg = -mp.eta * (1.0 - mp.R) * en / mp.g_den;
+
+  // unscaled stress S = C : eps
+  double S[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  if (DIM == 1) {
+    S[0][0] = mp.E * eps[0][0];
+  } else {
+    double tr = 0.0;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) tr += eps[i][i];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) S[i][j] = 2.0 * mp.mu * eps[i][j] + (i == j ? mp.lam * tr : 0.0);
+  }
+  const double wJ = detJ * mp.thick;  // Gauss weights are 1
+  const double se = e_scale[e];
+  const double chid = chi ? 1.0 : 0.0;
+
+  double* r = rec + gid * RC::STRIDE;
+#pragma unroll
+  for (int j = 0; j < DIM; ++j)
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) r[RC::JINV + j * DIM + d] = Ji[j][d];
+  r[RC::CUU] = wJ * (1.0 - D) * se;
+  r[RC::CUE] = wJ * dD * chid * se;
+#pragma unroll
+  for (int i = 0; i < DIM; ++i)
+#pragma unroll
+    for (int j = i; j < DIM; ++j) {
+      r[RC::S + sym_idx<DIM>(i, j)] = S[i][j];
+      r[RC::GH + sym_idx<DIM>(i, j)] = wJ * mp.h * G[i][j];
+    }
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) r[RC::GB + d] = gb[d];
+  r[RC::CEE] = wJ * mp.h;
+  r[RC::CGP] = wJ * mp.h * mp.c * dg * dD * chid;
+  r[RC::CG] = wJ * gv * mp.h * mp.c;
+  r[RC::RE] = wJ * mp.h * (ebar - eeq);
+  r[RC::FR] = wJ * mp.h * eeq;
+#pragma unroll
+  for (int f = RC::USED; f < RC::STRIDE; ++f) r[f] = 0.0;
+  kappa_t[gid] = kap;
+  D_t[gid] = D;
+}
+
+// ---------------------------------------------------------------------------
+// shared block / force evaluation for one (element, a, b) at one Gauss point
+// ---------------------------------------------------------------------------
+template <int DIM, typename T>
+__device__ __forceinline__ void block_and_force(const double* __restrict__ r, int g, int la, int lb,
+                                                const MatParams& mp, bool want_k, bool want_f,
+                                                T blk[DIM + 1][DIM + 1], double fa[DIM + 2]) {
+  using RC = Rec<DIM>;
+  double Na, Nb, dNa[DIM], dNb[DIM];
+  shape_at<DIM>(la, g, Na, dNa);
+  shape_at<DIM>(lb, g, Nb, dNb);
+  double Ji[DIM][DIM];
+#pragma unroll
+  for (int j = 0; j < DIM; ++j)
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) Ji[j][d] = r[RC::JINV + j * DIM + d];
+  double ga[DIM], gbv[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    double sa = 0.0, sb = 0.0;
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) {
+      sa += dNa[j] * Ji[j][d];
+      sb += dNb[j] * Ji[j][d];
+    }
+    ga[d] = sa;
+    gbv[d] = sb;
+  }
+  double S[DIM][DIM], Gh[DIM][DIM], grad_eb[DIM];
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) {
+    grad_eb[i] = r[RC::GB + i];
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) {
+      S[i][j] = r[RC::S + sym_idx<DIM>(i, j)];
+      Gh[i][j] = r[RC::GH + sym_idx<DIM>(i, j)];
+    }
+  }
+  const double cuu = r[RC::CUU];
+  double Sga[DIM];
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) s += S[i][j] * ga[j];
+    Sga[i] = s;
+  }
+  double ga_geb = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) ga_geb += ga[d] * grad_eb[d];
+  if (want_f) {
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) fa[i] += cuu * Sga[i];
+    fa[DIM] += r[RC::RE] * Na + r[RC::CG] * ga_geb;
+    fa[DIM + 1] += r[RC::FR] * Na;
+  }
+  if (!want_k) return;
+  // tangent block in the working precision T
+  const T tcuu = (T)cuu;
+  T tga[DIM], tgb[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    tga[d] = (T)ga[d];
+    tgb[d] = (T)gbv[d];
+  }
+  T dab = 0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) dab += tga[d] * tgb[d];
+  if (DIM == 1) {
+    blk[0][0] += tcuu * (T)mp.E * tga[0] * tgb[0];
+  } else {
+    const T lam = (T)mp.lam, mu = (T)mp.mu;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+      for (int j = 0; j < DIM; ++j)
+        blk[i][j] += tcuu * (lam * tga[i] * tgb[j] + mu * tga[j] * tgb[i] + (i == j ? mu * dab : (T)0));
+  }
+  const T cue = (T)r[RC::CUE];
+  const T tNa = (T)Na, tNb = (T)Nb;
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) blk[i][DIM] -= cue * (T)Sga[i] * tNb;
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) {
+    T s = 0;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) s += (T)Gh[j][i] * tgb[i];
+    blk[DIM][j] -= tNa * s;
+  }
+  blk[DIM][DIM] += (T)r[RC::CEE] * tNa * tNb + (T)r[RC::CGP] * (T)ga_geb * tNb + (T)r[RC::CG] * dab;
+}
+
+// ---------------------------------------------------------------------------
+// Kernel 2: node-row assembly
+// ---------------------------------------------------------------------------
+constexpr int NODE_BLOCK = 256;
+
+template <int DIM, typename T, bool WANT_K>
+__global__ void __launch_bounds__(NODE_BLOCK) node_kernel(
+    int64_t n_nodes, const int32_t* __restrict__ n2e_ptr, const int32_t* __restrict__ n2e,
+    const int32_t* __restrict__ nbr_ptr, const int32_t* __restrict__ nbr,
+    const uint8_t* __restrict__ pos, const int32_t* __restrict__ row_ptr,
+    const uint8_t* __restrict__ flags, const double* __restrict__ rec, MatParams mp,
+    T* __restrict__ vals, double* __restrict__ R, double* __restrict__ partials) {
+  using E = Elem<DIM>;
+  using RC = Rec<DIM>;
+  constexpr int NEN = E::NEN, ND = E::ND, NB = ND * ND;
+  constexpr int L = NEN * NEN;                 // lanes per node: (element slot k, local node b)
+  constexpr int NPB = NODE_BLOCK / L;          // nodes per workgroup
+  constexpr int RS = RC::STRIDE;
+  constexpr int RSP = RS + 1;                  // odd stride: the NEN records of a node sit in distinct LDS banks
+  constexpr int FPL = RS / NEN;                // record doubles each lane stages
+  static_assert(RS % NEN == 0, "record staging split");
+  __shared__ double s_rec[NPB][NEN][RSP];      // one Gauss point of the node's elements
+  __shared__ T s_blk[NB][NODE_BLOCK];          // [value][lane]
+  __shared__ int s_pos[NODE_BLOCK];
+  __shared__ double s_f[DIM + 2][NODE_BLOCK];
+  __shared__ double s_red[NORM_SLOTS][NPB];
+  __shared__ int s_chunks;
+
+  const int tid = threadIdx.x;
+  const int slot = tid / L;                    // node within the workgroup
+  const int l = tid % L;
+  const int k = l / NEN, b = l % NEN;
+  const int64_t a = (int64_t)blockIdx.x * NPB + slot;
+  const bool valid = a < n_nodes;
+  int e0 = 0, ne = 0, nnb = 0, nb0 = 0;
+  if (valid) {
+    e0 = n2e_ptr[a];
+    ne = n2e_ptr[a + 1] - e0;
+    nb0 = nbr_ptr[a];
+    nnb = nbr_ptr[a + 1] - nb0;
+  }
+  if (tid == 0) s_chunks = 0;
+  __syncthreads();
+  if (valid && l == 0) atomicMax(&s_chunks, (ne + NEN - 1) / NEN);
+  __syncthreads();
+  const int chunks = s_chunks;
+
+  T acc[ND][ND];
+#pragma unroll
+  for (int i = 0; i < ND; ++i)
+#pragma unroll
+    for (int j = 0; j < ND; ++j) acc[i][j] = (T)0;
+  double facc[DIM + 2];
+#pragma unroll
+  for (int i = 0; i < DIM + 2; ++i) facc[i] = 0.0;
+
+  for (int ch = 0; ch < chunks; ++ch) {
+    const int kk = ch * NEN + k;
+    const bool act = valid && kk < ne;
+    T blk[ND][ND];
+#pragma unroll
+    for (int i = 0; i < ND; ++i)
+#pragma unroll
+      for (int j = 0; j < ND; ++j) blk[i][j] = (T)0;
+    double f[DIM + 2];
+#pragma unroll
+    for (int i = 0; i < DIM + 2; ++i) f[i] = 0.0;
+    int p = -1, la = 0;
+    int64_t e = 0;
+    if (act) {
+      const int ent = n2e[e0 + kk];
+      e = ent >> 3;
+      la = ent & 7;
+      p = pos[(e * NEN + la) * NEN + b];
+    }
+    const bool wf = (b == 0);
+#pragma unroll 1
+    for (int g = 0; g < E::NGP; ++g) {
+      // stage record g of the node's elements: lane (k, b) copies doubles
+      // [b*FPL, (b+1)*FPL) of element k's record (coalesced per element)
+      if (act) {
+        const double* src = rec + (e * E::NGP + g) * RS + b * FPL;
+#pragma unroll
+        for (int q = 0; q < FPL; ++q) s_rec[slot][k][b * FPL + q] = src[q];
+      }
+      __syncthreads();
+      if (act) block_and_force<DIM, T>(&s_rec[slot][k][0], g, la, b, mp, WANT_K, wf, blk, f);
+      __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < ND; ++i)
+#pragma unroll
+      for (int j = 0; j < ND; ++j) s_blk[i * ND + j][tid] = blk[i][j];
+    s_pos[tid] = p;
+#pragma unroll
+    for (int i = 0; i < DIM + 2; ++i) s_f[i][tid] = f[i];
+    __syncthreads();
+    // lane l owns neighbour position l; sum contributions in element order
+    if (valid && l < nnb) {
+      const int base = slot * L;
+      for (int kq = 0; kq < NEN; ++kq) {
+#pragma unroll
+        for (int bq = 0; bq < NEN; ++bq) {
+          const int src = base + kq * NEN + bq;
+          if (s_pos[src] == l) {
+#pragma unroll
+            for (int i = 0; i < ND; ++i)
+#pragma unroll
+              for (int j = 0; j < ND; ++j) acc[i][j] += s_blk[i * ND + j][src];
+          }
+        }
+      }
+    }
+    if (valid && l == 0) {
+      const int base = slot * L;
+      for (int kq = 0; kq < NEN; ++kq) {
+#pragma unroll
+        for (int i = 0; i < DIM + 2; ++i) facc[i] += s_f[i][base + kq * NEN];
+      }
+    }
+    __syncthreads();
+  }
+
+  // write the CSR row block of node a: rows a*ND + r, positions p, columns c
+  if (WANT_K && valid && l < nnb) {
+    const int64_t nbn = nbr[nb0 + l];
+    const int64_t rb = row_ptr[a * ND];
+    const int64_t rowlen = (int64_t)nnb * ND;
+#pragma unroll
+    for (int r = 0; r < ND; ++r) {
+      const int64_t row = a * ND + r;
+      const bool rd = flags[row] & 1;
+#pragma unroll
+      for (int c = 0; c < ND; ++c) {
+        const int64_t col = nbn * ND + c;
+        T v = acc[r][c];
+        if (rd)
+          v = (col == row) ? (T)1 : (T)0;
+        else if (flags[col] & 1)
+          v = (T)0;
+        vals[rb + r * rowlen + (int64_t)l * ND + c] = v;
+      }
+    }
+  }
+  // residual R = -f_int (0 on Dirichlet rows) and norm partials
+  double red[NORM_SLOTS] = {0, 0, 0, 0, 0, 0};
+  if (valid && l == 0) {
+#pragma unroll
+    for (int r = 0; r < ND; ++r) {
+      const int64_t row = a * ND + r;
+      const uint8_t fl = flags[row];
+      const double fv = facc[r];
+      const double rv = (fl & 1) ? 0.0 : -fv;
+      R[row] = rv;
+      if (r < DIM) {
+        red[0] += rv * rv;
+        red[2] += fv * fv;
+        if (fl & 2) red[4] += fv;
+      } else {
+        red[1] += rv * rv;
+      }
+      if (!isfinite(fv)) red[5] += 1.0;
+    }
+    red[3] += facc[DIM + 1] * facc[DIM + 1];
+  }
+  if (l == 0) {
+#pragma unroll
+    for (int q = 0; q < NORM_SLOTS; ++q) s_red[q][slot] = red[q];
+  }
+  __syncthreads();
+  if (tid < NORM_SLOTS) {
+    double s = 0.0;
+    for (int i = 0; i < NPB; ++i) s += s_red[tid][i];
+    partials[(int64_t)blockIdx.x * NORM_SLOTS + tid] = s;
+  }
+}
+
+// fixed-order sum of the per-workgroup partials
+__global__ void __launch_bounds__(256) norm_reduce_kernel(int64_t nblk,
+                                                          const double* __restrict__ partials,
+                                                          double* __restrict__ out) {
+  __shared__ double s[NORM_SLOTS][256];
+  const int t = threadIdx.x;
+  double acc[NORM_SLOTS] = {0, 0, 0, 0, 0, 0};
+  for (int64_t i = t; i < nblk; i += 256)
+#pragma unroll
+    for (int q = 0; q < NORM_SLOTS; ++q) acc[q] += partials[i * NORM_SLOTS + q];
+#pragma unroll
+  for (int q = 0; q < NORM_SLOTS; ++q) s[q][t] = acc[q];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w)
+#pragma unroll
+      for (int q = 0; q < NORM_SLOTS; ++q) s[q][t] += s[q][t + w];
+    __syncthreads();
+  }
+  if (t < NORM_SLOTS) out[t] = s[t][0];
+}
+
+__global__ void set_dirichlet_kernel(int64_t n, const int32_t* __restrict__ dofs,
+                                     const double* __restrict__ vals, double lambda,
+                                     double* __restrict__ x) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[dofs[i]] = lambda * vals[i];
+}
+
+__global__ void damage_kernel(int64_t n, const double* __restrict__ kappa, MatParams mp,
+                              double* __restrict__ D) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double kap = kappa[i];
+  double d = 0.0;
+  if (!((kap - mp.kappa0) < mp.tol_dmg)) {
+    const double ex = exp(-mp.beta * (kap - mp.kappa0));
+    d = 1.0 - mp.kappa0 / kap * (1.0 - mp.alpha + mp.alpha * ex);
+  }
+  D[i] = d;
+}
+
+// element blocks for parity checks: one thread per (element, a, b)
+template <int DIM>
+__global__ void element_blocks_kernel(int64_t e0, int64_t e1, const double* __restrict__ rec,
+                                      MatParams mp, double* __restrict__ Ke,
+                                      double* __restrict__ fe) {
+  using E = Elem<DIM>;
+  using RC = Rec<DIM>;
+  constexpr int NEN = E::NEN, ND = E::ND, NL = NEN * ND;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ne = e1 - e0;
+  if (t >= ne * NEN * NEN) return;
+  const int64_t el = t / (NEN * NEN);
+  const int la = (int)((t / NEN) % NEN), lb = (int)(t % NEN);
+  const int64_t e = e0 + el;
+  double blk[ND][ND];
+#pragma unroll
+  for (int i = 0; i < ND; ++i)
+#pragma unroll
+    for (int j = 0; j < ND; ++j) blk[i][j] = 0.0;
+  double f[DIM + 2];
+#pragma unroll
+  for (int i = 0; i < DIM + 2; ++i) f[i] = 0.0;
+  for (int g = 0; g < E::NGP; ++g)
+    block_and_force<DIM, double>(rec + (e * E::NGP + g) * RC::STRIDE, g, la, lb, mp, Ke != nullptr,
+                                 lb == 0, blk, f);
+  if (Ke) {
+    double* out = Ke + el * NL * NL;
+#pragma unroll
+    for (int i = 0; i < ND; ++i)
+#pragma unroll
+      for (int j = 0; j < ND; ++j) out[(la * ND + i) * NL + lb * ND + j] = blk[i][j];
+  }
+  if (fe && lb == 0) {
+#pragma unroll
+    for (int i = 0; i < ND; ++i) fe[el * NL + la * ND + i] = f[i];
+  }
+}
+
+__global__ void __launch_bounds__(256) max_reduce_kernel(int64_t n, const double* __restrict__ v,
+                                                         double* __restrict__ out) {
+  __shared__ double s[256];
+  double m = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) m = fmax(m, v[i]);
+  s[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = s[0];
+}
+
+template <int DIM> int node_lanes() { return Elem<DIM>::NEN * Elem<DIM>::NEN; }
+
+}  // namespace
+
+MatParams make_params(const lgdm_material& m, int dim) {
+  MatParams p{};
+  const double lam = m.E * m.nu / ((1.0 + m.nu) * (1.0 - 2.0 * m.nu));
+  const double mu = m.E / (2.0 * (1.0 + m.nu));
+  p.mu = mu;
+  p.lam = lam;
+  p.ezz_fac = 0.0;
+  if (dim == 2 && m.plane == LGDM_PLANE_STRESS) {
+    p.lam = 2.0 * lam * mu / (lam + 2.0 * mu);
+    p.ezz_fac = -m.nu / (1.0 - m.nu);
+  }
+  p.E = m.E;
+  p.nu = m.nu;
+  p.kappa0 = m.kappa0;
+  p.alpha = m.alpha;
+  p.beta = m.beta;
+  p.c = m.c;
+  p.R = m.R;
+  p.eta = m.eta;
+  p.h = m.h;
+  p.tol_hist = m.tol_hist;
+  p.tol_dmg = m.tol_dmg;
+  p.k = m.k;
+  p.c1 = (m.k - 1.0) / (2.0 * m.k * (1.0 - 2.0 * m.nu));
+  p.c2 = (m.k - 1.0) / (1.0 - 2.0 * m.nu);
+  p.c3 = 12.0 * m.k / ((1.0 + m.nu) * (1.0 + m.nu));
+  p.thick = dim < 3 ? m.thickness : 1.0;
+  p.g_den = 1.0 - std::exp(-m.eta);
+  return p;
+}
+
+int64_t node_kernel_blocks(const lgdm_ctx* c) {
+  const int L = c->dim == 1 ? node_lanes<1>() : (c->dim == 2 ? node_lanes<2>() : node_lanes<3>());
+  const int npb = NODE_BLOCK / L;
+  return (c->n_nodes + npb - 1) / npb;
+}
+
+hipError_t launch_gp_kernel(lgdm_ctx* c, const MatParams& mp) {
+  const int bs = 256;
+  const int64_t grid = (c->ngauss + bs - 1) / bs;
+  if (grid == 0) return hipSuccess;
+  switch (c->dim) {
+    case 1:
+      gp_kernel<1><<<grid, bs, 0, c->stream>>>(c->ngauss, c->coords, c->conn, c->e_scale, c->x,
+                                               c->kappa_n, mp, c->rec, c->kappa_t, c->D_t);
+      break;
+    case 2:
+      gp_kernel<2><<<grid, bs, 0, c->stream>>>(c->ngauss, c->coords, c->conn, c->e_scale, c->x,
+                                               c->kappa_n, mp, c->rec, c->kappa_t, c->D_t);
+      break;
+    default:
+      gp_kernel<3><<<grid, bs, 0, c->stream>>>(c->ngauss, c->coords, c->conn, c->e_scale, c->x,
+                                               c->kappa_n, mp, c->rec, c->kappa_t, c->D_t);
+  }
+  return hipGetLastError();
+}
+
+template <int DIM, typename T>
+static void node_launch(lgdm_ctx* c, const MatParams& mp, bool want_k, T* vals) {
+  const int64_t grid = node_kernel_blocks(c);
+  if (grid == 0) return;
+  if (want_k)
+    node_kernel<DIM, T, true><<<grid, NODE_BLOCK, 0, c->stream>>>(
+        c->n_nodes, c->n2e_ptr, c->n2e, c->nbr_ptr, c->nbr, c->pos, c->row_ptr, c->dof_flags,
+        c->rec, mp, vals, c->R, c->partials);
+  else
+    node_kernel<DIM, T, false><<<grid, NODE_BLOCK, 0, c->stream>>>(
+        c->n_nodes, c->n2e_ptr, c->n2e, c->nbr_ptr, c->nbr, c->pos, c->row_ptr, c->dof_flags,
+        c->rec, mp, vals, c->R, c->partials);
+}
+
+hipError_t launch_node_kernel(lgdm_ctx* c, const MatParams& mp, bool want_k) {
+  const bool mixed = c->precision == LGDM_MIXED;
+  switch (c->dim) {
+    case 1:
+      if (mixed) node_launch<1, float>(c, mp, want_k, c->vals32);
+      else node_launch<1, double>(c, mp, want_k, c->vals);
+      break;
+    case 2:
+      if (mixed) node_launch<2, float>(c, mp, want_k, c->vals32);
+      else node_launch<2, double>(c, mp, want_k, c->vals);
+      break;
+    default:
+      if (mixed) node_launch<3, float>(c, mp, want_k, c->vals32);
+      else node_launch<3, double>(c, mp, want_k, c->vals);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_norm_reduce(lgdm_ctx* c) {
+  norm_reduce_kernel<<<1, 256, 0, c->stream>>>(node_kernel_blocks(c), c->partials, c->norms_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_dirichlet(lgdm_ctx* c, double lambda) {
+  if (c->nbc == 0) return hipSuccess;
+  const int64_t grid = (c->nbc + 255) / 256;
+  set_dirichlet_kernel<<<grid, 256, 0, c->stream>>>(c->nbc, c->bc_dofs, c->bc_vals, lambda, c->x);
+  return hipGetLastError();
+}
+
+hipError_t launch_damage_from_kappa(lgdm_ctx* c, const MatParams& mp) {
+  const int64_t grid = (c->ngauss + 255) / 256;
+  if (grid == 0) return hipSuccess;
+  damage_kernel<<<grid, 256, 0, c->stream>>>(c->ngauss, c->kappa_n, mp, c->D_n);
+  return hipGetLastError();
+}
+
+hipError_t launch_element_blocks(lgdm_ctx* c, const MatParams& mp, int64_t e0, int64_t e1,
+                                 double* Ke, double* fe) {
+  const int64_t n = (e1 - e0) * c->nen * c->nen;
+  const int64_t grid = (n + 255) / 256;
+  if (grid == 0) return hipSuccess;
+  switch (c->dim) {
+    case 1: element_blocks_kernel<1><<<grid, 256, 0, c->stream>>>(e0, e1, c->rec, mp, Ke, fe); break;
+    case 2: element_blocks_kernel<2><<<grid, 256, 0, c->stream>>>(e0, e1, c->rec, mp, Ke, fe); break;
+    default: element_blocks_kernel<3><<<grid, 256, 0, c->stream>>>(e0, e1, c->rec, mp, Ke, fe);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_max_reduce(lgdm_ctx* c, const double* v, int64_t n, double* out_dev) {
+  max_reduce_kernel<<<1, 256, 0, c->stream>>>(n, v, out_dev);
+  return hipGetLastError();
+}
+
+}  // namespace lgdm

@@ -1,0 +1,161 @@
+// Internal declarations of the LGDM HIP library: the context, device-side
+// parameter structs and the launch wrappers each translation unit exports.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "lgdm.h"
+
+namespace lgdm {
+
+// Material constants as the kernels need them (Eq. 1, Appendix A).
+struct MatParams {
+  double lam, mu;        // Lame constants of the element law (plane stress: lambda*)
+  double E;              // 1D modulus
+  double nu, kappa0, alpha, beta, c, R, eta, h, tol_hist, tol_dmg;
+  double c1, c2, c3, k;  // modified von Mises coefficients (A.3)
+  double ezz_fac;        // plane stress: eps_zz = ezz_fac (eps_xx + eps_yy); else 0
+  double thick;          // thickness (2D) / area (1D); 1 in 3D
+  double g_den;          // 1 - exp(-eta)
+};
+
+// Record layout of one Gauss point written by the Gauss-point kernel and
+// read by the node-row assembly kernel.  Tensor components are stored as
+// symmetric tensor entries (not engineering shears): 2D (xx, yy, xy),
+// 3D (xx, yy, zz, xy, yz, xz).
+template <int DIM> struct Rec {
+  static constexpr int NS = DIM == 1 ? 1 : (DIM == 2 ? 3 : 6);
+  static constexpr int JINV = 0;                 // J^-1 [DIM*DIM], (J^-1)_{j d}
+  static constexpr int CUU = DIM * DIM;          // wJ (1 - D) s_e
+  static constexpr int CUE = CUU + 1;            // wJ D' chi s_e
+  static constexpr int S = CUE + 1;              // C : eps (unscaled stress) [NS]
+  static constexpr int GH = S + NS;              // wJ h d eeq / d eps [NS]
+  static constexpr int GB = GH + NS;             // grad ebar [DIM]
+  static constexpr int CEE = GB + DIM;           // wJ h
+  static constexpr int CGP = CEE + 1;            // wJ h c g' D' chi
+  static constexpr int CG = CGP + 1;             // wJ g h c
+  static constexpr int RE = CG + 1;              // wJ h (ebar - eeq)
+  static constexpr int FR = RE + 1;              // wJ h eeq
+  static constexpr int USED = FR + 1;
+  static constexpr int STRIDE = DIM == 1 ? 12 : (DIM == 2 ? 20 : 32);
+  static_assert(USED <= STRIDE, "record stride");
+};
+
+constexpr int NORM_SLOTS = 6;  // |R_u|^2, |R_e|^2, |f_u|^2, |fref_e|^2, reaction, non-finite count
+
+}  // namespace lgdm
+
+struct lgdm_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int precision = LGDM_FP64;
+  void* (*alloc_fn)(size_t, void*) = nullptr;
+  void (*free_fn)(void*, void*) = nullptr;
+  void* alloc_user = nullptr;
+  std::string err;
+  std::vector<std::pair<void*, size_t>> allocs;  // every live device allocation
+
+  // mesh and pattern (H0)
+  int dim = 0, nen = 0, ngp = 0, nd = 0;
+  int64_t n_nodes = 0, n_elems = 0, ndof = 0, ngauss = 0, nnz = 0, npairs = 0;
+  int max_elem_per_node = 0, max_nbr = 0;
+  double* coords = nullptr;
+  int32_t* conn = nullptr;
+  double* e_scale = nullptr;
+  int32_t* n2e_ptr = nullptr;   // node -> element list offsets [n_nodes + 1]
+  int32_t* n2e = nullptr;       // (element << 3) | local node, ascending element
+  int32_t* nbr_ptr = nullptr;   // node graph offsets [n_nodes + 1]
+  int32_t* nbr = nullptr;       // neighbour node ids, ascending [npairs]
+  int32_t* dpos = nullptr;      // position of the node itself in its neighbour list
+  uint8_t* pos = nullptr;       // [n_elems * nen * nen] position of node b in node a's list
+  int32_t* row_ptr = nullptr;
+  int32_t* col_idx = nullptr;
+
+  // boundary conditions
+  uint8_t* dof_flags = nullptr;  // bit0 Dirichlet, bit1 loaded (nonzero reference value)
+  int32_t* bc_dofs = nullptr;
+  double* bc_vals = nullptr;
+  int64_t nbc = 0;
+
+  // material
+  lgdm_material mat{};
+  bool has_mat = false;
+
+  // state (H2, H7)
+  double* x = nullptr;
+  double* x_save = nullptr;
+  double* kappa_n = nullptr;
+  double* D_n = nullptr;
+  double* kappa_t = nullptr;
+  double* D_t = nullptr;
+  int64_t increment = 0;
+  bool in_increment = false;
+  bool assembled = false;
+
+  // assembly outputs (H3-H5)
+  double* rec = nullptr;
+  double* vals = nullptr;
+  float* vals32 = nullptr;
+  double* R = nullptr;
+  double* partials = nullptr;
+  int64_t n_partials = 0;
+  double* norms_dev = nullptr;     // NORM_SLOTS
+  double* norms_host = nullptr;    // pinned
+  double last_norms[lgdm::NORM_SLOTS] = {0, 0, 0, 0, 0, 0};
+
+  // Krylov workspace (H6)
+  double* kv = nullptr;            // 8 FP64 vectors of ndof
+  float* kv32 = nullptr;           // FP32 vectors for the mixed inner solve
+  double* minv = nullptr;          // block-Jacobi inverses [n_nodes * nd * nd]
+  float* minv32 = nullptr;
+  double* kpart = nullptr;         // per-block partial sums
+  int64_t n_kpart = 0;
+  double* kscal = nullptr;         // device scalars
+  double* kscal_host = nullptr;    // pinned copy
+  unsigned int* kcount = nullptr;  // last-block counters
+  double* delta = nullptr;
+
+  hipEvent_t ev[8] = {};
+  bool events_ready = false;
+};
+
+namespace lgdm {
+
+// allocation helpers (capi.cpp)
+void* dalloc(lgdm_ctx* c, size_t bytes);
+void dfree(lgdm_ctx* c, void* p);
+
+// H0 (pattern.hip)
+hipError_t build_pattern(lgdm_ctx* c, std::string& msg, int& status);
+
+// H1-H5 (element.hip)
+MatParams make_params(const lgdm_material& m, int dim);
+hipError_t launch_gp_kernel(lgdm_ctx* c, const MatParams& mp);
+hipError_t launch_node_kernel(lgdm_ctx* c, const MatParams& mp, bool want_k);
+hipError_t launch_norm_reduce(lgdm_ctx* c);
+hipError_t launch_set_dirichlet(lgdm_ctx* c, double lambda);
+hipError_t launch_damage_from_kappa(lgdm_ctx* c, const MatParams& mp);
+hipError_t launch_element_blocks(lgdm_ctx* c, const MatParams& mp, int64_t e0, int64_t e1,
+                                 double* Ke, double* fe);
+hipError_t launch_max_reduce(lgdm_ctx* c, const double* v, int64_t n, double* out_dev);
+int64_t node_kernel_blocks(const lgdm_ctx* c);
+
+// H6 (krylov.hip)
+struct KrylovResult {
+  int status;          // LGDM_OK / LGDM_ERR_NAN / LGDM_ERR_BREAKDOWN / LGDM_ERR_NOT_CONVERGED
+  int64_t iters;
+  int restarts;
+  double rel_u, rel_e;
+};
+hipError_t krylov_setup(lgdm_ctx* c);  // block-Jacobi from the assembled matrix
+hipError_t krylov_solve(lgdm_ctx* c, const double* b, double* xout, const lgdm_solver_opts& o,
+                        KrylovResult& res);
+hipError_t launch_spmv_only(lgdm_ctx* c, const double* x, double* scratch);  // y = S K x
+hipError_t launch_axpy(lgdm_ctx* c, double* y, const double* x, double a, int64_t n);
+hipError_t launch_field_norms(lgdm_ctx* c, const double* v, double* out_dev);  // |v_u|^2, |v_e|^2
+
+}  // namespace lgdm

@@ -344,17 +344,17 @@ def eval_elements(dim, coords, conn, e_scale, mat, x, kappa_n, elems=None, want_
         if not want_K:
             continue
         # Eq. 11a
-        Kuu += np.einsum("esc,est,etd->ecd", B, ((1.0 - D) * wJ)[:, None, None] * Cs, B)
+        Kuu += np.einsum("esc,est,etd->ecd", B, ((1.0 - D) * wJ)[:, None, None] * Cs, B, optimize=True)
         # Eq. 11b (R1): -B^T (C eps dD/dkappa dkappa/debar) N
         v = Ceps * (dD * chi * wJ)[:, None]
-        Kue -= np.einsum("esc,es,a->eca", B, v, N)
+        Kue -= np.einsum("esc,es,a->eca", B, v, N, optimize=True)
         # Eq. 11c: -N h n^T B
-        Keu -= np.einsum("a,es,esc->eac", N, (h * wJ)[:, None] * n, B)
+        Keu -= np.einsum("a,es,esc->eac", N, (h * wJ)[:, None] * n, B, optimize=True)
         # Eq. 11d (R3): h N N^T + h c g' D' chi (B_e grad ebar) N^T + g h c B_e^T B_e
         Kee += (h * wJ)[:, None, None] * np.outer(N, N)[None]
         Kee += np.einsum("e,ea,b->eab", h * c * dg * dD * chi * wJ,
-                         np.einsum("ead,ed->ea", dNdx, gradb), N)
-        Kee += np.einsum("e,ead,ebd->eab", gv * h * c * wJ, dNdx, dNdx)
+                         np.einsum("ead,ed->ea", dNdx, gradb), N, optimize=True)
+        Kee += np.einsum("e,ead,ebd->eab", gv * h * c * wJ, dNdx, dNdx, optimize=True)
 
     res = {"kappa": out_k, "D": out_D, "eeq": out_eeq, "ebar": out_eb, "fref": fr}
     nl = nen * nd

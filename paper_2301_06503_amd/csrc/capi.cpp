@@ -73,7 +73,7 @@ void free_mesh(lgdm_ctx* c) {
   c->x = c->x_save = c->kappa_n = c->D_n = c->kappa_t = c->D_t = nullptr;
   c->rec = c->vals = c->R = c->partials = c->norms_dev = nullptr;
   c->vals32 = nullptr;
-  c->kv = nullptr; c->kv32 = nullptr; c->minv = nullptr; c->minv32 = nullptr;
+  c->kv = nullptr; c->minv = nullptr; c->minv32 = nullptr;
   c->kpart = nullptr; c->kscal = nullptr; c->kcount = nullptr; c->delta = nullptr;
   c->dim = 0;
   c->assembled = false;
@@ -285,20 +285,16 @@ lgdm_status lgdm_upload_mesh(lgdm_ctx* c, int32_t dim, int32_t elem_type, int64_
   c->partials = (double*)dalloc(c, c->n_partials * NORM_SLOTS * sizeof(double));
   c->norms_dev = (double*)dalloc(c, 16 * sizeof(double));
   c->dof_flags = (uint8_t*)dalloc(c, nd);
-  if (mixed) {
-    c->kv32 = (float*)dalloc(c, 8 * nd * sizeof(float));
-    c->minv32 = (float*)dalloc(c, n_nodes * c->nd * c->nd * sizeof(float));
-  } else {
-    c->kv = (double*)dalloc(c, 8 * nd * sizeof(double));
-    c->minv = (double*)dalloc(c, n_nodes * c->nd * c->nd * sizeof(double));
-  }
+  c->kv = (double*)dalloc(c, 9 * nd * sizeof(double));  // 8 Krylov vectors + best iterate
+  if (mixed) c->minv32 = (float*)dalloc(c, n_nodes * c->nd * c->nd * sizeof(float));
+  else c->minv = (double*)dalloc(c, n_nodes * c->nd * c->nd * sizeof(double));
   c->n_kpart = 2048 * 8;
   c->kpart = (double*)dalloc(c, c->n_kpart * sizeof(double));
   c->kscal = (double*)dalloc(c, 64 * sizeof(double));
   c->kcount = (unsigned*)dalloc(c, 16 * sizeof(unsigned));
   if (!c->x || !c->x_save || !c->R || !c->delta || !c->kappa_n || !c->D_n || !c->kappa_t || !c->D_t ||
       !c->rec || (!c->vals && !c->vals32) || !c->partials || !c->norms_dev || !c->dof_flags ||
-      (!c->kv && !c->kv32) || (!c->minv && !c->minv32) || !c->kpart || !c->kscal || !c->kcount) {
+      !c->kv || (!c->minv && !c->minv32) || !c->kpart || !c->kscal || !c->kcount) {
     free_mesh(c);
     return fail(c, LGDM_ERR_OOM, "device allocation failed (state / matrix / solver)");
   }

@@ -40,32 +40,29 @@ template <int DIM> struct Elem {
   static constexpr int ND = DIM + 1;
 };
 
-// reference node coordinate xi_a,d of the local node order: line2 (x0, x1);
-// quad4 counter-clockwise; hex8 bottom face then top face
-__device__ __forceinline__ double xi_node(int a, int d) {
-  if (d == 0) return ((a & 3) == 1 || (a & 3) == 2) ? 1.0 : -1.0;
-  if (d == 1) return ((a & 3) >= 2) ? 1.0 : -1.0;
-  return (a >= 4) ? 1.0 : -1.0;
+// sign bits of the reference node (bit d set where xi_a,d = +1); the Gauss
+// point index g = i_xi + 2 i_eta + 4 i_zeta has bit d set where xi_g,d = +1/sqrt(3)
+template <int DIM> __device__ __forceinline__ int node_bits(int a) {
+  if (DIM == 1) return a;
+  const int x = (a & 1) ^ ((a >> 1) & 1), y = (a >> 1) & 1;
+  return DIM == 2 ? (x | (y << 1)) : (x | (y << 1) | (a & 4));
 }
 
-// Gauss point coordinate: g = i_xi + 2 i_eta + 4 i_zeta, +-1/sqrt(3)
-__device__ __forceinline__ double xi_gp(int g, int d) {
-  const double s = 0.57735026918962576451;  // 1/sqrt(3)
-  return ((g >> d) & 1) ? s : -s;
-}
-
-// N_a and dN_a/dxi_j at Gauss point g (multilinear Lagrange functions)
-template <int DIM>
-__device__ __forceinline__ void shape_at(int a, int g, double& N, double dN[DIM]) {
-  double f[DIM];
+// N_a(xi_g) and dN_a/dxi(xi_g) from the factor (1 + xi_a,d xi_g,d)/2, which
+// takes (1 +- 1/sqrt(3))/2 when the signs agree / differ
+template <int DIM, typename T>
+__device__ __forceinline__ void shape_fast(int a, int g, T& N, T dN[DIM]) {
+  const T cp = (T)0.78867513459481288225, cm = (T)0.21132486540518711775;
+  const int ab = node_bits<DIM>(a);
+  T f[DIM];
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) f[d] = 0.5 * (1.0 + xi_node(a, d) * xi_gp(g, d));
-  N = 1.0;
+  for (int d = 0; d < DIM; ++d) f[d] = (((ab ^ g) >> d) & 1) ? cm : cp;
+  N = (T)1;
 #pragma unroll
   for (int d = 0; d < DIM; ++d) N *= f[d];
 #pragma unroll
   for (int j = 0; j < DIM; ++j) {
-    double p = 0.5 * xi_node(a, j);
+    T p = ((ab >> j) & 1) ? (T)0.5 : (T)-0.5;
 #pragma unroll
     for (int d = 0; d < DIM; ++d)
       if (d != j) p *= f[d];
@@ -120,7 +117,7 @@ __global__ void __launch_bounds__(256) gp_kernel(int64_t ngauss, const double* _
 #pragma unroll
   for (int a = 0; a < E::NEN; ++a) {
     double dN[DIM];
-    shape_at<DIM>(a, g, N[a], dN);
+    shape_fast<DIM, double>(a, g, N[a], dN);
 #pragma unroll
     for (int j = 0; j < DIM; ++j) dNx[a][j] = dN[j];  // reference gradient for now
 #pragma unroll
@@ -301,101 +298,121 @@ __global__ void __launch_bounds__(256) gp_kernel(int64_t ngauss, const double* _
 }
 
 // ---------------------------------------------------------------------------
-// shared block / force evaluation for one (element, a, b) at one Gauss point
+// per-Gauss-point pieces of the node-row assembly
 // ---------------------------------------------------------------------------
+// record fields in registers in precision T (16-byte loads; records are
+// 16-byte aligned)
 template <int DIM, typename T>
-__device__ __forceinline__ void block_and_force(const double* __restrict__ r, int g, int la, int lb,
+__device__ __forceinline__ void load_rec(const double* __restrict__ rv, T (&rr)[(Rec<DIM>::USED + 1) & ~1]) {
+  constexpr int RU = (Rec<DIM>::USED + 1) & ~1;
+#pragma unroll
+  for (int i = 0; i < RU; i += 2) {
+    const double2 t = *reinterpret_cast<const double2*>(rv + i);
+    rr[i] = (T)t.x;
+    rr[i + 1] = (T)t.y;
+  }
+}
+
+// gradient of N_a at Gauss point g from the record's J^-1
+template <int DIM, typename T>
+__device__ __forceinline__ void grad_n(const T* r, const T dNxi[DIM], T out[DIM]) {
+  using RC = Rec<DIM>;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    T s = 0;
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) s += dNxi[j] * r[RC::JINV + j * DIM + d];
+    out[d] = s;
+  }
+}
+
+// tangent block d f_a / d x_b and (want_f) the internal force on node a of
+// one element at Gauss point g: one read of the record serves both;
+// gradients in FP64, block arithmetic in the working precision T
+template <int DIM, typename T>
+__device__ __forceinline__ void block_and_force(const double* __restrict__ rv, int g, int la, int lb,
                                                 const MatParams& mp, bool want_k, bool want_f,
                                                 T blk[DIM + 1][DIM + 1], double fa[DIM + 2]) {
   using RC = Rec<DIM>;
-  double Na, Nb, dNa[DIM], dNb[DIM];
-  shape_at<DIM>(la, g, Na, dNa);
-  shape_at<DIM>(lb, g, Nb, dNb);
-  double Ji[DIM][DIM];
-#pragma unroll
-  for (int j = 0; j < DIM; ++j)
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) Ji[j][d] = r[RC::JINV + j * DIM + d];
-  double ga[DIM], gbv[DIM];
-#pragma unroll
-  for (int d = 0; d < DIM; ++d) {
-    double sa = 0.0, sb = 0.0;
-#pragma unroll
-    for (int j = 0; j < DIM; ++j) {
-      sa += dNa[j] * Ji[j][d];
-      sb += dNb[j] * Ji[j][d];
-    }
-    ga[d] = sa;
-    gbv[d] = sb;
-  }
-  double S[DIM][DIM], Gh[DIM][DIM], grad_eb[DIM];
-#pragma unroll
-  for (int i = 0; i < DIM; ++i) {
-    grad_eb[i] = r[RC::GB + i];
-#pragma unroll
-    for (int j = 0; j < DIM; ++j) {
-      S[i][j] = r[RC::S + sym_idx<DIM>(i, j)];
-      Gh[i][j] = r[RC::GH + sym_idx<DIM>(i, j)];
-    }
-  }
-  const double cuu = r[RC::CUU];
+  double r[(RC::USED + 1) & ~1];
+  load_rec<DIM, double>(rv, r);
+  double Na, Nb, dNa[DIM], dNb[DIM], ga[DIM], gbv[DIM];
+  shape_fast<DIM, double>(la, g, Na, dNa);
+  shape_fast<DIM, double>(lb, g, Nb, dNb);
+  grad_n<DIM, double>(r, dNa, ga);
+  grad_n<DIM, double>(r, dNb, gbv);
   double Sga[DIM];
 #pragma unroll
   for (int i = 0; i < DIM; ++i) {
     double s = 0.0;
 #pragma unroll
-    for (int j = 0; j < DIM; ++j) s += S[i][j] * ga[j];
+    for (int j = 0; j < DIM; ++j) s += r[RC::S + sym_idx<DIM>(i, j)] * ga[j];
     Sga[i] = s;
   }
   double ga_geb = 0.0;
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) ga_geb += ga[d] * grad_eb[d];
+  for (int d = 0; d < DIM; ++d) ga_geb += ga[d] * r[RC::GB + d];
   if (want_f) {
 #pragma unroll
-    for (int i = 0; i < DIM; ++i) fa[i] += cuu * Sga[i];
+    for (int i = 0; i < DIM; ++i) fa[i] += r[RC::CUU] * Sga[i];
     fa[DIM] += r[RC::RE] * Na + r[RC::CG] * ga_geb;
     fa[DIM + 1] += r[RC::FR] * Na;
   }
   if (!want_k) return;
-  // tangent block in the working precision T
-  const T tcuu = (T)cuu;
-  T tga[DIM], tgb[DIM];
+  const T cuu = (T)r[RC::CUU];
+  T ta[DIM], tb[DIM];
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
-    tga[d] = (T)ga[d];
-    tgb[d] = (T)gbv[d];
+    ta[d] = (T)ga[d];
+    tb[d] = (T)gbv[d];
   }
   T dab = 0;
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) dab += tga[d] * tgb[d];
+  for (int d = 0; d < DIM; ++d) dab += ta[d] * tb[d];
   if (DIM == 1) {
-    blk[0][0] += tcuu * (T)mp.E * tga[0] * tgb[0];
+    blk[0][0] += cuu * (T)mp.E * ta[0] * tb[0];
   } else {
     const T lam = (T)mp.lam, mu = (T)mp.mu;
 #pragma unroll
     for (int i = 0; i < DIM; ++i)
 #pragma unroll
       for (int j = 0; j < DIM; ++j)
-        blk[i][j] += tcuu * (lam * tga[i] * tgb[j] + mu * tga[j] * tgb[i] + (i == j ? mu * dab : (T)0));
+        blk[i][j] += cuu * (lam * ta[i] * tb[j] + mu * ta[j] * tb[i] + (i == j ? mu * dab : (T)0));
   }
-  const T cue = (T)r[RC::CUE];
-  const T tNa = (T)Na, tNb = (T)Nb;
+  const T cueN = (T)r[RC::CUE] * (T)Nb;
 #pragma unroll
-  for (int i = 0; i < DIM; ++i) blk[i][DIM] -= cue * (T)Sga[i] * tNb;
+  for (int i = 0; i < DIM; ++i) blk[i][DIM] -= cueN * (T)Sga[i];
+  const T tNa = (T)Na;
 #pragma unroll
   for (int j = 0; j < DIM; ++j) {
-    T s = 0;
+    T gg = 0;
 #pragma unroll
-    for (int i = 0; i < DIM; ++i) s += (T)Gh[j][i] * tgb[i];
-    blk[DIM][j] -= tNa * s;
+    for (int i = 0; i < DIM; ++i) gg += (T)r[RC::GH + sym_idx<DIM>(j, i)] * tb[i];
+    blk[DIM][j] -= tNa * gg;
   }
-  blk[DIM][DIM] += (T)r[RC::CEE] * tNa * tNb + (T)r[RC::CGP] * (T)ga_geb * tNb + (T)r[RC::CG] * dab;
+  blk[DIM][DIM] += (T)r[RC::CEE] * tNa * (T)Nb + (T)r[RC::CGP] * (T)ga_geb * (T)Nb + (T)r[RC::CG] * dab;
 }
 
 // ---------------------------------------------------------------------------
 // Kernel 2: node-row assembly
 // ---------------------------------------------------------------------------
 constexpr int NODE_BLOCK = 256;
+
+template <int DIM, typename T> struct NodeLds {
+  using E = Elem<DIM>;
+  static constexpr int NEN = E::NEN, NGP = E::NGP, ND = E::ND, NB = ND * ND;
+  static constexpr int L = NEN * NEN;                 // lanes per node
+  static constexpr int NPB = NODE_BLOCK / L;          // nodes per workgroup
+  static constexpr int RS = Rec<DIM>::STRIDE;
+  static constexpr int GS = RS + 2;                   // per Gauss point (even: 16-byte aligned)
+  static constexpr int KS = NGP * GS + 2;             // per element: spreads a node's elements over LDS banks
+  static constexpr int REC_D = NPB * NEN * KS;        // phase 1: records, doubles
+  static constexpr int BLK_B = NB * NODE_BLOCK * (int)sizeof(T);
+  static constexpr int F_B = (DIM + 2) * NODE_BLOCK * 8;
+  static constexpr int SLOT_B = NPB * NEN * L * 4;
+  static constexpr int P2_D = (BLK_B + F_B + SLOT_B + 7) / 8;   // phase 2, doubles
+  static constexpr int SMEM_D = REC_D > P2_D ? REC_D : P2_D;
+};
 
 template <int DIM, typename T, bool WANT_K>
 __global__ void __launch_bounds__(NODE_BLOCK) node_kernel(
@@ -406,19 +423,19 @@ __global__ void __launch_bounds__(NODE_BLOCK) node_kernel(
     T* __restrict__ vals, double* __restrict__ R, double* __restrict__ partials) {
   using E = Elem<DIM>;
   using RC = Rec<DIM>;
-  constexpr int NEN = E::NEN, ND = E::ND, NB = ND * ND;
-  constexpr int L = NEN * NEN;                 // lanes per node: (element slot k, local node b)
-  constexpr int NPB = NODE_BLOCK / L;          // nodes per workgroup
-  constexpr int RS = RC::STRIDE;
-  constexpr int RSP = RS + 1;                  // odd stride: the NEN records of a node sit in distinct LDS banks
-  constexpr int FPL = RS / NEN;                // record doubles each lane stages
+  using LD = NodeLds<DIM, T>;
+  constexpr int NEN = E::NEN, ND = E::ND, NB = ND * ND, NGP = E::NGP;
+  constexpr int L = LD::L, NPB = LD::NPB, RS = LD::RS, GS = LD::GS, KS = LD::KS;
+  constexpr int FPL = RS / NEN;                // record doubles each lane stages per Gauss point
   static_assert(RS % NEN == 0, "record staging split");
-  __shared__ double s_rec[NPB][NEN][RSP];      // one Gauss point of the node's elements
-  __shared__ T s_blk[NB][NODE_BLOCK];          // [value][lane]
-  __shared__ int s_pos[NODE_BLOCK];
-  __shared__ double s_f[DIM + 2][NODE_BLOCK];
+  // phase 1: the Gauss-point records of the node's elements; phase 2 (same
+  // memory): element blocks, forces and the position -> local node table
+  __shared__ __align__(16) double smem[LD::SMEM_D];
   __shared__ double s_red[NORM_SLOTS][NPB];
   __shared__ int s_chunks;
+  T* s_blk = reinterpret_cast<T*>(smem);                                   // [NB][NODE_BLOCK]
+  double* s_f = reinterpret_cast<double*>(reinterpret_cast<char*>(smem) + LD::BLK_B);  // [DIM+2][NODE_BLOCK]
+  int* s_slot = reinterpret_cast<int*>(reinterpret_cast<char*>(smem) + LD::BLK_B + LD::F_B);  // [NPB][NEN][L]
 
   const int tid = threadIdx.x;
   const int slot = tid / L;                    // node within the workgroup
@@ -451,14 +468,6 @@ __global__ void __launch_bounds__(NODE_BLOCK) node_kernel(
   for (int ch = 0; ch < chunks; ++ch) {
     const int kk = ch * NEN + k;
     const bool act = valid && kk < ne;
-    T blk[ND][ND];
-#pragma unroll
-    for (int i = 0; i < ND; ++i)
-#pragma unroll
-      for (int j = 0; j < ND; ++j) blk[i][j] = (T)0;
-    double f[DIM + 2];
-#pragma unroll
-    for (int i = 0; i < DIM + 2; ++i) f[i] = 0.0;
     int p = -1, la = 0;
     int64_t e = 0;
     if (act) {
@@ -467,41 +476,55 @@ __global__ void __launch_bounds__(NODE_BLOCK) node_kernel(
       la = ent & 7;
       p = pos[(e * NEN + la) * NEN + b];
     }
-    const bool wf = (b == 0);
-#pragma unroll 1
-    for (int g = 0; g < E::NGP; ++g) {
-      // stage record g of the node's elements: lane (k, b) copies doubles
-      // [b*FPL, (b+1)*FPL) of element k's record (coalesced per element)
-      if (act) {
-        const double* src = rec + (e * E::NGP + g) * RS + b * FPL;
+    // phase 1: stage every Gauss point of the node's elements in one round
+    // (lane (k, b) copies doubles [b*FPL, (b+1)*FPL) of each record of element k)
+    double* srec = smem + (slot * NEN + k) * KS;
+    if (act) {
+      const double* src = rec + e * NGP * RS + b * FPL;
 #pragma unroll
-        for (int q = 0; q < FPL; ++q) s_rec[slot][k][b * FPL + q] = src[q];
-      }
-      __syncthreads();
-      if (act) block_and_force<DIM, T>(&s_rec[slot][k][0], g, la, b, mp, WANT_K, wf, blk, f);
-      __syncthreads();
+      for (int g = 0; g < NGP; ++g)
+#pragma unroll
+        for (int q = 0; q < FPL; ++q) srec[g * GS + b * FPL + q] = src[g * RS + q];
     }
+    __syncthreads();
+    T blk[ND][ND];
 #pragma unroll
     for (int i = 0; i < ND; ++i)
 #pragma unroll
-      for (int j = 0; j < ND; ++j) s_blk[i * ND + j][tid] = blk[i][j];
-    s_pos[tid] = p;
+      for (int j = 0; j < ND; ++j) blk[i][j] = (T)0;
+    double f[DIM + 2];
 #pragma unroll
-    for (int i = 0; i < DIM + 2; ++i) s_f[i][tid] = f[i];
+    for (int i = 0; i < DIM + 2; ++i) f[i] = 0.0;
+    if (act) {
+      const bool wf = (b == 0);
+#pragma unroll 1
+      for (int g = 0; g < NGP; ++g) block_and_force<DIM, T>(srec + g * GS, g, la, b, mp, WANT_K, wf, blk, f);
+    }
     __syncthreads();
-    // lane l owns neighbour position l; sum contributions in element order
+    // phase 2: blocks to LDS, position -> local node table
+#pragma unroll
+    for (int q = 0; q < NEN; ++q) s_slot[(slot * NEN + k) * L + b * NEN + q] = -1;
+    __syncthreads();
+    if (p >= 0) s_slot[(slot * NEN + k) * L + p] = b;
+#pragma unroll
+    for (int i = 0; i < ND; ++i)
+#pragma unroll
+      for (int j = 0; j < ND; ++j) s_blk[(i * ND + j) * NODE_BLOCK + tid] = blk[i][j];
+#pragma unroll
+    for (int i = 0; i < DIM + 2; ++i) s_f[i * NODE_BLOCK + tid] = f[i];
+    __syncthreads();
+    // lane l owns neighbour position l: sum its blocks in element order
     if (valid && l < nnb) {
       const int base = slot * L;
+#pragma unroll
       for (int kq = 0; kq < NEN; ++kq) {
-#pragma unroll
-        for (int bq = 0; bq < NEN; ++bq) {
+        const int bq = s_slot[(slot * NEN + kq) * L + l];
+        if (bq >= 0) {
           const int src = base + kq * NEN + bq;
-          if (s_pos[src] == l) {
 #pragma unroll
-            for (int i = 0; i < ND; ++i)
+          for (int i = 0; i < ND; ++i)
 #pragma unroll
-              for (int j = 0; j < ND; ++j) acc[i][j] += s_blk[i * ND + j][src];
-          }
+            for (int j = 0; j < ND; ++j) acc[i][j] += s_blk[(i * ND + j) * NODE_BLOCK + src];
         }
       }
     }
@@ -509,7 +532,7 @@ __global__ void __launch_bounds__(NODE_BLOCK) node_kernel(
       const int base = slot * L;
       for (int kq = 0; kq < NEN; ++kq) {
 #pragma unroll
-        for (int i = 0; i < DIM + 2; ++i) facc[i] += s_f[i][base + kq * NEN];
+        for (int i = 0; i < DIM + 2; ++i) facc[i] += s_f[i * NODE_BLOCK + base + kq * NEN];
       }
     }
     __syncthreads();
@@ -563,9 +586,9 @@ __global__ void __launch_bounds__(NODE_BLOCK) node_kernel(
   }
   __syncthreads();
   if (tid < NORM_SLOTS) {
-    double s = 0.0;
-    for (int i = 0; i < NPB; ++i) s += s_red[tid][i];
-    partials[(int64_t)blockIdx.x * NORM_SLOTS + tid] = s;
+    double sum = 0.0;
+    for (int i = 0; i < NPB; ++i) sum += s_red[tid][i];
+    partials[(int64_t)blockIdx.x * NORM_SLOTS + tid] = sum;
   }
 }
 

@@ -15,9 +15,10 @@
 //    device-scope fences, which write back L2 on every block of a
 //    multi-XCD part), so results are bitwise repeatable.  The host reads the
 //    scalars every `check_every` iterations.
-//  - FP64 contexts run everything in FP64.  Mixed contexts keep the matrix,
-//    preconditioner and Krylov vectors in FP32 (FP32 SpMV accumulation)
-//    while dot products, norms and the solution accumulate in FP64.
+//  - FP64 contexts run everything in FP64.  Mixed contexts keep the matrix
+//    and the block-Jacobi inverses in FP32 (SpMV and preconditioner apply
+//    accumulate in FP32: the bytes that bound an iteration) while the Krylov
+//    vectors, recurrences, dot products and the solution stay FP64.
 #include <cmath>
 #include <type_traits>
 
@@ -38,10 +39,17 @@ enum {
 // status values
 enum { KS_RUN = 0, KS_CONV = 1, KS_BREAK = 2, KS_NAN = 3 };
 // a recurrence scalar below this fraction of the norms it is made of is a
-// breakdown: ~1e2 ulp of the vector precision (FP64 1e-14, FP32 1e-5)
-template <typename T> constexpr double break_rel() { return std::is_same<T, float>::value ? 1e-5 : 1e-14; }
+// breakdown (~1e2 ulp of the FP64 Krylov vectors)
+template <typename T> constexpr double break_rel() { return 1e-14; }
 // residual at this fraction of |S b| is at the FP64 precision floor: stop
 constexpr double FLOOR_REL2 = 1e-30;
+// a field is judged against max(|b_field|, FIELD_FLOOR |b|): the scaled fields
+// have comparable magnitudes, and a field whose right-hand side is far below
+// the other's cannot be resolved below the operator's rounding of the other
+constexpr double FIELD_FLOOR2 = 1e-6;
+// checks without a new best residual after which a solve has stagnated (the
+// FP32 operator of a mixed context bounds the attainable residual)
+constexpr int STALL_CHECKS = 12;
 
 struct Vecs {
   void* r;
@@ -91,8 +99,9 @@ template <typename T, int ND, int G, int MODE>
 __global__ void __launch_bounds__(BS) spmv_kernel(int64_t nrows, const int32_t* __restrict__ row_ptr,
                                                   const int32_t* __restrict__ nbr_ptr,
                                                   const int32_t* __restrict__ nbr,
-                                                  const T* __restrict__ vals, const T* __restrict__ x,
-                                                  T* __restrict__ y, const T* __restrict__ w,
+                                                  const T* __restrict__ vals,
+                                                  const double* __restrict__ x,
+                                                  double* __restrict__ y, const double* __restrict__ w,
                                                   const double* __restrict__ sc,
                                                   double* __restrict__ part) {
   __shared__ double sm[2][BS];
@@ -119,7 +128,7 @@ __global__ void __launch_bounds__(BS) spmv_kernel(int64_t nrows, const int32_t* 
         if (v < len) {
           const int q = v / ND, c = v - q * ND;
           pv[u] = rv[v];
-          px[u] = x[(int64_t)nb[q] * ND + c];
+          px[u] = (T)x[(int64_t)nb[q] * ND + c];
         } else {
           pv[u] = (T)0;
           px[u] = (T)0;
@@ -131,16 +140,15 @@ __global__ void __launch_bounds__(BS) spmv_kernel(int64_t nrows, const int32_t* 
 #pragma unroll
     for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
     if (lane == 0) {
-      const double yv = (double)acc * row_scale(row, ND, se);
-      const T yt = (T)yv;
+      const double yt = (double)acc * row_scale(row, ND, se);
       y[row] = yt;
       if (MODE == 1) {
-        d0 += (double)w[row] * (double)yt;
-        d1 += (double)yt * (double)yt;
+        d0 += w[row] * yt;
+        d1 += yt * yt;
       }
       if (MODE == 2) {
-        d0 += (double)yt * (double)w[row];
-        d1 += (double)yt * (double)yt;
+        d0 += yt * w[row];
+        d1 += yt * yt;
       }
     }
   }
@@ -213,8 +221,8 @@ __global__ void __launch_bounds__(BS) scalar_kernel(int nblk, const double* __re
   } else {  // KIND 4: after init: rho, |r_u|^2, |r_e|^2, |b_u|^2, |b_e|^2
     const double bu = acc[3], be = acc[4];
     const double btot = bu + be;
-    sc[K_BU] = bu > 0.0 ? bu : btot;
-    sc[K_BE] = be > 0.0 ? be : btot;
+    sc[K_BU] = fmax(bu, FIELD_FLOOR2 * btot);
+    sc[K_BE] = fmax(be, FIELD_FLOOR2 * btot);
     sc[K_B2] = btot;
     sc[K_RH2] = acc[0];
     sc[K_RHO] = acc[0];
@@ -241,13 +249,13 @@ __global__ void __launch_bounds__(BS) scalar_kernel(int nblk, const double* __re
 // p = r + beta (p - omega v); ph = M^-1 p    (one thread per node)
 template <typename T, int ND>
 __global__ void __launch_bounds__(BS) pupdate_kernel(int64_t n_nodes, const T* __restrict__ minv,
-                                                     const T* __restrict__ r, T* __restrict__ p,
-                                                     const T* __restrict__ v, T* __restrict__ ph,
+                                                     const double* __restrict__ r, double* __restrict__ p,
+                                                     const double* __restrict__ v, double* __restrict__ ph,
                                                      const double* __restrict__ sc) {
   if (sc[K_DONE] != 0.0) return;
-  const T beta = (T)sc[K_BETA], om = (T)sc[K_OMEGA];
+  const double beta = sc[K_BETA], om = sc[K_OMEGA];
   for (int64_t a = (int64_t)blockIdx.x * BS + threadIdx.x; a < n_nodes; a += (int64_t)gridDim.x * BS) {
-    T pv[ND];
+    double pv[ND];
 #pragma unroll
     for (int i = 0; i < ND; ++i) {
       const int64_t k = a * ND + i;
@@ -259,8 +267,8 @@ __global__ void __launch_bounds__(BS) pupdate_kernel(int64_t n_nodes, const T* _
     for (int i = 0; i < ND; ++i) {
       T s = 0;
 #pragma unroll
-      for (int j = 0; j < ND; ++j) s += m[i * ND + j] * pv[j];
-      ph[a * ND + i] = s;
+      for (int j = 0; j < ND; ++j) s += m[i * ND + j] * (T)pv[j];
+      ph[a * ND + i] = (double)s;
     }
   }
 }
@@ -268,13 +276,13 @@ __global__ void __launch_bounds__(BS) pupdate_kernel(int64_t n_nodes, const T* _
 // s = r - alpha v; sh = M^-1 s
 template <typename T, int ND>
 __global__ void __launch_bounds__(BS) supdate_kernel(int64_t n_nodes, const T* __restrict__ minv,
-                                                     const T* __restrict__ r, const T* __restrict__ v,
-                                                     T* __restrict__ s, T* __restrict__ sh,
+                                                     const double* __restrict__ r, const double* __restrict__ v,
+                                                     double* __restrict__ s, double* __restrict__ sh,
                                                      const double* __restrict__ sc) {
   if (sc[K_DONE] != 0.0) return;
-  const T al = (T)sc[K_ALPHA];
+  const double al = sc[K_ALPHA];
   for (int64_t a = (int64_t)blockIdx.x * BS + threadIdx.x; a < n_nodes; a += (int64_t)gridDim.x * BS) {
-    T sv[ND];
+    double sv[ND];
 #pragma unroll
     for (int i = 0; i < ND; ++i) {
       const int64_t k = a * ND + i;
@@ -286,18 +294,18 @@ __global__ void __launch_bounds__(BS) supdate_kernel(int64_t n_nodes, const T* _
     for (int i = 0; i < ND; ++i) {
       T acc = 0;
 #pragma unroll
-      for (int j = 0; j < ND; ++j) acc += m[i * ND + j] * sv[j];
-      sh[a * ND + i] = acc;
+      for (int j = 0; j < ND; ++j) acc += m[i * ND + j] * (T)sv[j];
+      sh[a * ND + i] = (double)acc;
     }
   }
 }
 
 // x += alpha ph + omega sh; r = s - omega t; partials of rho, |r_u|^2, |r_e|^2
-template <typename T, int ND>
+template <int ND>
 __global__ void __launch_bounds__(BS) xupdate_kernel(int64_t n, double* __restrict__ x,
-                                                     const T* __restrict__ ph, const T* __restrict__ sh,
-                                                     const T* __restrict__ s, const T* __restrict__ t,
-                                                     T* __restrict__ r, const T* __restrict__ rh,
+                                                     const double* __restrict__ ph, const double* __restrict__ sh,
+                                                     const double* __restrict__ s, const double* __restrict__ t,
+                                                     double* __restrict__ r, const double* __restrict__ rh,
                                                      const double* __restrict__ sc,
                                                      double* __restrict__ part) {
   __shared__ double sm[3][BS];
@@ -305,11 +313,10 @@ __global__ void __launch_bounds__(BS) xupdate_kernel(int64_t n, double* __restri
   const double al = sc[K_ALPHA], om = sc[K_OMEGA];
   double d[3] = {0.0, 0.0, 0.0};
   for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
-    x[i] += al * (double)ph[i] + om * (double)sh[i];
-    const T rv = (T)((double)s[i] - om * (double)t[i]);
-    r[i] = rv;
-    const double rd = (double)rv;
-    d[0] += (double)rh[i] * rd;
+    x[i] += al * ph[i] + om * sh[i];
+    const double rd = s[i] - om * t[i];
+    r[i] = rd;
+    d[0] += rh[i] * rd;
     if (i % ND == ND - 1) d[2] += rd * rd;
     else d[1] += rd * rd;
   }
@@ -317,11 +324,11 @@ __global__ void __launch_bounds__(BS) xupdate_kernel(int64_t n, double* __restri
 }
 
 // r = S b - y, rh = r, p = v = 0; partials of rho and the field norms of r and S b
-template <typename T, int ND>
+template <int ND>
 __global__ void __launch_bounds__(BS) init_kernel(int64_t n, const double* __restrict__ b,
-                                                  const T* __restrict__ y, int use_y, T* __restrict__ r,
-                                                  T* __restrict__ rh, T* __restrict__ p,
-                                                  T* __restrict__ v, const double* __restrict__ sc,
+                                                  const double* __restrict__ y, int use_y, double* __restrict__ r,
+                                                  double* __restrict__ rh, double* __restrict__ p,
+                                                  double* __restrict__ v, const double* __restrict__ sc,
                                                   double* __restrict__ part) {
   __shared__ double sm[5][BS];
   const double se = sc[K_SE];
@@ -329,13 +336,11 @@ __global__ void __launch_bounds__(BS) init_kernel(int64_t n, const double* __res
   for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
     const bool fe = (i % ND == ND - 1);
     const double sb = b[i] * (fe ? se : 1.0);
-    const double rv = sb - (use_y ? (double)y[i] : 0.0);
-    const T rt = (T)rv;
-    r[i] = rt;
-    rh[i] = rt;
-    p[i] = (T)0;
-    v[i] = (T)0;
-    const double rd = (double)rt;
+    const double rd = sb - (use_y ? y[i] : 0.0);
+    r[i] = rd;
+    rh[i] = rd;
+    p[i] = 0.0;
+    v[i] = 0.0;
     d[0] += rd * rd;
     if (fe) {
       d[2] += rd * rd;
@@ -399,12 +404,6 @@ __global__ void bjacobi_kernel(int64_t n_nodes, const int32_t* __restrict__ row_
     for (int c = 0; c < ND; ++c) out[r * ND + c] = ok ? (T)m[r][ND + c] : (T)(r == c ? 1.0 : 0.0);
 }
 
-template <typename T>
-__global__ void to_type_kernel(int64_t n, const double* __restrict__ a, T* __restrict__ b) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) b[i] = (T)a[i];
-}
-
 __global__ void axpy_kernel(int64_t n, double* __restrict__ y, const double* __restrict__ x, double a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] += a * x[i];
@@ -451,7 +450,9 @@ struct Solver {
   double* sc;
   int64_t n, nn;
 
-  void spmv(const T* x, T* y, int mode, const T* w) {
+  double* vec(void* p) { return static_cast<double*>(p); }
+
+  void spmv(const double* x, double* y, int mode, const double* w) {
     const int64_t g = grid_for(n * G);
     if (mode == 0) {
       spmv_kernel<T, ND, G, 0><<<g, BS, 0, c->stream>>>(n, c->row_ptr, c->nbr_ptr, c->nbr, vals, x, y,
@@ -467,22 +468,22 @@ struct Solver {
     }
   }
 
-  void init(const double* b, bool use_y, T* y) {
+  void init(const double* b, bool use_y, const double* y) {
     const int64_t g = grid_for(n);
-    init_kernel<T, ND><<<g, BS, 0, c->stream>>>(n, b, y, use_y ? 1 : 0, (T*)V.r, (T*)V.rh, (T*)V.p,
-                                                (T*)V.v, sc, c->kpart);
+    init_kernel<ND><<<g, BS, 0, c->stream>>>(n, b, y, use_y ? 1 : 0, vec(V.r), vec(V.rh), vec(V.p),
+                                             vec(V.v), sc, c->kpart);
     scalar_kernel<4, 5><<<1, BS, 0, c->stream>>>((int)g, c->kpart, sc);
   }
 
   void iteration(double* x) {
     const int64_t gn = grid_for(nn);
-    pupdate_kernel<T, ND><<<gn, BS, 0, c->stream>>>(nn, minv, (T*)V.r, (T*)V.p, (T*)V.v, (T*)V.ph, sc);
-    spmv((T*)V.ph, (T*)V.v, 1, (T*)V.rh);
-    supdate_kernel<T, ND><<<gn, BS, 0, c->stream>>>(nn, minv, (T*)V.r, (T*)V.v, (T*)V.s, (T*)V.sh, sc);
-    spmv((T*)V.sh, (T*)V.t, 2, (T*)V.s);
+    pupdate_kernel<T, ND><<<gn, BS, 0, c->stream>>>(nn, minv, vec(V.r), vec(V.p), vec(V.v), vec(V.ph), sc);
+    spmv(vec(V.ph), vec(V.v), 1, vec(V.rh));
+    supdate_kernel<T, ND><<<gn, BS, 0, c->stream>>>(nn, minv, vec(V.r), vec(V.v), vec(V.s), vec(V.sh), sc);
+    spmv(vec(V.sh), vec(V.t), 2, vec(V.s));
     const int64_t g = grid_for(n);
-    xupdate_kernel<T, ND><<<g, BS, 0, c->stream>>>(n, x, (T*)V.ph, (T*)V.sh, (T*)V.s, (T*)V.t,
-                                                   (T*)V.r, (T*)V.rh, sc, c->kpart);
+    xupdate_kernel<ND><<<g, BS, 0, c->stream>>>(n, x, vec(V.ph), vec(V.sh), vec(V.s), vec(V.t),
+                                                vec(V.r), vec(V.rh), sc, c->kpart);
     scalar_kernel<3, 3><<<1, BS, 0, c->stream>>>((int)g, c->kpart, sc);
   }
 };
@@ -497,13 +498,13 @@ hipError_t solve_impl(lgdm_ctx* c, const double* b, double* xout, const lgdm_sol
   const bool mixed = std::is_same<T, float>::value;
   S.vals = mixed ? (const T*)c->vals32 : (const T*)c->vals;
   S.minv = mixed ? (const T*)c->minv32 : (const T*)c->minv;
-  T* base = mixed ? (T*)c->kv32 : (T*)c->kv;
+  double* base = c->kv;
   void** vp[8] = {&S.V.r, &S.V.rh, &S.V.p, &S.V.v, &S.V.s, &S.V.t, &S.V.ph, &S.V.sh};
   for (int i = 0; i < 8; ++i) *vp[i] = base + (int64_t)i * c->ndof;
   S.sc = c->kscal;
   hipError_t e;
   double tol = o.tol_krylov;
-  if (mixed && tol < 1e-6) tol = 1e-6;  // FP32 inner solve; Newton refines in FP64
+  if (mixed && tol < 1e-6) tol = 1e-6;  // FP32 operator; Newton refines on the FP64 residual
   const double se = c->mat.E / c->mat.h;
   set_scalars_kernel<<<1, 64, 0, c->stream>>>(S.sc, tol * tol, se, break_rel<T>());
   if ((e = hipMemsetAsync(xout, 0, c->ndof * sizeof(double), c->stream)) != hipSuccess) return e;
@@ -515,13 +516,22 @@ hipError_t solve_impl(lgdm_ctx* c, const double* b, double* xout, const lgdm_sol
   int64_t done_iters = 0;
   bool true_residual = true;   // the scalars describe b - A x computed directly
   int replacements = 0;
+  // best iterate so far (per-field relative residual); returned when the
+  // solve stagnates or a recurrence turns non-finite
+  double* xbest = c->kv + 8 * c->ndof;
+  double best = INFINITY;
+  int stall = 0;
+  bool have_best = false;
+  auto return_best = [&](int status) {
+    if (have_best)
+      (void)hipMemcpyAsync(xout, xbest, c->ndof * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+    res.status = status;
+  };
   // restart the recurrences from the current iterate with its true residual
   auto restart_from_x = [&]() {
-    T* tmp = (T*)S.V.ph;
-    to_type_kernel<T><<<(S.n + 255) / 256, 256, 0, c->stream>>>(S.n, xout, tmp);
     set_scalars_kernel<<<1, 64, 0, c->stream>>>(S.sc, tol * tol, se, break_rel<T>());
-    S.spmv(tmp, (T*)S.V.t, 0, nullptr);
-    S.init(b, true, (T*)S.V.t);
+    S.spmv(xout, S.vec(S.V.t), 0, nullptr);
+    S.init(b, true, S.vec(S.V.t));
   };
   while (true) {
     if ((e = hipMemcpyAsync(c->kscal_host, S.sc, K_NSLOTS * sizeof(double), hipMemcpyDeviceToHost,
@@ -548,7 +558,8 @@ hipError_t solve_impl(lgdm_ctx* c, const double* b, double* xout, const lgdm_sol
         continue;
       }
       if (st == KS_NAN) {
-        res.status = LGDM_ERR_NAN;
+        if (have_best) return_best(LGDM_ERR_NOT_CONVERGED);
+        else res.status = LGDM_ERR_NAN;
         break;
       }
       // breakdown: restart from the current iterate with the true residual
@@ -563,8 +574,19 @@ hipError_t solve_impl(lgdm_ctx* c, const double* b, double* xout, const lgdm_sol
       continue;
     }
     true_residual = false;
+    const double score = std::max(res.rel_u, res.rel_e);
+    if (std::isfinite(score) && score < best * (1.0 - 1e-3)) {
+      best = score;
+      stall = 0;
+      have_best = true;
+      if ((e = hipMemcpyAsync(xbest, xout, c->ndof * sizeof(double), hipMemcpyDeviceToDevice,
+                              c->stream)) != hipSuccess) return e;
+    } else if (++stall >= STALL_CHECKS) {
+      return_best(LGDM_ERR_NOT_CONVERGED);
+      break;
+    }
     if (res.iters >= o.max_krylov) {
-      res.status = LGDM_ERR_NOT_CONVERGED;
+      return_best(LGDM_ERR_NOT_CONVERGED);
       break;
     }
     for (int i = 0; i < every; ++i) S.iteration(xout);
@@ -612,11 +634,9 @@ template <typename T, int ND> hipError_t spmv_only_impl(lgdm_ctx* c, const doubl
   S.nn = c->n_nodes;
   const bool mixed = std::is_same<T, float>::value;
   S.vals = mixed ? (const T*)c->vals32 : (const T*)c->vals;
-  T* base = mixed ? (T*)c->kv32 : (T*)c->kv;
   S.sc = c->kscal;
   set_scalars_kernel<<<1, 64, 0, c->stream>>>(S.sc, 0.0, c->mat.E / c->mat.h, break_rel<T>());
-  to_type_kernel<T><<<(S.n + 255) / 256, 256, 0, c->stream>>>(S.n, x, base);
-  S.spmv(base, base + c->ndof, 0, nullptr);
+  S.spmv(x, c->kv, 0, nullptr);
   return hipGetLastError();
 }
 

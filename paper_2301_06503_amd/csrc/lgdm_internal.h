@@ -108,8 +108,7 @@ struct lgdm_ctx {
   double last_norms[lgdm::NORM_SLOTS] = {0, 0, 0, 0, 0, 0};
 
   // Krylov workspace (H6)
-  double* kv = nullptr;            // 8 FP64 vectors of ndof
-  float* kv32 = nullptr;           // FP32 vectors for the mixed inner solve
+  double* kv = nullptr;            // 8 FP64 Krylov vectors + the best iterate, ndof each
   double* minv = nullptr;          // block-Jacobi inverses [n_nodes * nd * nd]
   float* minv32 = nullptr;
   double* kpart = nullptr;         // per-block partial sums

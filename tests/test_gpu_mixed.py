@@ -1,0 +1,95 @@
+"""Mixed precision (FP32 tangent, block-Jacobi and inner SpMV; FP64 residual,
+history/damage update, Krylov dots and Newton update) against the FP64 oracle
+and against the FP64 GPU path.  The errors are printed (the stated error of
+each result against FP64) and bounded:
+
+  FP32 CSR values vs oracle            <= 2e-6 max|block| per block type
+  FP64 residual / kappa / D (injected)  1e-12 (the residual path stays FP64)
+  damage over a load path vs oracle    <= 1e-7 absolute (Newton to 1e-10)
+  3D mixed vs FP64 GPU (both to ||R||/||F|| < 1e-8): the two converged states
+  differ by what the Newton tolerance allows at the conditioning of the
+  problem; stated, and bounded by 1e-4 (fields, relative) / 1e-5 (damage)
+"""
+import numpy as np
+import pytest
+
+import lgdm_workloads as W
+from oracle.lgdm import Oracle
+from tests.gpu_util import context, blockwise_error, fieldwise_error, tiny_problems
+
+pytestmark = pytest.mark.gpu
+
+TINY = tiny_problems()
+MIXED = 1
+
+
+@pytest.mark.parametrize("name", ["bar1d_37", "sen2d_9x6_distorted", "beam3d_10x4x3", "c3p"])
+def test_mixed_injected_assembly(name):
+    print("case:", name, flush=True)
+    prob = TINY[name] if name in TINY else W.config(name)
+    x, kn = W.injected_state(prob, seed=4)
+    ctx = context(prob, MIXED)
+    ctx.set_state(x, kn)
+    view, R = ctx.assemble()
+    assert not view.vals and view.vals32
+    vals = ctx.csr_values(view)
+    assert vals.dtype == np.float32
+    rp, ci = ctx.csr_pattern()
+    st = Oracle(prob).eval_state(x, kn)
+    err = blockwise_error(vals.astype(np.float64), st["K"].data, rp, ci, prob.ndpn)
+    print("FP32 tangent error vs FP64 oracle per block:", err)
+    assert max(err.values()) <= 2e-6, err
+    ferr = fieldwise_error(R.cpu().numpy(), st["R"], prob.ndpn)
+    assert max(ferr.values()) <= 1e-12, ferr
+    np.testing.assert_allclose(ctx.query(4), st["D"].ravel(), rtol=0, atol=1e-12)
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", ["bar1d_37", "sen2d_13x7_ps", "beam3d_10x4x3"])
+def test_mixed_load_path_vs_oracle(name):
+    from paper_2301_06503_amd import binding
+    print("case:", name, flush=True)
+    prob = TINY[name]
+    ctx = context(prob, MIXED)
+    o = Oracle(prob)
+    opts = binding.solver_opts(tol_newton=1e-10, tol_krylov=1e-6, max_krylov=50000)
+    errs = []
+    newton = []
+    for n in range(1, prob.n_increments + 1):
+        lam = n / prob.n_increments
+        rg = ctx.solve_increment(lam, opts)
+        ro = o.solve_increment(lam=lam, tol=1e-10)
+        assert ro["converged"]
+        errs.append(float(np.abs(ctx.query(2) - ro["D"]).max()))
+        newton.append((rg["newton_iters"], ro["iters"]))
+    print("mixed vs FP64 oracle: max damage error %.3e over %d increments; Newton iterations "
+          "mixed/oracle total %d/%d" % (max(errs), len(errs), sum(a for a, _ in newton),
+                                         sum(b for _, b in newton)))
+    assert max(errs) <= 1e-7
+    ctx.close()
+
+
+@pytest.mark.parametrize("name,n_inc", [("c3p", 6), ("c3", 2)])
+def test_mixed_vs_fp64_gpu(name, n_inc):
+    from paper_2301_06503_amd import binding
+    print("case:", name, flush=True)
+    prob = W.config(name)
+    # with an FP32 operator Newton refines at the rate the FP32 inner solve
+    # allows, so it may need more iterations than the FP64 path
+    opts = binding.solver_opts(max_newton=80, tol_newton=1e-8, tol_krylov=1e-6, max_krylov=20000)
+    res = {}
+    for prec in (0, MIXED):
+        ctx = context(prob, prec)
+        reps = [ctx.solve_increment(n / prob.n_increments, opts) for n in range(1, n_inc + 1)]
+        res[prec] = (ctx.query(0), ctx.query(2), reps)
+        ctx.close()
+    x64, d64, r64 = res[0]
+    x32, d32, r32 = res[MIXED]
+    ferr = fieldwise_error(x32, x64, prob.ndpn)
+    derr = float(np.abs(d32 - d64).max())
+    print("mixed vs FP64 GPU after %d increments: field error %s, damage error %.3e, Newton "
+          "iterations %s vs %s, Krylov %s vs %s" % (
+              n_inc, ferr, derr, [r["newton_iters"] for r in r32], [r["newton_iters"] for r in r64],
+              [r["krylov_iters"] for r in r32], [r["krylov_iters"] for r in r64]))
+    assert max(ferr.values()) <= 1e-4, ferr
+    assert derr <= 1e-5

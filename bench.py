@@ -181,6 +181,26 @@ def cpu_baseline(prob, budget_s=20.0):
                       % (done_el, prob.n_elems, dt, os.cpu_count())}
 
 
+def copy_calibration(nbytes=1 << 30):
+    """A plain elementwise copy of known size (reads and writes nbytes), so
+    that hardware byte counters of the same run can be scaled to bytes."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.mul(a, 1.0, out=b)                       # warm-up (module load)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(5):
+        torch.mul(a, 1.0, out=b)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / 5
+    del a, b
+    return {"kernel": "torch.mul(a, 1.0, out=b) float32", "bytes_read": nbytes, "bytes_written": nbytes,
+            "ms": ms, "gbs": 2 * nbytes / (ms * 1e-3) / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -227,6 +247,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(prob)
+    copy_cal = copy_calibration()
     out = {
         "metric": METRIC,
         "value": main_res["gp_per_s"],
@@ -246,6 +267,7 @@ def main():
         "roofline": roofline,
         "roofline_assembly": roof_asm,
         "cpu_baseline": cpu,
+        "copy_calibration": copy_cal,
         "detail": main_res,
         "fp64": fp64_res,
     }

@@ -51,7 +51,8 @@ enum {
   LGDM_ERR_NOT_CONVERGED = 4,/* Newton did not converge; committed state kept  */
   LGDM_ERR_NAN = 5,          /* non-finite residual or solver scalar           */
   LGDM_ERR_BREAKDOWN = 6,    /* Krylov breakdown that restarts did not cure    */
-  LGDM_ERR_STATE = 7         /* call needs a mesh / material / state first     */
+  LGDM_ERR_STATE = 7,        /* call needs a mesh / material / state first     */
+  LGDM_ERR_BUSY = 8          /* batch: no free slot or HBM budget right now    */
 };
 
 enum { LGDM_FP64 = 0, LGDM_MIXED = 1 };          /* precision of a context      */
@@ -244,6 +245,97 @@ lgdm_status lgdm_kernel_times(lgdm_ctx* ctx, int32_t reps, double* avg_ms);
 
 /* Device bytes held by the context (mesh, pattern, state, matrix, solver). */
 lgdm_status lgdm_footprint(lgdm_ctx* ctx, int64_t* bytes);
+
+/* ------------------------------------------------------------------------
+ * Continuous batching of many simulation requests on one device.
+ *
+ * A batch holds up to max_slots requests.  Each admitted request keeps its
+ * mesh, pattern, state (u, ebar, kappa_n) and tangent resident in its own
+ * slot.  lgdm_batch_tick advances every running request by one Newton
+ * iteration of Algorithm 2: one fused Gauss-point launch and one fused
+ * node-row assembly launch cover all running requests; the linear solves of
+ * the requests that need one run on per-slot streams and overlap on the
+ * device.  Converged increments are committed per request (Eq. A.2) and the
+ * request moves to its next load step.  Every reduction belongs to one
+ * request and runs in a fixed order, so a request's results do not depend
+ * on which other requests share the batch.
+ * ------------------------------------------------------------------------ */
+typedef struct lgdm_batch lgdm_batch;
+
+/* One request: the problem statement of Algorithm 2 (geometry, material,
+ * loads and boundary conditions) plus its number of uniform load steps.
+ * Arrays are host pointers, copied at admission. */
+typedef struct lgdm_request {
+  int32_t dim, elem_type;
+  int64_t n_nodes;
+  const double* coords;      /* [n_nodes * dim]                    */
+  int64_t n_elems;
+  const int32_t* conn;       /* [n_elems * 2^dim]                  */
+  const double* e_scale;     /* [n_elems] or NULL                  */
+  lgdm_material material;
+  int64_t n_bc;
+  const int64_t* bc_dofs;    /* [n_bc] displacement dofs           */
+  const double* bc_values;   /* [n_bc] values at load factor 1     */
+  int64_t n_increments;      /* load factor of increment n is n / n_increments */
+} lgdm_request;
+
+enum { LGDM_SLOT_FREE = 0, LGDM_SLOT_RUNNING = 1, LGDM_SLOT_FINISHED = 2, LGDM_SLOT_FAILED = 3 };
+
+typedef struct lgdm_slot_info {
+  int32_t state;             /* LGDM_SLOT_*                                   */
+  int32_t newton_in_increment;
+  int64_t increment;         /* committed increments                          */
+  int64_t n_increments;
+  int64_t newton_total, krylov_total, assemblies_total;
+  int64_t n_gauss, ndof, footprint_bytes;
+  double max_damage;         /* of the last committed increment               */
+  int32_t last_status;       /* lgdm_status of the failure for FAILED slots   */
+  int32_t reserved;
+} lgdm_slot_info;
+
+typedef struct lgdm_tick_report {
+  int32_t running;           /* requests advanced by this tick                */
+  int32_t solves;            /* linear solves performed                       */
+  int32_t committed;         /* increments committed                          */
+  int32_t finished;          /* requests that completed their load path       */
+  int64_t gauss_points;      /* Gauss points assembled by the fused launch    */
+  int64_t krylov_iters;
+  double t_assembly_ms;      /* device time of the fused assembly launches    */
+  double t_tick_ms;          /* host wall time of the tick                    */
+} lgdm_tick_report;
+
+/* Create a batch on `device` (fused launches go to hip_stream; each slot gets
+ * a stream of its own at default priority).  precision as lgdm_create.
+ * hbm_budget_bytes bounds the sum of admitted footprints (0 = free device
+ * memory at creation). */
+lgdm_status lgdm_batch_create(lgdm_batch** out, int32_t device, void* hip_stream, int32_t precision,
+                              int32_t max_slots, int64_t hbm_budget_bytes);
+lgdm_status lgdm_batch_destroy(lgdm_batch* b);
+const char* lgdm_batch_last_error(const lgdm_batch* b);
+
+/* Upper bound of the device bytes one request of this size holds. */
+lgdm_status lgdm_request_footprint(int32_t dim, int64_t n_nodes, int64_t n_elems, int32_t precision,
+                                   int64_t* bytes);
+
+/* Admit a request into a free slot if its footprint fits the budget:
+ * LGDM_OK and *slot on success, LGDM_ERR_BUSY (nothing changed) when no slot
+ * or budget is free; INVALID_ARG for a bad request or a request whose
+ * dimension differs from the requests already in the batch. */
+lgdm_status lgdm_batch_admit(lgdm_batch* b, const lgdm_request* r, int32_t* slot);
+
+/* One Newton iteration for every running request (see above).  o nullable. */
+lgdm_status lgdm_batch_tick(lgdm_batch* b, const lgdm_solver_opts* o, lgdm_tick_report* rep);
+
+lgdm_status lgdm_batch_slot_info(lgdm_batch* b, int32_t slot, lgdm_slot_info* info);
+
+/* lgdm_query_state on the request in `slot`. */
+lgdm_status lgdm_batch_query(lgdm_batch* b, int32_t slot, int32_t field, double* out, int64_t n);
+
+/* Release a finished or failed request's slot and device memory. */
+lgdm_status lgdm_batch_retire(lgdm_batch* b, int32_t slot);
+
+/* Bytes admitted, the budget, and the number of occupied slots. */
+lgdm_status lgdm_batch_usage(lgdm_batch* b, int64_t* used, int64_t* budget, int32_t* occupied);
 
 #ifdef __cplusplus
 }

@@ -278,7 +278,7 @@ class Request:
 
 def serving_stream(n_requests: int = 256, rate_per_s: float = 20.0, seed: int = 0,
                    nx_min: int = 40, nx_max: int = 400, inc_min: int = 50,
-                   inc_max: int = 200) -> List[Request]:
+                   inc_max: int = 200, first_increments: Optional[int] = None) -> List[Request]:
     """Seeded stream of 2D notched-plate requests with Poisson arrivals.
 
     Per request, in this draw order from numpy's PCG64 (default_rng(seed)):
@@ -287,7 +287,9 @@ def serving_stream(n_requests: int = 256, rate_per_s: float = 20.0, seed: int = 
     f ~ U[0.2, 0.5] (length round(f*nx) elements at row ny/2); E ~ U[2e4, 4e4]
     MPa; kappa0 ~ U[5e-5, 2e-4]; beta ~ U[100, 500]; c ~ U[1, 16] mm^2;
     R ~ U[0.005, 0.05]; increments ~ U{inc_min..inc_max}.  Fixed: nu = 0.2,
-    alpha = 0.99, eta = 5, k = 10, top displacement 0.1 mm.
+    alpha = 0.99, eta = 5, k = 10, top displacement 0.1 mm.  first_increments
+    (short runs) keeps only the first increments of each request's load path
+    (same step size, proportionally smaller final displacement).
     """
     rng = np.random.default_rng(seed)
     t = 0.0
@@ -303,8 +305,12 @@ def serving_stream(n_requests: int = 256, rate_per_s: float = 20.0, seed: int = 
         R = float(rng.uniform(0.005, 0.05))
         n_inc = int(rng.integers(inc_min, inc_max + 1))
         mat = base_material(E=E, beta=beta, kappa0=kappa0, c=c, R=R)
-        prob = sen2d(nx=nx, ny=nx // 2, notch_len=int(round(f * nx)), n_increments=n_inc,
-                     material=mat)
+        u_top, n_run = 0.1, n_inc
+        if first_increments is not None and first_increments < n_inc:
+            n_run = first_increments
+            u_top = 0.1 * n_run / n_inc
+        prob = sen2d(nx=nx, ny=nx // 2, notch_len=int(round(f * nx)), n_increments=n_run,
+                     u_top=u_top, material=mat)
         prob.name = "req%03d_%dx%d" % (rid, nx, nx // 2)
         out.append(Request(rid, t, prob))
     return out

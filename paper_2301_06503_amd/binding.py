@@ -22,8 +22,10 @@ FP64, MIXED = 0, 1
 FIELD_X, FIELD_KAPPA, FIELD_DAMAGE, FIELD_KAPPA_TRIAL, FIELD_DAMAGE_TRIAL = 0, 1, 2, 3, 4
 FIELD_RESIDUAL, FIELD_REACTION = 5, 6
 
+LGDM_ERR_BUSY = 8
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "OOM", 3: "DEVICE", 4: "NOT_CONVERGED", 5: "NAN",
-                6: "BREAKDOWN", 7: "STATE"}
+                6: "BREAKDOWN", 7: "STATE", 8: "BUSY"}
+SLOT_FREE, SLOT_RUNNING, SLOT_FINISHED, SLOT_FAILED = 0, 1, 2, 3
 
 # every entry point the header declares
 EXPORTS = [
@@ -33,6 +35,9 @@ EXPORTS = [
     "lgdm_newton_iteration", "lgdm_commit_increment", "lgdm_abort_increment", "lgdm_get_csr",
     "lgdm_get_connectivity", "lgdm_get_sizes", "lgdm_query_state", "lgdm_set_state",
     "lgdm_debug_element_blocks", "lgdm_kernel_times", "lgdm_footprint",
+    "lgdm_batch_create", "lgdm_batch_destroy", "lgdm_batch_last_error", "lgdm_request_footprint",
+    "lgdm_batch_admit", "lgdm_batch_tick", "lgdm_batch_slot_info", "lgdm_batch_query",
+    "lgdm_batch_retire", "lgdm_batch_usage",
 ]
 
 
@@ -65,6 +70,33 @@ class CsrView(ctypes.Structure):
     _fields_ = [("nrows", ctypes.c_int64), ("nnz", ctypes.c_int64),
                 ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p),
                 ("vals", ctypes.c_void_p), ("vals32", ctypes.c_void_p)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("elem_type", ctypes.c_int32), ("n_nodes", ctypes.c_int64),
+                ("coords", ctypes.c_void_p), ("n_elems", ctypes.c_int64), ("conn", ctypes.c_void_p),
+                ("e_scale", ctypes.c_void_p), ("material", Material), ("n_bc", ctypes.c_int64),
+                ("bc_dofs", ctypes.c_void_p), ("bc_values", ctypes.c_void_p),
+                ("n_increments", ctypes.c_int64)]
+
+
+class SlotInfo(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("newton_in_increment", ctypes.c_int32)] + [
+        (n, ctypes.c_int64) for n in ("increment", "n_increments", "newton_total", "krylov_total",
+                                      "assemblies_total", "n_gauss", "ndof", "footprint_bytes")] + [
+        ("max_damage", ctypes.c_double), ("last_status", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class TickReport(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("running", "solves", "committed", "finished")] + [
+        ("gauss_points", ctypes.c_int64), ("krylov_iters", ctypes.c_int64),
+        ("t_assembly_ms", ctypes.c_double), ("t_tick_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
 
 
 _lib = None
@@ -107,6 +139,15 @@ def load_library(path: str = LIB_PATH):
         "lgdm_debug_element_blocks": [P, I64, I64, P, P],
         "lgdm_footprint": [P, ctypes.POINTER(I64)],
         "lgdm_kernel_times": [P, I32, P],
+        "lgdm_batch_create": [ctypes.POINTER(P), I32, P, I32, I32, I64],
+        "lgdm_batch_destroy": [P],
+        "lgdm_request_footprint": [I32, I64, I64, I32, ctypes.POINTER(I64)],
+        "lgdm_batch_admit": [P, ctypes.POINTER(Request), ctypes.POINTER(I32)],
+        "lgdm_batch_tick": [P, ctypes.POINTER(SolverOpts), ctypes.POINTER(TickReport)],
+        "lgdm_batch_slot_info": [P, I32, ctypes.POINTER(SlotInfo)],
+        "lgdm_batch_query": [P, I32, I32, P, I64],
+        "lgdm_batch_retire": [P, I32],
+        "lgdm_batch_usage": [P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I32)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -114,6 +155,8 @@ def load_library(path: str = LIB_PATH):
         f.restype = I32
     lib.lgdm_last_error.argtypes = [P]
     lib.lgdm_last_error.restype = ctypes.c_char_p
+    lib.lgdm_batch_last_error.argtypes = [P]
+    lib.lgdm_batch_last_error.restype = ctypes.c_char_p
     _lib = lib
     return lib
 
@@ -361,3 +404,90 @@ class Context:
         b = ctypes.c_int64()
         self._check(self.lib.lgdm_footprint(self.h, ctypes.byref(b)))
         return b.value
+
+
+class Batch:
+    """Continuous batching of requests on one device (lgdm_batch_* of the C ABI)."""
+
+    def __init__(self, device: int = 0, precision: int = MIXED, max_slots: int = 64,
+                 hbm_budget_bytes: int = 0, stream=None):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        st = self.lib.lgdm_batch_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream),
+                                        precision, max_slots, int(hbm_budget_bytes))
+        if st != LGDM_OK:
+            raise LgdmError(st, "lgdm_batch_create failed")
+        self.h = h
+        self.precision = precision
+        self._keep = {}
+
+    def _check(self, st, ok=(LGDM_OK,)):
+        if st not in ok:
+            raise LgdmError(st, self.lib.lgdm_batch_last_error(self.h).decode())
+        return st
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lgdm_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def footprint(self, prob) -> int:
+        b = ctypes.c_int64()
+        self._check(self.lib.lgdm_request_footprint(prob.dim, prob.n_nodes, prob.n_elems,
+                                                    self.precision, ctypes.byref(b)))
+        return b.value
+
+    def admit(self, prob):
+        """Admit an lgdm_workloads.Problem; returns its slot, or None if the
+        batch has no free slot or HBM budget right now."""
+        coords = np.ascontiguousarray(prob.coords, dtype=np.float64)
+        conn = np.ascontiguousarray(prob.conn, dtype=np.int32)
+        es = np.ascontiguousarray(prob.e_scale, dtype=np.float64)
+        dofs = np.ascontiguousarray(prob.bc_dofs(), dtype=np.int64)
+        vals = np.ascontiguousarray(prob.bc_values, dtype=np.float64)
+        r = Request(dim=prob.dim, elem_type=prob.elem_type, n_nodes=prob.n_nodes,
+                    coords=coords.ctypes.data, n_elems=prob.n_elems, conn=conn.ctypes.data,
+                    e_scale=es.ctypes.data, material=material_struct(prob.material),
+                    n_bc=dofs.size, bc_dofs=dofs.ctypes.data, bc_values=vals.ctypes.data,
+                    n_increments=prob.n_increments)
+        slot = ctypes.c_int32(-1)
+        st = self.lib.lgdm_batch_admit(self.h, ctypes.byref(r), ctypes.byref(slot))
+        if st == LGDM_ERR_BUSY:
+            return None
+        self._check(st)
+        return slot.value
+
+    def tick(self, opts: Optional[SolverOpts] = None):
+        rep = TickReport()
+        o = opts or SolverOpts()
+        self._check(self.lib.lgdm_batch_tick(self.h, ctypes.byref(o), ctypes.byref(rep)))
+        return rep.as_dict()
+
+    def info(self, slot: int):
+        i = SlotInfo()
+        self._check(self.lib.lgdm_batch_slot_info(self.h, slot, ctypes.byref(i)))
+        return i.as_dict()
+
+    def query(self, slot: int, field: int, n: int):
+        out = np.empty(n, dtype=np.float64)
+        self._check(self.lib.lgdm_batch_query(self.h, slot, field, out.ctypes.data_as(ctypes.c_void_p), n))
+        return out
+
+    def retire(self, slot: int):
+        self._check(self.lib.lgdm_batch_retire(self.h, slot))
+
+    def usage(self):
+        u, b, o = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        self._check(self.lib.lgdm_batch_usage(self.h, ctypes.byref(u), ctypes.byref(b), ctypes.byref(o)))
+        return u.value, b.value, o.value

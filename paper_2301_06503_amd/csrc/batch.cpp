@@ -1,0 +1,411 @@
+// Continuous batching of LGDM simulation requests on one device: slots with
+// resident per-request state, admission by HBM footprint, one fused launch of
+// each element kernel per tick over all running requests, and per-slot
+// BiCGSTAB runs on per-slot streams interleaved by the host so that their
+// kernels overlap on the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lgdm_internal.h"
+
+using namespace lgdm;
+
+namespace {
+
+struct Slot {
+  lgdm_ctx* ctx = nullptr;
+  hipStream_t stream = nullptr;
+  int state = LGDM_SLOT_FREE;
+  int64_t n_increments = 0;
+  int64_t footprint = 0;
+  bool in_increment = false;
+  int newton = 0;               // solves in the current increment
+  int64_t newton_total = 0, krylov_total = 0, assemblies_total = 0;
+  double max_damage = 0.0;
+  int last_status = LGDM_OK;
+  std::unique_ptr<KrylovRun> run;
+  bool solving = false;
+  KrylovResult kres{};
+};
+
+}  // namespace
+
+struct lgdm_batch {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int precision = LGDM_FP64;
+  int dim = 0;                  // all requests of a batch share the element type
+  int64_t budget = 0, used = 0;
+  std::vector<Slot> slots;
+  SlotDesc* desc_host = nullptr;  // pinned
+  SlotDesc* desc_dev = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::string err;
+};
+
+namespace {
+
+lgdm_status bfail(lgdm_batch* b, lgdm_status s, const std::string& m) {
+  if (b) b->err = m;
+  return s;
+}
+
+#define BHIP(b, expr, where)                                                              \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess) return bfail(b, LGDM_ERR_DEVICE, std::string(where) + ": " +   \
+                                                             hipGetErrorString(e_));      \
+  } while (0)
+
+bool converged(const lgdm_ctx* c, double tol) {
+  const double tiny = 1e-300;
+  return std::sqrt(c->last_norms[0]) <= tol * std::max(std::sqrt(c->last_norms[2]), tiny) &&
+         std::sqrt(c->last_norms[1]) <= tol * std::max(std::sqrt(c->last_norms[3]), tiny);
+}
+
+lgdm_solver_opts opts_or_default(const lgdm_solver_opts* o) {
+  lgdm_solver_opts r{};
+  if (o) r = *o;
+  if (r.max_newton <= 0) r.max_newton = 30;
+  if (r.max_krylov <= 0) r.max_krylov = 20000;
+  if (!(r.tol_newton > 0)) r.tol_newton = 1e-8;
+  if (!(r.tol_krylov > 0)) r.tol_krylov = 1e-10;
+  if (r.check_every <= 0) r.check_every = 16;
+  if (r.max_restarts <= 0) r.max_restarts = 8;
+  return r;
+}
+
+void release(lgdm_batch* b, Slot& s) {
+  if (s.ctx) {
+    lgdm_destroy(s.ctx);
+    s.ctx = nullptr;
+  }
+  if (s.stream) {
+    (void)hipStreamDestroy(s.stream);
+    s.stream = nullptr;
+  }
+  b->used -= s.footprint;
+  s = Slot();
+}
+
+void fail_slot(Slot& s, lgdm_status st) {
+  s.state = LGDM_SLOT_FAILED;
+  s.last_status = st;
+  s.solving = false;
+  s.run.reset();
+  if (s.ctx) lgdm_abort_increment(s.ctx);
+  s.in_increment = false;
+}
+
+}  // namespace
+
+extern "C" {
+
+lgdm_status lgdm_request_footprint(int32_t dim, int64_t n_nodes, int64_t n_elems, int32_t precision,
+                                   int64_t* bytes) {
+  if (!bytes || dim < 1 || dim > 3 || n_nodes <= 0 || n_elems <= 0) return LGDM_ERR_INVALID_ARG;
+  const int64_t nd = dim + 1, nen = 1 << dim, ngp = 1 << dim;
+  int64_t nbr = 1;
+  for (int d = 0; d < dim; ++d) nbr *= 3;                       // structured bound
+  const int64_t ndof = n_nodes * nd, ng = n_elems * ngp;
+  const int64_t nnz = n_nodes * nbr * nd * nd;
+  const int64_t sval = precision == LGDM_MIXED ? 4 : 8;
+  const int64_t rs = dim == 1 ? Rec<1>::STRIDE : (dim == 2 ? Rec<2>::STRIDE : Rec<3>::STRIDE);
+  int64_t s = 0;
+  s += n_nodes * dim * 8 + n_elems * nen * 4 + n_elems * 8;     // mesh
+  s += (n_nodes + 1) * 4 * 2 + n_elems * nen * 4 + n_nodes * nbr * 4 + n_nodes * 4;  // graph
+  s += n_elems * nen * nen;                                     // positions
+  s += (ndof + 1) * 4 + nnz * 4 + nnz * sval;                   // CSR
+  s += ndof * 8 * (4 + 9) + ndof;                               // state, Krylov vectors, flags
+  s += ng * 8 * 4 + ng * rs * 8;                                // Gauss-point state, records
+  s += n_nodes * nd * nd * sval;                                // block-Jacobi
+  s += (int64_t)(2048 * 8 + 1024 * 6 + 256) * 8;               // partials
+  s += ((n_nodes + 3) / 4 + 1) * 6 * 8;
+  *bytes = s + (int64_t)64 * 256;                               // allocation rounding
+  return LGDM_OK;
+}
+
+lgdm_status lgdm_batch_create(lgdm_batch** out, int32_t device, void* hip_stream, int32_t precision,
+                              int32_t max_slots, int64_t hbm_budget_bytes) {
+  if (!out || max_slots <= 0 || max_slots > 4096) return LGDM_ERR_INVALID_ARG;
+  if (precision != LGDM_FP64 && precision != LGDM_MIXED) return LGDM_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (hipSetDevice(device) != hipSuccess) return LGDM_ERR_DEVICE;
+  lgdm_batch* b = new (std::nothrow) lgdm_batch();
+  if (!b) return LGDM_ERR_OOM;
+  b->device = device;
+  b->stream = (hipStream_t)hip_stream;
+  b->precision = precision;
+  b->slots.resize(max_slots);
+  if (hbm_budget_bytes <= 0) {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+      delete b;
+      return LGDM_ERR_DEVICE;
+    }
+    hbm_budget_bytes = (int64_t)fr;
+  }
+  b->budget = hbm_budget_bytes;
+  if (hipHostMalloc((void**)&b->desc_host, max_slots * sizeof(SlotDesc), hipHostMallocDefault) != hipSuccess ||
+      hipMalloc((void**)&b->desc_dev, max_slots * sizeof(SlotDesc)) != hipSuccess ||
+      hipEventCreate(&b->ev0) != hipSuccess || hipEventCreate(&b->ev1) != hipSuccess) {
+    lgdm_batch_destroy(b);
+    return LGDM_ERR_DEVICE;
+  }
+  *out = b;
+  return LGDM_OK;
+}
+
+lgdm_status lgdm_batch_destroy(lgdm_batch* b) {
+  if (!b) return LGDM_ERR_INVALID_ARG;
+  (void)hipSetDevice(b->device);
+  for (auto& s : b->slots)
+    if (s.ctx || s.stream) release(b, s);
+  if (b->desc_host) (void)hipHostFree(b->desc_host);
+  if (b->desc_dev) (void)hipFree(b->desc_dev);
+  if (b->ev0) (void)hipEventDestroy(b->ev0);
+  if (b->ev1) (void)hipEventDestroy(b->ev1);
+  delete b;
+  return LGDM_OK;
+}
+
+const char* lgdm_batch_last_error(const lgdm_batch* b) { return b ? b->err.c_str() : "null batch"; }
+
+lgdm_status lgdm_batch_admit(lgdm_batch* b, const lgdm_request* r, int32_t* slot_out) {
+  if (!b || !r || !slot_out) return bfail(b, LGDM_ERR_INVALID_ARG, "NULL argument");
+  if (b->dim != 0 && r->dim != b->dim) {
+    // the slots may have emptied: the batch takes the element type of its next request
+    bool any = false;
+    for (auto& s : b->slots) any |= s.state != LGDM_SLOT_FREE;
+    if (any) return bfail(b, LGDM_ERR_INVALID_ARG, "all requests of a batch share one element type");
+  }
+  if (r->n_increments <= 0) return bfail(b, LGDM_ERR_INVALID_ARG, "n_increments must be positive");
+  int64_t est = 0;
+  if (lgdm_request_footprint(r->dim, r->n_nodes, r->n_elems, b->precision, &est) != LGDM_OK)
+    return bfail(b, LGDM_ERR_INVALID_ARG, "bad request sizes");
+  int free_slot = -1;
+  for (int i = 0; i < (int)b->slots.size(); ++i)
+    if (b->slots[i].state == LGDM_SLOT_FREE) {
+      free_slot = i;
+      break;
+    }
+  if (free_slot < 0) return bfail(b, LGDM_ERR_BUSY, "no free slot");
+  if (b->used + est > b->budget) return bfail(b, LGDM_ERR_BUSY, "HBM budget exhausted");
+  Slot& s = b->slots[free_slot];
+  BHIP(b, hipSetDevice(b->device), "set device");
+  BHIP(b, hipStreamCreate(&s.stream), "slot stream");
+  lgdm_status st = lgdm_create(&s.ctx, b->device, s.stream, b->precision);
+  if (st == LGDM_OK) st = lgdm_upload_mesh(s.ctx, r->dim, r->elem_type, r->n_nodes, r->coords, r->n_elems,
+                                           r->conn, r->e_scale);
+  if (st == LGDM_OK) st = lgdm_set_material(s.ctx, &r->material);
+  if (st == LGDM_OK) st = lgdm_set_dirichlet(s.ctx, r->n_bc, r->bc_dofs, r->bc_values);
+  if (st != LGDM_OK) {
+    std::string m = s.ctx ? s.ctx->err : std::string("context creation failed");
+    release(b, s);
+    return bfail(b, st, "admission: " + m);
+  }
+  int64_t fp = 0;
+  lgdm_footprint(s.ctx, &fp);
+  s.footprint = fp;
+  b->used += fp;
+  s.state = LGDM_SLOT_RUNNING;
+  s.n_increments = r->n_increments;
+  b->dim = r->dim;
+  *slot_out = free_slot;
+  return LGDM_OK;
+}
+
+lgdm_status lgdm_batch_tick(lgdm_batch* b, const lgdm_solver_opts* o, lgdm_tick_report* rep) {
+  if (!b) return LGDM_ERR_INVALID_ARG;
+  const auto t0 = std::chrono::steady_clock::now();
+  const lgdm_solver_opts op = opts_or_default(o);
+  lgdm_tick_report R{};
+  BHIP(b, hipSetDevice(b->device), "set device");
+  // 1. requests between increments start their next load step
+  std::vector<int> act;
+  for (int i = 0; i < (int)b->slots.size(); ++i) {
+    Slot& s = b->slots[i];
+    if (s.state != LGDM_SLOT_RUNNING) continue;
+    if (!s.in_increment) {
+      const double lam = (double)(s.ctx->increment + 1) / (double)s.n_increments;
+      lgdm_status st = lgdm_begin_increment(s.ctx, lam);
+      if (st != LGDM_OK) {
+        fail_slot(s, st);
+        continue;
+      }
+      s.in_increment = true;
+      s.newton = 0;
+    }
+    act.push_back(i);
+  }
+  for (int i : act) BHIP(b, hipStreamSynchronize(b->slots[i].stream), "slot sync");
+  R.running = (int)act.size();
+  if (act.empty()) {
+    if (rep) *rep = R;
+    return LGDM_OK;
+  }
+  // 2. one fused launch of each element kernel over every running request
+  int64_t gpb = 0, nodeb = 0;
+  for (size_t j = 0; j < act.size(); ++j) {
+    lgdm_ctx* c = b->slots[act[j]].ctx;
+    SlotDesc& d = b->desc_host[j];
+    d.gp = gp_args(c);
+    d.node = node_args(c);
+    d.mp = make_params(c->mat, c->dim);
+    d.gp_block0 = gpb;
+    d.node_block0 = nodeb;
+    gpb += gp_kernel_blocks(c);
+    nodeb += node_kernel_blocks(c);
+    R.gauss_points += c->ngauss;
+  }
+  BHIP(b, hipMemcpyAsync(b->desc_dev, b->desc_host, act.size() * sizeof(SlotDesc), hipMemcpyHostToDevice,
+                         b->stream), "slot table");
+  BHIP(b, hipEventRecord(b->ev0, b->stream), "event");
+  BHIP(b, launch_fused_assembly(b->stream, b->dim, b->precision == LGDM_MIXED, b->desc_dev, (int)act.size(),
+                                gpb, nodeb), "fused assembly");
+  BHIP(b, hipEventRecord(b->ev1, b->stream), "event");
+  for (int i : act) {
+    lgdm_ctx* c = b->slots[i].ctx;
+    BHIP(b, launch_norm_reduce_on(c, b->stream), "norms");
+    BHIP(b, hipMemcpyAsync(c->norms_host, c->norms_dev, NORM_SLOTS * sizeof(double), hipMemcpyDeviceToHost,
+                           b->stream), "norms");
+  }
+  BHIP(b, hipStreamSynchronize(b->stream), "fused assembly");
+  float ms = 0.f;
+  BHIP(b, hipEventElapsedTime(&ms, b->ev0, b->ev1), "event time");
+  R.t_assembly_ms = ms;
+  // 3. per-request decisions: commit, fail, or solve
+  for (int i : act) {
+    Slot& s = b->slots[i];
+    lgdm_ctx* c = s.ctx;
+    std::memcpy(c->last_norms, c->norms_host, sizeof(c->last_norms));
+    c->assembled = true;
+    s.assemblies_total++;
+    if (c->last_norms[5] != 0.0 || !std::isfinite(c->last_norms[0]) || !std::isfinite(c->last_norms[1])) {
+      fail_slot(s, LGDM_ERR_NAN);
+      continue;
+    }
+    if (converged(c, op.tol_newton)) {
+      BHIP(b, launch_max_reduce(c, c->D_t, c->ngauss, c->norms_dev + 12), "max damage");
+      BHIP(b, hipMemcpyAsync(c->norms_host + 12, c->norms_dev + 12, sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream), "max damage");
+      lgdm_status st = lgdm_commit_increment(c);   // synchronises the slot stream
+      if (st != LGDM_OK) {
+        fail_slot(s, st);
+        continue;
+      }
+      s.max_damage = c->norms_host[12];
+      s.in_increment = false;
+      R.committed++;
+      if (c->increment >= s.n_increments) {
+        s.state = LGDM_SLOT_FINISHED;
+        R.finished++;
+      }
+      continue;
+    }
+    if (s.newton >= op.max_newton) {
+      fail_slot(s, LGDM_ERR_NOT_CONVERGED);
+      continue;
+    }
+    BHIP(b, krylov_setup(c), "block-Jacobi setup");
+    s.run = make_krylov_run(c, c->R, c->delta, op);
+    BHIP(b, s.run->start(), "Krylov start");
+    s.solving = true;
+    R.solves++;
+  }
+  // 4. interleave the solves: each slot's iterations go to its own stream
+  bool pending = true;
+  while (pending) {
+    pending = false;
+    for (int i : act) {
+      Slot& s = b->slots[i];
+      if (!s.solving || !s.run) continue;
+      BHIP(b, s.run->check(), "Krylov check");
+      if (s.run->finished()) continue;
+      pending = true;
+      if (!s.run->needs_check()) BHIP(b, s.run->launch(), "Krylov iterations");
+    }
+  }
+  // 5. Newton update of the solved requests
+  for (int i : act) {
+    Slot& s = b->slots[i];
+    if (!s.solving) continue;
+    s.kres = s.run->result();
+    s.run.reset();
+    s.solving = false;
+    R.krylov_iters += s.kres.iters;
+    s.krylov_total += s.kres.iters;
+    if (s.kres.status == LGDM_ERR_NAN) {
+      fail_slot(s, LGDM_ERR_NAN);
+      continue;
+    }
+    BHIP(b, launch_axpy(s.ctx, s.ctx->x, s.ctx->delta, 1.0, s.ctx->ndof), "update");
+    s.newton++;
+    s.newton_total++;
+  }
+  for (int i : act)
+    if (b->slots[i].stream) BHIP(b, hipStreamSynchronize(b->slots[i].stream), "slot sync");
+  R.t_tick_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (rep) *rep = R;
+  return LGDM_OK;
+}
+
+lgdm_status lgdm_batch_slot_info(lgdm_batch* b, int32_t slot, lgdm_slot_info* info) {
+  if (!b || !info || slot < 0 || slot >= (int)b->slots.size()) return bfail(b, LGDM_ERR_INVALID_ARG, "slot");
+  const Slot& s = b->slots[slot];
+  lgdm_slot_info I{};
+  I.state = s.state;
+  I.newton_in_increment = s.newton;
+  I.increment = s.ctx ? s.ctx->increment : 0;
+  I.n_increments = s.n_increments;
+  I.newton_total = s.newton_total;
+  I.krylov_total = s.krylov_total;
+  I.assemblies_total = s.assemblies_total;
+  I.n_gauss = s.ctx ? s.ctx->ngauss : 0;
+  I.ndof = s.ctx ? s.ctx->ndof : 0;
+  I.footprint_bytes = s.footprint;
+  I.max_damage = s.max_damage;
+  I.last_status = s.last_status;
+  *info = I;
+  return LGDM_OK;
+}
+
+lgdm_status lgdm_batch_query(lgdm_batch* b, int32_t slot, int32_t field, double* out, int64_t n) {
+  if (!b || slot < 0 || slot >= (int)b->slots.size()) return bfail(b, LGDM_ERR_INVALID_ARG, "slot");
+  Slot& s = b->slots[slot];
+  if (!s.ctx) return bfail(b, LGDM_ERR_STATE, "empty slot");
+  lgdm_status st = lgdm_query_state(s.ctx, field, out, n);
+  if (st != LGDM_OK) b->err = s.ctx->err;
+  return st;
+}
+
+lgdm_status lgdm_batch_retire(lgdm_batch* b, int32_t slot) {
+  if (!b || slot < 0 || slot >= (int)b->slots.size()) return bfail(b, LGDM_ERR_INVALID_ARG, "slot");
+  Slot& s = b->slots[slot];
+  if (s.state == LGDM_SLOT_FREE) return bfail(b, LGDM_ERR_STATE, "slot is free");
+  if (s.state == LGDM_SLOT_RUNNING) return bfail(b, LGDM_ERR_STATE, "request still running");
+  release(b, s);
+  return LGDM_OK;
+}
+
+lgdm_status lgdm_batch_usage(lgdm_batch* b, int64_t* used, int64_t* budget, int32_t* occupied) {
+  if (!b) return LGDM_ERR_INVALID_ARG;
+  if (used) *used = b->used;
+  if (budget) *budget = b->budget;
+  if (occupied) {
+    int n = 0;
+    for (auto& s : b->slots) n += s.state != LGDM_SLOT_FREE;
+    *occupied = n;
+  }
+  return LGDM_OK;
+}
+
+}  // extern "C"

@@ -71,7 +71,7 @@ void free_mesh(lgdm_ctx* c) {
   c->pos = nullptr; c->row_ptr = c->col_idx = nullptr;
   c->dof_flags = nullptr; c->bc_dofs = nullptr; c->bc_vals = nullptr; c->nbc = 0;
   c->x = c->x_save = c->kappa_n = c->D_n = c->kappa_t = c->D_t = nullptr;
-  c->rec = c->vals = c->R = c->partials = c->norms_dev = nullptr;
+  c->rec = c->vals = c->R = c->partials = c->norms_dev = c->red2 = nullptr;
   c->vals32 = nullptr;
   c->kv = nullptr; c->minv = nullptr; c->minv32 = nullptr;
   c->kpart = nullptr; c->kscal = nullptr; c->kcount = nullptr; c->delta = nullptr;
@@ -284,6 +284,7 @@ lgdm_status lgdm_upload_mesh(lgdm_ctx* c, int32_t dim, int32_t elem_type, int64_
   c->n_partials = node_kernel_blocks(c);
   c->partials = (double*)dalloc(c, c->n_partials * NORM_SLOTS * sizeof(double));
   c->norms_dev = (double*)dalloc(c, 16 * sizeof(double));
+  c->red2 = (double*)dalloc(c, RED_CHUNKS * NORM_SLOTS * sizeof(double));
   c->dof_flags = (uint8_t*)dalloc(c, nd);
   c->kv = (double*)dalloc(c, 9 * nd * sizeof(double));  // 8 Krylov vectors + best iterate
   if (mixed) c->minv32 = (float*)dalloc(c, n_nodes * c->nd * c->nd * sizeof(float));
@@ -293,7 +294,7 @@ lgdm_status lgdm_upload_mesh(lgdm_ctx* c, int32_t dim, int32_t elem_type, int64_
   c->kscal = (double*)dalloc(c, 64 * sizeof(double));
   c->kcount = (unsigned*)dalloc(c, 16 * sizeof(unsigned));
   if (!c->x || !c->x_save || !c->R || !c->delta || !c->kappa_n || !c->D_n || !c->kappa_t || !c->D_t ||
-      !c->rec || (!c->vals && !c->vals32) || !c->partials || !c->norms_dev || !c->dof_flags ||
+      !c->rec || (!c->vals && !c->vals32) || !c->partials || !c->norms_dev || !c->red2 || !c->dof_flags ||
       !c->kv || (!c->minv && !c->minv32) || !c->kpart || !c->kscal || !c->kcount) {
     free_mesh(c);
     return fail(c, LGDM_ERR_OOM, "device allocation failed (state / matrix / solver)");

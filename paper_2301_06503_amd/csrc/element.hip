@@ -83,18 +83,18 @@ template <int DIM> __device__ __forceinline__ constexpr int sym_idx(int i, int j
 // Kernel 1: Gauss-point state and record
 // ---------------------------------------------------------------------------
 template <int DIM>
-__global__ void __launch_bounds__(256) gp_kernel(int64_t ngauss, const double* __restrict__ coords,
-                                                 const int32_t* __restrict__ conn,
-                                                 const double* __restrict__ e_scale,
-                                                 const double* __restrict__ x,
-                                                 const double* __restrict__ kappa_n, MatParams mp,
-                                                 double* __restrict__ rec,
-                                                 double* __restrict__ kappa_t,
-                                                 double* __restrict__ D_t) {
+__device__ __forceinline__ void gp_point(int64_t gid, const GpArgs& A, const MatParams& mp) {
   using E = Elem<DIM>;
   using RC = Rec<DIM>;
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= ngauss) return;
+  if (gid >= A.ngauss) return;
+  const double* __restrict__ coords = A.coords;
+  const int32_t* __restrict__ conn = A.conn;
+  const double* __restrict__ e_scale = A.e_scale;
+  const double* __restrict__ x = A.x;
+  const double* __restrict__ kappa_n = A.kappa_n;
+  double* __restrict__ rec = A.rec;
+  double* __restrict__ kappa_t = A.kappa_t;
+  double* __restrict__ D_t = A.D_t;
   const int64_t e = gid / E::NGP;
   const int g = (int)(gid - e * E::NGP);
 
@@ -297,6 +297,31 @@ __global__ void __launch_bounds__(256) gp_kernel(int64_t ngauss, const double* _
   D_t[gid] = D;
 }
 
+template <int DIM>
+__global__ void __launch_bounds__(256) gp_kernel(GpArgs A, MatParams mp) {
+  gp_point<DIM>((int64_t)blockIdx.x * blockDim.x + threadIdx.x, A, mp);
+}
+
+// slot of workgroup b in a fused launch (slot ranges ascending by first block)
+__device__ __forceinline__ int find_slot(const SlotDesc* __restrict__ slots, int nslots, int64_t b,
+                                         bool node) {
+  int lo = 0, hi = nslots - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int64_t b0 = node ? slots[mid].node_block0 : slots[mid].gp_block0;
+    if (b0 <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int DIM>
+__global__ void __launch_bounds__(256) gp_fused_kernel(const SlotDesc* __restrict__ slots, int nslots) {
+  const int s = find_slot(slots, nslots, blockIdx.x, false);
+  const int64_t lb = (int64_t)blockIdx.x - slots[s].gp_block0;
+  gp_point<DIM>(lb * blockDim.x + threadIdx.x, slots[s].gp, slots[s].mp);
+}
+
 // ---------------------------------------------------------------------------
 // per-Gauss-point pieces of the node-row assembly
 // ---------------------------------------------------------------------------
@@ -415,12 +440,19 @@ template <int DIM, typename T> struct NodeLds {
 };
 
 template <int DIM, typename T, bool WANT_K>
-__global__ void __launch_bounds__(NODE_BLOCK) node_kernel(
-    int64_t n_nodes, const int32_t* __restrict__ n2e_ptr, const int32_t* __restrict__ n2e,
-    const int32_t* __restrict__ nbr_ptr, const int32_t* __restrict__ nbr,
-    const uint8_t* __restrict__ pos, const int32_t* __restrict__ row_ptr,
-    const uint8_t* __restrict__ flags, const double* __restrict__ rec, MatParams mp,
-    T* __restrict__ vals, double* __restrict__ R, double* __restrict__ partials) {
+__device__ __forceinline__ void node_block(int64_t blk, const NodeArgs& A, const MatParams& mp) {
+  const int64_t n_nodes = A.n_nodes;
+  const int32_t* __restrict__ n2e_ptr = A.n2e_ptr;
+  const int32_t* __restrict__ n2e = A.n2e;
+  const int32_t* __restrict__ nbr_ptr = A.nbr_ptr;
+  const int32_t* __restrict__ nbr = A.nbr;
+  const uint8_t* __restrict__ pos = A.pos;
+  const int32_t* __restrict__ row_ptr = A.row_ptr;
+  const uint8_t* __restrict__ flags = A.flags;
+  const double* __restrict__ rec = A.rec;
+  T* __restrict__ vals = static_cast<T*>(A.vals);
+  double* __restrict__ R = A.R;
+  double* __restrict__ partials = A.partials;
   using E = Elem<DIM>;
   using RC = Rec<DIM>;
   using LD = NodeLds<DIM, T>;
@@ -441,7 +473,7 @@ __global__ void __launch_bounds__(NODE_BLOCK) node_kernel(
   const int slot = tid / L;                    // node within the workgroup
   const int l = tid % L;
   const int k = l / NEN, b = l % NEN;
-  const int64_t a = (int64_t)blockIdx.x * NPB + slot;
+  const int64_t a = blk * NPB + slot;
   const bool valid = a < n_nodes;
   int e0 = 0, ne = 0, nnb = 0, nb0 = 0;
   if (valid) {
@@ -588,18 +620,33 @@ __global__ void __launch_bounds__(NODE_BLOCK) node_kernel(
   if (tid < NORM_SLOTS) {
     double sum = 0.0;
     for (int i = 0; i < NPB; ++i) sum += s_red[tid][i];
-    partials[(int64_t)blockIdx.x * NORM_SLOTS + tid] = sum;
+    partials[blk * NORM_SLOTS + tid] = sum;
   }
 }
 
-// fixed-order sum of the per-workgroup partials
-__global__ void __launch_bounds__(256) norm_reduce_kernel(int64_t nblk,
+template <int DIM, typename T, bool WANT_K>
+__global__ void __launch_bounds__(NODE_BLOCK) node_kernel(NodeArgs A, MatParams mp) {
+  node_block<DIM, T, WANT_K>(blockIdx.x, A, mp);
+}
+
+template <int DIM, typename T, bool WANT_K>
+__global__ void __launch_bounds__(NODE_BLOCK) node_fused_kernel(const SlotDesc* __restrict__ slots,
+                                                                int nslots) {
+  const int s = find_slot(slots, nslots, blockIdx.x, true);
+  node_block<DIM, T, WANT_K>((int64_t)blockIdx.x - slots[s].node_block0, slots[s].node, slots[s].mp);
+}
+
+// fixed-order two-stage sums: stage one sums contiguous chunks of the
+// per-workgroup partials, stage two (one workgroup) sums the chunk totals
+__global__ void __launch_bounds__(256) norm_reduce_kernel(int64_t nblk, int64_t chunk,
                                                           const double* __restrict__ partials,
                                                           double* __restrict__ out) {
   __shared__ double s[NORM_SLOTS][256];
   const int t = threadIdx.x;
+  const int64_t lo = (int64_t)blockIdx.x * chunk;
+  const int64_t hi = lo + chunk < nblk ? lo + chunk : nblk;
   double acc[NORM_SLOTS] = {0, 0, 0, 0, 0, 0};
-  for (int64_t i = t; i < nblk; i += 256)
+  for (int64_t i = lo + t; i < hi; i += 256)
 #pragma unroll
     for (int q = 0; q < NORM_SLOTS; ++q) acc[q] += partials[i * NORM_SLOTS + q];
 #pragma unroll
@@ -611,7 +658,7 @@ __global__ void __launch_bounds__(256) norm_reduce_kernel(int64_t nblk,
       for (int q = 0; q < NORM_SLOTS; ++q) s[q][t] += s[q][t + w];
     __syncthreads();
   }
-  if (t < NORM_SLOTS) out[t] = s[t][0];
+  if (t < NORM_SLOTS) out[(int64_t)blockIdx.x * NORM_SLOTS + t] = s[t][0];
 }
 
 __global__ void set_dirichlet_kernel(int64_t n, const int32_t* __restrict__ dofs,
@@ -672,18 +719,21 @@ __global__ void element_blocks_kernel(int64_t e0, int64_t e1, const double* __re
   }
 }
 
-__global__ void __launch_bounds__(256) max_reduce_kernel(int64_t n, const double* __restrict__ v,
+__global__ void __launch_bounds__(256) max_reduce_kernel(int64_t n, int64_t chunk,
+                                                         const double* __restrict__ v,
                                                          double* __restrict__ out) {
   __shared__ double s[256];
+  const int64_t lo = (int64_t)blockIdx.x * chunk;
+  const int64_t hi = lo + chunk < n ? lo + chunk : n;
   double m = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 256) m = fmax(m, v[i]);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) m = fmax(m, v[i]);
   s[threadIdx.x] = m;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + w]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) *out = s[0];
+  if (threadIdx.x == 0) out[blockIdx.x] = s[0];
 }
 
 template <int DIM> int node_lanes() { return Elem<DIM>::NEN * Elem<DIM>::NEN; }
@@ -727,62 +777,93 @@ int64_t node_kernel_blocks(const lgdm_ctx* c) {
   return (c->n_nodes + npb - 1) / npb;
 }
 
+GpArgs gp_args(const lgdm_ctx* c) {
+  return GpArgs{c->ngauss, c->coords, c->conn, c->e_scale, c->x, c->kappa_n, c->rec, c->kappa_t, c->D_t};
+}
+
+NodeArgs node_args(const lgdm_ctx* c) {
+  void* vals = c->precision == LGDM_MIXED ? (void*)c->vals32 : (void*)c->vals;
+  return NodeArgs{c->n_nodes, c->n2e_ptr, c->n2e, c->nbr_ptr, c->nbr, c->pos, c->row_ptr, c->dof_flags,
+                  c->rec, vals, c->R, c->partials};
+}
+
+int64_t gp_kernel_blocks(const lgdm_ctx* c) { return (c->ngauss + 255) / 256; }
+
 hipError_t launch_gp_kernel(lgdm_ctx* c, const MatParams& mp) {
-  const int bs = 256;
-  const int64_t grid = (c->ngauss + bs - 1) / bs;
+  const int64_t grid = gp_kernel_blocks(c);
   if (grid == 0) return hipSuccess;
+  const GpArgs A = gp_args(c);
   switch (c->dim) {
-    case 1:
-      gp_kernel<1><<<grid, bs, 0, c->stream>>>(c->ngauss, c->coords, c->conn, c->e_scale, c->x,
-                                               c->kappa_n, mp, c->rec, c->kappa_t, c->D_t);
-      break;
-    case 2:
-      gp_kernel<2><<<grid, bs, 0, c->stream>>>(c->ngauss, c->coords, c->conn, c->e_scale, c->x,
-                                               c->kappa_n, mp, c->rec, c->kappa_t, c->D_t);
-      break;
-    default:
-      gp_kernel<3><<<grid, bs, 0, c->stream>>>(c->ngauss, c->coords, c->conn, c->e_scale, c->x,
-                                               c->kappa_n, mp, c->rec, c->kappa_t, c->D_t);
+    case 1: gp_kernel<1><<<grid, 256, 0, c->stream>>>(A, mp); break;
+    case 2: gp_kernel<2><<<grid, 256, 0, c->stream>>>(A, mp); break;
+    default: gp_kernel<3><<<grid, 256, 0, c->stream>>>(A, mp);
   }
   return hipGetLastError();
 }
 
 template <int DIM, typename T>
-static void node_launch(lgdm_ctx* c, const MatParams& mp, bool want_k, T* vals) {
+static void node_launch(lgdm_ctx* c, const MatParams& mp, bool want_k) {
   const int64_t grid = node_kernel_blocks(c);
   if (grid == 0) return;
-  if (want_k)
-    node_kernel<DIM, T, true><<<grid, NODE_BLOCK, 0, c->stream>>>(
-        c->n_nodes, c->n2e_ptr, c->n2e, c->nbr_ptr, c->nbr, c->pos, c->row_ptr, c->dof_flags,
-        c->rec, mp, vals, c->R, c->partials);
-  else
-    node_kernel<DIM, T, false><<<grid, NODE_BLOCK, 0, c->stream>>>(
-        c->n_nodes, c->n2e_ptr, c->n2e, c->nbr_ptr, c->nbr, c->pos, c->row_ptr, c->dof_flags,
-        c->rec, mp, vals, c->R, c->partials);
+  const NodeArgs A = node_args(c);
+  if (want_k) node_kernel<DIM, T, true><<<grid, NODE_BLOCK, 0, c->stream>>>(A, mp);
+  else node_kernel<DIM, T, false><<<grid, NODE_BLOCK, 0, c->stream>>>(A, mp);
 }
 
 hipError_t launch_node_kernel(lgdm_ctx* c, const MatParams& mp, bool want_k) {
   const bool mixed = c->precision == LGDM_MIXED;
   switch (c->dim) {
     case 1:
-      if (mixed) node_launch<1, float>(c, mp, want_k, c->vals32);
-      else node_launch<1, double>(c, mp, want_k, c->vals);
+      if (mixed) node_launch<1, float>(c, mp, want_k);
+      else node_launch<1, double>(c, mp, want_k);
       break;
     case 2:
-      if (mixed) node_launch<2, float>(c, mp, want_k, c->vals32);
-      else node_launch<2, double>(c, mp, want_k, c->vals);
+      if (mixed) node_launch<2, float>(c, mp, want_k);
+      else node_launch<2, double>(c, mp, want_k);
       break;
     default:
-      if (mixed) node_launch<3, float>(c, mp, want_k, c->vals32);
-      else node_launch<3, double>(c, mp, want_k, c->vals);
+      if (mixed) node_launch<3, float>(c, mp, want_k);
+      else node_launch<3, double>(c, mp, want_k);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_norm_reduce(lgdm_ctx* c) {
-  norm_reduce_kernel<<<1, 256, 0, c->stream>>>(node_kernel_blocks(c), c->partials, c->norms_dev);
+// one fused launch of each element kernel over several problems of the same
+// dimension and precision (slots: device array, ascending block ranges)
+hipError_t launch_fused_assembly(hipStream_t st, int dim, bool mixed, const SlotDesc* slots_dev,
+                                 int nslots, int64_t gp_blocks, int64_t node_blocks) {
+  if (nslots == 0) return hipSuccess;
+  switch (dim) {
+    case 1: gp_fused_kernel<1><<<gp_blocks, 256, 0, st>>>(slots_dev, nslots); break;
+    case 2: gp_fused_kernel<2><<<gp_blocks, 256, 0, st>>>(slots_dev, nslots); break;
+    default: gp_fused_kernel<3><<<gp_blocks, 256, 0, st>>>(slots_dev, nslots);
+  }
+  switch (dim) {
+    case 1:
+      if (mixed) node_fused_kernel<1, float, true><<<node_blocks, NODE_BLOCK, 0, st>>>(slots_dev, nslots);
+      else node_fused_kernel<1, double, true><<<node_blocks, NODE_BLOCK, 0, st>>>(slots_dev, nslots);
+      break;
+    case 2:
+      if (mixed) node_fused_kernel<2, float, true><<<node_blocks, NODE_BLOCK, 0, st>>>(slots_dev, nslots);
+      else node_fused_kernel<2, double, true><<<node_blocks, NODE_BLOCK, 0, st>>>(slots_dev, nslots);
+      break;
+    default:
+      if (mixed) node_fused_kernel<3, float, true><<<node_blocks, NODE_BLOCK, 0, st>>>(slots_dev, nslots);
+      else node_fused_kernel<3, double, true><<<node_blocks, NODE_BLOCK, 0, st>>>(slots_dev, nslots);
+  }
   return hipGetLastError();
 }
+
+hipError_t launch_norm_reduce_on(lgdm_ctx* c, hipStream_t st) {
+  const int64_t nblk = node_kernel_blocks(c);
+  const int64_t nb1 = nblk < RED_CHUNKS ? nblk : RED_CHUNKS;
+  const int64_t chunk = (nblk + nb1 - 1) / nb1;
+  norm_reduce_kernel<<<nb1, 256, 0, st>>>(nblk, chunk, c->partials, c->red2);
+  norm_reduce_kernel<<<1, 256, 0, st>>>(nb1, nb1, c->red2, c->norms_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_norm_reduce(lgdm_ctx* c) { return launch_norm_reduce_on(c, c->stream); }
 
 hipError_t launch_set_dirichlet(lgdm_ctx* c, double lambda) {
   if (c->nbc == 0) return hipSuccess;
@@ -812,7 +893,10 @@ hipError_t launch_element_blocks(lgdm_ctx* c, const MatParams& mp, int64_t e0, i
 }
 
 hipError_t launch_max_reduce(lgdm_ctx* c, const double* v, int64_t n, double* out_dev) {
-  max_reduce_kernel<<<1, 256, 0, c->stream>>>(n, v, out_dev);
+  const int64_t nb1 = (n + 255) / 256 < RED_CHUNKS ? (n + 255) / 256 : RED_CHUNKS;
+  const int64_t chunk = (n + nb1 - 1) / nb1;
+  max_reduce_kernel<<<nb1, 256, 0, c->stream>>>(n, chunk, v, c->red2);
+  max_reduce_kernel<<<1, 256, 0, c->stream>>>(nb1, nb1, c->red2, out_dev);
   return hipGetLastError();
 }
 

@@ -4,7 +4,9 @@
 //
 //  - SpMV uses the node graph for its column indices (one int per node pair
 //    instead of one per nonzero): row r of node a lists, for each neighbour
-//    q of a in ascending order, the nd columns q*nd .. q*nd + nd - 1.
+//    q of a in ascending order, the nd columns q*nd .. q*nd + nd - 1.  The nd
+//    rows of a node share their columns, so a lane group computes them
+//    together and gathers each x entry once.
 //  - Rows of the micro-equivalent-strain equation carry the coupling
 //    modulus h (about 1e-9 of the displacement rows); the solver works on
 //    S K with S = diag(1 on u rows, E/h on ebar rows) and S b.  Per-field
@@ -15,11 +17,14 @@
 //    device-scope fences, which write back L2 on every block of a
 //    multi-XCD part), so results are bitwise repeatable.  The host reads the
 //    scalars every `check_every` iterations.
-//  - FP64 contexts run everything in FP64.  Mixed contexts keep the matrix
-//    and the block-Jacobi inverses in FP32 (SpMV and preconditioner apply
-//    accumulate in FP32: the bytes that bound an iteration) while the Krylov
-//    vectors, recurrences, dot products and the solution stay FP64.
+//  - FP64 contexts run everything in FP64.  Mixed contexts store the matrix
+//    and the block-Jacobi inverses in FP32 (the bytes that bound an
+//    iteration) and apply them in FP64 arithmetic to FP64 Krylov vectors, so
+//    the inner operator is the fixed linear map of the FP32 matrix: an FP32
+//    accumulation would make it a noisy map whose rounding, once the Newton
+//    residual is smooth, exceeds K p and stalls the refinement.
 #include <cmath>
+#include <memory>
 #include <type_traits>
 
 #include "lgdm_internal.h"
@@ -47,9 +52,9 @@ constexpr double FLOOR_REL2 = 1e-30;
 // have comparable magnitudes, and a field whose right-hand side is far below
 // the other's cannot be resolved below the operator's rounding of the other
 constexpr double FIELD_FLOOR2 = 1e-6;
-// checks without a new best residual after which a solve has stagnated (the
-// FP32 operator of a mixed context bounds the attainable residual)
-constexpr int STALL_CHECKS = 12;
+// iterations without a new best residual after which a solve has stagnated
+// (the FP32 operator of a mixed context bounds the attainable residual)
+constexpr int STALL_ITERS = 500;
 
 struct Vecs {
   void* r;
@@ -93,10 +98,14 @@ __device__ __forceinline__ void write_partials(double (&v)[NQ], double* part, do
     for (int q = 0; q < NQ; ++q) part[blockIdx.x * NQ + q] = v[q];
 }
 
-// y = S A x (+ optional dots); G lanes per row, grid-stride over rows.
-// MODE 0: no dots; 1: dot(rh, y); 2: dot(y, s), dot(y, y)
-template <typename T, int ND, int G, int MODE>
-__global__ void __launch_bounds__(BS) spmv_kernel(int64_t nrows, const int32_t* __restrict__ row_ptr,
+// y = S A x (+ optional dots).  One group of G lanes per node a computes the
+// ND rows of the node together: lane v takes column v of the node's row block
+// (neighbour q = v / ND, component c = v % ND), gathers x once and multiplies
+// it into the ND rows (coalesced reads of each row), then the group reduces
+// its ND sums.  Grid-stride over nodes.
+// MODE 0: no dots; 1: dot(rh, y), |y|^2; 2: dot(y, s), |y|^2
+template <typename T, int ND, int G, int UNR, int MODE>
+__global__ void __launch_bounds__(BS) spmv_kernel(int64_t n_nodes, const int32_t* __restrict__ row_ptr,
                                                   const int32_t* __restrict__ nbr_ptr,
                                                   const int32_t* __restrict__ nbr,
                                                   const T* __restrict__ vals,
@@ -106,41 +115,54 @@ __global__ void __launch_bounds__(BS) spmv_kernel(int64_t nrows, const int32_t* 
                                                   double* __restrict__ part) {
   __shared__ double sm[2][BS];
   if (sc[K_DONE] != 0.0) return;
-  constexpr int UNR = 4;
   const double se = sc[K_SE];
   const int lane = threadIdx.x % G;
   const int64_t grp = ((int64_t)blockIdx.x * BS + threadIdx.x) / G;
   const int64_t ngrp = (int64_t)gridDim.x * BS / G;
   double d0 = 0.0, d1 = 0.0;
-  for (int64_t row = grp; row < nrows; row += ngrp) {
-    const int64_t a = row / ND;
-    const T* __restrict__ rv = vals + row_ptr[row];
+  for (int64_t a = grp; a < n_nodes; a += ngrp) {
     const int32_t p0 = nbr_ptr[a];
     const int len = (nbr_ptr[a + 1] - p0) * ND;
+    const T* __restrict__ rv = vals + row_ptr[a * ND];
     const int32_t* __restrict__ nb = nbr + p0;
-    T acc = (T)0;
-    // UNR independent loads in flight per lane
+    // stored values of type T (FP32 in mixed contexts), FP64 arithmetic:
+    // the operator is the fixed linear map of the stored matrix
+    double acc[ND];
+#pragma unroll
+    for (int r = 0; r < ND; ++r) acc[r] = 0.0;
     for (int v0 = lane; v0 < len; v0 += UNR * G) {
-      T pv[UNR], px[UNR];
+      double xv[UNR];
+      T mv[UNR][ND];
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
         const int v = v0 + u * G;
         if (v < len) {
           const int q = v / ND, c = v - q * ND;
-          pv[u] = rv[v];
-          px[u] = (T)x[(int64_t)nb[q] * ND + c];
+          xv[u] = x[(int64_t)nb[q] * ND + c];
+#pragma unroll
+          for (int r = 0; r < ND; ++r) mv[u][r] = rv[r * len + v];
         } else {
-          pv[u] = (T)0;
-          px[u] = (T)0;
+          xv[u] = 0.0;
+#pragma unroll
+          for (int r = 0; r < ND; ++r) mv[u][r] = (T)0;
         }
       }
 #pragma unroll
-      for (int u = 0; u < UNR; ++u) acc += pv[u] * px[u];
+      for (int u = 0; u < UNR; ++u)
+#pragma unroll
+        for (int r = 0; r < ND; ++r) acc[r] += (double)mv[u][r] * xv[u];
     }
 #pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
-    if (lane == 0) {
-      const double yt = (double)acc * row_scale(row, ND, se);
+    for (int o = G / 2; o > 0; o >>= 1)
+#pragma unroll
+      for (int r = 0; r < ND; ++r) acc[r] += __shfl_xor(acc[r], o, G);
+    if (lane < ND) {
+      double mine = acc[0];
+#pragma unroll
+      for (int r = 1; r < ND; ++r)
+        if (lane == r) mine = acc[r];
+      const int64_t row = a * ND + lane;
+      const double yt = mine * (lane == ND - 1 ? se : 1.0);
       y[row] = yt;
       if (MODE == 1) {
         d0 += w[row] * yt;
@@ -265,10 +287,10 @@ __global__ void __launch_bounds__(BS) pupdate_kernel(int64_t n_nodes, const T* _
     const T* m = minv + a * ND * ND;
 #pragma unroll
     for (int i = 0; i < ND; ++i) {
-      T s = 0;
+      double s = 0.0;
 #pragma unroll
-      for (int j = 0; j < ND; ++j) s += m[i * ND + j] * (T)pv[j];
-      ph[a * ND + i] = (double)s;
+      for (int j = 0; j < ND; ++j) s += (double)m[i * ND + j] * pv[j];
+      ph[a * ND + i] = s;
     }
   }
 }
@@ -292,10 +314,10 @@ __global__ void __launch_bounds__(BS) supdate_kernel(int64_t n_nodes, const T* _
     const T* m = minv + a * ND * ND;
 #pragma unroll
     for (int i = 0; i < ND; ++i) {
-      T acc = 0;
+      double acc = 0.0;
 #pragma unroll
-      for (int j = 0; j < ND; ++j) acc += m[i * ND + j] * (T)sv[j];
-      sh[a * ND + i] = (double)acc;
+      for (int j = 0; j < ND; ++j) acc += (double)m[i * ND + j] * sv[j];
+      sh[a * ND + i] = acc;
     }
   }
 }
@@ -409,14 +431,33 @@ __global__ void axpy_kernel(int64_t n, double* __restrict__ y, const double* __r
   if (i < n) y[i] += a * x[i];
 }
 
-__global__ void __launch_bounds__(256) field_norms_kernel(int64_t n, int nd, const double* __restrict__ v,
+// |v_u|^2, |v_e|^2 of contiguous chunks (stage one of a fixed-order sum)
+__global__ void __launch_bounds__(256) field_norms_kernel(int64_t n, int64_t chunk, int nd,
+                                                          const double* __restrict__ v,
                                                           double* __restrict__ out) {
   __shared__ double sm[2][BS];
+  const int64_t lo = (int64_t)blockIdx.x * chunk;
+  const int64_t hi = lo + chunk < n ? lo + chunk : n;
   double d[2] = {0.0, 0.0};
-  for (int64_t i = threadIdx.x; i < n; i += BS) {
+  for (int64_t i = lo + threadIdx.x; i < hi; i += BS) {
     const double x = v[i];
     if (i % nd == nd - 1) d[1] += x * x;
     else d[0] += x * x;
+  }
+  block_sum<2>(d, sm);
+  if (threadIdx.x == 0) {
+    out[blockIdx.x * 2] = d[0];
+    out[blockIdx.x * 2 + 1] = d[1];
+  }
+}
+
+__global__ void __launch_bounds__(256) pair_sum_kernel(int nblk, const double* __restrict__ in,
+                                                       double* __restrict__ out) {
+  __shared__ double sm[2][BS];
+  double d[2] = {0.0, 0.0};
+  for (int i = threadIdx.x; i < nblk; i += BS) {
+    d[0] += in[2 * i];
+    d[1] += in[2 * i + 1];
   }
   block_sum<2>(d, sm);
   if (threadIdx.x == 0) {
@@ -442,7 +483,13 @@ inline int64_t grid_for(int64_t work) {
 
 template <typename T, int ND>
 struct Solver {
-  static constexpr int G = ND == 4 ? 16 : (ND == 3 ? 8 : 4);
+  // lanes per node in the SpMV and unroll depth: row blocks hold up to
+  // 27 x 4 (hex8), 9 x 3 (quad4) and 3 x 2 (line2) columns, so G * UNR
+  // covers a hex8 row block in one unrolled pass (measured on the 3D beam:
+  // FP32 values favour a full wave per node, FP64 two nodes per wave)
+  static constexpr bool F32 = std::is_same<T, float>::value;
+  static constexpr int G = ND == 4 ? (F32 ? 64 : 32) : (ND == 3 ? 8 : 2);
+  static constexpr int UNR = ND == 4 ? (F32 ? 2 : 4) : 4;
   lgdm_ctx* c;
   const T* vals;
   const T* minv;
@@ -453,16 +500,16 @@ struct Solver {
   double* vec(void* p) { return static_cast<double*>(p); }
 
   void spmv(const double* x, double* y, int mode, const double* w) {
-    const int64_t g = grid_for(n * G);
+    const int64_t g = grid_for(nn * G);
     if (mode == 0) {
-      spmv_kernel<T, ND, G, 0><<<g, BS, 0, c->stream>>>(n, c->row_ptr, c->nbr_ptr, c->nbr, vals, x, y,
+      spmv_kernel<T, ND, G, UNR, 0><<<g, BS, 0, c->stream>>>(nn, c->row_ptr, c->nbr_ptr, c->nbr, vals, x, y,
                                                         w, sc, c->kpart);
     } else if (mode == 1) {
-      spmv_kernel<T, ND, G, 1><<<g, BS, 0, c->stream>>>(n, c->row_ptr, c->nbr_ptr, c->nbr, vals, x, y,
+      spmv_kernel<T, ND, G, UNR, 1><<<g, BS, 0, c->stream>>>(nn, c->row_ptr, c->nbr_ptr, c->nbr, vals, x, y,
                                                         w, sc, c->kpart);
       scalar_kernel<1, 2><<<1, BS, 0, c->stream>>>((int)g, c->kpart, sc);
     } else {
-      spmv_kernel<T, ND, G, 2><<<g, BS, 0, c->stream>>>(n, c->row_ptr, c->nbr_ptr, c->nbr, vals, x, y,
+      spmv_kernel<T, ND, G, UNR, 2><<<g, BS, 0, c->stream>>>(nn, c->row_ptr, c->nbr_ptr, c->nbr, vals, x, y,
                                                         w, sc, c->kpart);
       scalar_kernel<2, 2><<<1, BS, 0, c->stream>>>((int)g, c->kpart, sc);
     }
@@ -488,90 +535,133 @@ struct Solver {
   }
 };
 
+// One linear solve as a state machine: start() enqueues the initial
+// residual, then alternately check() (reads the device scalars; decides
+// convergence, restart, stagnation) and launch() (enqueues check_every
+// iterations) until finished().  Several runs on different streams can be
+// interleaved by the host so their kernels overlap on the device.
 template <typename T, int ND>
-hipError_t solve_impl(lgdm_ctx* c, const double* b, double* xout, const lgdm_solver_opts& o,
-                      KrylovResult& res) {
+struct KrylovRunImpl final : KrylovRun {
   Solver<T, ND> S;
-  S.c = c;
-  S.n = c->ndof;
-  S.nn = c->n_nodes;
-  const bool mixed = std::is_same<T, float>::value;
-  S.vals = mixed ? (const T*)c->vals32 : (const T*)c->vals;
-  S.minv = mixed ? (const T*)c->minv32 : (const T*)c->minv;
-  double* base = c->kv;
-  void** vp[8] = {&S.V.r, &S.V.rh, &S.V.p, &S.V.v, &S.V.s, &S.V.t, &S.V.ph, &S.V.sh};
-  for (int i = 0; i < 8; ++i) *vp[i] = base + (int64_t)i * c->ndof;
-  S.sc = c->kscal;
-  hipError_t e;
-  double tol = o.tol_krylov;
-  if (mixed && tol < 1e-6) tol = 1e-6;  // FP32 operator; Newton refines on the FP64 residual
-  const double se = c->mat.E / c->mat.h;
-  set_scalars_kernel<<<1, 64, 0, c->stream>>>(S.sc, tol * tol, se, break_rel<T>());
-  if ((e = hipMemsetAsync(xout, 0, c->ndof * sizeof(double), c->stream)) != hipSuccess) return e;
-  S.init(b, false, nullptr);
-  res.iters = 0;
-  res.restarts = 0;
-  res.status = LGDM_ERR_NOT_CONVERGED;
-  const int every = o.check_every > 0 ? o.check_every : 16;
+  lgdm_ctx* c;
+  const double* b;
+  double* xout;
+  lgdm_solver_opts o;
+  KrylovResult res{};
+  double tol = 0, se = 0;
+  int every = 16;
   int64_t done_iters = 0;
   bool true_residual = true;   // the scalars describe b - A x computed directly
   int replacements = 0;
-  // best iterate so far (per-field relative residual); returned when the
-  // solve stagnates or a recurrence turns non-finite
-  double* xbest = c->kv + 8 * c->ndof;
+  double* xbest = nullptr;     // best iterate so far (per-field relative residual)
   double best = INFINITY;
   int stall = 0;
   bool have_best = false;
-  auto return_best = [&](int status) {
+  bool fin = false;
+
+  KrylovRunImpl(lgdm_ctx* ctx, const double* b_, double* x_, const lgdm_solver_opts& o_)
+      : c(ctx), b(b_), xout(x_), o(o_) {
+    S.c = c;
+    S.n = c->ndof;
+    S.nn = c->n_nodes;
+    const bool mixed = std::is_same<T, float>::value;
+    S.vals = mixed ? (const T*)c->vals32 : (const T*)c->vals;
+    S.minv = mixed ? (const T*)c->minv32 : (const T*)c->minv;
+    void** vp[8] = {&S.V.r, &S.V.rh, &S.V.p, &S.V.v, &S.V.s, &S.V.t, &S.V.ph, &S.V.sh};
+    for (int i = 0; i < 8; ++i) *vp[i] = c->kv + (int64_t)i * c->ndof;
+    S.sc = c->kscal;
+    xbest = c->kv + 8 * c->ndof;
+    tol = o.tol_krylov;
+    if (mixed && tol < 1e-8) tol = 1e-8;  // FP32 matrix; Newton refines on the FP64 residual
+    se = c->mat.E / c->mat.h;
+    every = o.check_every > 0 ? o.check_every : 16;
+    res.status = LGDM_ERR_NOT_CONVERGED;
+  }
+
+  void return_best(int status) {
     if (have_best)
       (void)hipMemcpyAsync(xout, xbest, c->ndof * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
     res.status = status;
-  };
+    fin = true;
+  }
+
   // restart the recurrences from the current iterate with its true residual
-  auto restart_from_x = [&]() {
+  void restart_from_x() {
     set_scalars_kernel<<<1, 64, 0, c->stream>>>(S.sc, tol * tol, se, break_rel<T>());
     S.spmv(xout, S.vec(S.V.t), 0, nullptr);
     S.init(b, true, S.vec(S.V.t));
-  };
-  while (true) {
-    if ((e = hipMemcpyAsync(c->kscal_host, S.sc, K_NSLOTS * sizeof(double), hipMemcpyDeviceToHost,
-                            c->stream)) != hipSuccess) return e;
-    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
+  }
+
+  hipError_t start() override {
+    set_scalars_kernel<<<1, 64, 0, c->stream>>>(S.sc, tol * tol, se, break_rel<T>());
+    hipError_t e = hipMemsetAsync(xout, 0, c->ndof * sizeof(double), c->stream);
+    if (e != hipSuccess) return e;
+    S.init(b, false, nullptr);
+    // read the scalars of the initial residual asynchronously
+    return hipMemcpyAsync(c->kscal_host, S.sc, K_NSLOTS * sizeof(double), hipMemcpyDeviceToHost,
+                          c->stream);
+  }
+
+  hipError_t launch() override {
+    if (fin) return hipSuccess;
+    for (int i = 0; i < every; ++i) S.iteration(xout);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return hipMemcpyAsync(c->kscal_host, S.sc, K_NSLOTS * sizeof(double), hipMemcpyDeviceToHost,
+                          c->stream);
+  }
+
+  // reads the scalars enqueued by the last start()/launch(); restart and
+  // replacement kernels are enqueued here and read at the next check
+  hipError_t check() override {
+    if (fin) return hipSuccess;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return e;
     const double* h = c->kscal_host;
     res.iters = done_iters + (int64_t)h[K_ITER];
     const double bu = h[K_BU] > 0 ? h[K_BU] : 1.0, be = h[K_BE] > 0 ? h[K_BE] : 1.0;
     res.rel_u = std::sqrt(h[K_RU] / bu);
     res.rel_e = std::sqrt(h[K_RE] / be);
     const int st = (int)h[K_STATUS];
+    pending_read = false;
     if (h[K_DONE] != 0.0) {
       if (st == KS_CONV) {
         // accept only a converged true residual; a converged recurrence
         // residual is first replaced by the true one (it can drift)
         if (true_residual || replacements >= 4) {
           res.status = LGDM_OK;
-          break;
+          fin = true;
+          return hipSuccess;
         }
         replacements++;
         done_iters = res.iters;
         restart_from_x();
         true_residual = true;
-        continue;
+        pending_read = true;
+        return hipMemcpyAsync(c->kscal_host, S.sc, K_NSLOTS * sizeof(double), hipMemcpyDeviceToHost,
+                              c->stream);
       }
       if (st == KS_NAN) {
         if (have_best) return_best(LGDM_ERR_NOT_CONVERGED);
-        else res.status = LGDM_ERR_NAN;
-        break;
+        else {
+          res.status = LGDM_ERR_NAN;
+          fin = true;
+        }
+        return hipSuccess;
       }
       // breakdown: restart from the current iterate with the true residual
       if (res.restarts >= o.max_restarts || res.iters >= o.max_krylov) {
         res.status = LGDM_ERR_BREAKDOWN;
-        break;
+        fin = true;
+        return hipSuccess;
       }
       res.restarts++;
       done_iters = res.iters;
       restart_from_x();
       true_residual = true;
-      continue;
+      pending_read = true;
+      return hipMemcpyAsync(c->kscal_host, S.sc, K_NSLOTS * sizeof(double), hipMemcpyDeviceToHost,
+                            c->stream);
     }
     true_residual = false;
     const double score = std::max(res.rel_u, res.rel_e);
@@ -579,20 +669,26 @@ hipError_t solve_impl(lgdm_ctx* c, const double* b, double* xout, const lgdm_sol
       best = score;
       stall = 0;
       have_best = true;
-      if ((e = hipMemcpyAsync(xbest, xout, c->ndof * sizeof(double), hipMemcpyDeviceToDevice,
-                              c->stream)) != hipSuccess) return e;
-    } else if (++stall >= STALL_CHECKS) {
+      e = hipMemcpyAsync(xbest, xout, c->ndof * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+      if (e != hipSuccess) return e;
+    } else if ((stall += every) >= STALL_ITERS) {
       return_best(LGDM_ERR_NOT_CONVERGED);
-      break;
+      return hipSuccess;
     }
-    if (res.iters >= o.max_krylov) {
-      return_best(LGDM_ERR_NOT_CONVERGED);
-      break;
-    }
-    for (int i = 0; i < every; ++i) S.iteration(xout);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (res.iters >= o.max_krylov) return_best(LGDM_ERR_NOT_CONVERGED);
+    return hipSuccess;
   }
-  return hipSuccess;
+
+  bool pending_read = false;   // a restart's scalars are in flight: check again before launching
+  bool needs_check() const override { return pending_read; }
+  bool finished() const override { return fin; }
+  const KrylovResult& result() const override { return res; }
+};
+
+template <typename T, int ND>
+std::unique_ptr<KrylovRun> make_run_impl(lgdm_ctx* c, const double* b, double* x,
+                                         const lgdm_solver_opts& o) {
+  return std::unique_ptr<KrylovRun>(new KrylovRunImpl<T, ND>(c, b, x, o));
 }
 
 template <typename T, int ND> hipError_t setup_impl(lgdm_ctx* c) {
@@ -617,14 +713,27 @@ hipError_t krylov_setup(lgdm_ctx* c) {
   }
 }
 
-hipError_t krylov_solve(lgdm_ctx* c, const double* b, double* xout, const lgdm_solver_opts& o,
-                        KrylovResult& res) {
+std::unique_ptr<KrylovRun> make_krylov_run(lgdm_ctx* c, const double* b, double* x,
+                                           const lgdm_solver_opts& o) {
   const bool mixed = c->precision == LGDM_MIXED;
   switch (c->nd) {
-    case 2: return mixed ? solve_impl<float, 2>(c, b, xout, o, res) : solve_impl<double, 2>(c, b, xout, o, res);
-    case 3: return mixed ? solve_impl<float, 3>(c, b, xout, o, res) : solve_impl<double, 3>(c, b, xout, o, res);
-    default: return mixed ? solve_impl<float, 4>(c, b, xout, o, res) : solve_impl<double, 4>(c, b, xout, o, res);
+    case 2: return mixed ? make_run_impl<float, 2>(c, b, x, o) : make_run_impl<double, 2>(c, b, x, o);
+    case 3: return mixed ? make_run_impl<float, 3>(c, b, x, o) : make_run_impl<double, 3>(c, b, x, o);
+    default: return mixed ? make_run_impl<float, 4>(c, b, x, o) : make_run_impl<double, 4>(c, b, x, o);
   }
+}
+
+hipError_t krylov_solve(lgdm_ctx* c, const double* b, double* xout, const lgdm_solver_opts& o,
+                        KrylovResult& res) {
+  std::unique_ptr<KrylovRun> run = make_krylov_run(c, b, xout, o);
+  hipError_t e = run->start();
+  while (e == hipSuccess) {
+    e = run->check();
+    if (e != hipSuccess || run->finished()) break;
+    if (!run->needs_check()) e = run->launch();
+  }
+  res = run->result();
+  return e;
 }
 
 template <typename T, int ND> hipError_t spmv_only_impl(lgdm_ctx* c, const double* x) {
@@ -657,7 +766,11 @@ hipError_t launch_axpy(lgdm_ctx* c, double* y, const double* x, double a, int64_
 }
 
 hipError_t launch_field_norms(lgdm_ctx* c, const double* v, double* out_dev) {
-  field_norms_kernel<<<1, BS, 0, c->stream>>>(c->ndof, c->nd, v, out_dev);
+  const int64_t n = c->ndof;
+  const int64_t nb1 = (n + BS - 1) / BS < RED_CHUNKS ? (n + BS - 1) / BS : RED_CHUNKS;
+  const int64_t chunk = (n + nb1 - 1) / nb1;
+  field_norms_kernel<<<nb1, BS, 0, c->stream>>>(n, chunk, c->nd, v, c->red2);
+  pair_sum_kernel<<<1, BS, 0, c->stream>>>((int)nb1, c->red2, out_dev);
   return hipGetLastError();
 }
 

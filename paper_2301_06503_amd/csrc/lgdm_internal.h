@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -45,7 +46,47 @@ template <int DIM> struct Rec {
   static_assert(USED <= STRIDE, "record stride");
 };
 
+// arguments of the Gauss-point kernel for one problem
+struct GpArgs {
+  int64_t ngauss;
+  const double* coords;
+  const int32_t* conn;
+  const double* e_scale;
+  const double* x;
+  const double* kappa_n;
+  double* rec;
+  double* kappa_t;
+  double* D_t;
+};
+
+// arguments of the node-row assembly kernel for one problem
+struct NodeArgs {
+  int64_t n_nodes;
+  const int32_t* n2e_ptr;
+  const int32_t* n2e;
+  const int32_t* nbr_ptr;
+  const int32_t* nbr;
+  const uint8_t* pos;
+  const int32_t* row_ptr;
+  const uint8_t* flags;
+  const double* rec;
+  void* vals;          // double* (FP64) or float* (mixed)
+  double* R;
+  double* partials;
+};
+
+// one problem of a fused multi-problem launch: its arguments and the first
+// workgroup of its range in the fused grids
+struct SlotDesc {
+  GpArgs gp;
+  NodeArgs node;
+  MatParams mp;
+  int64_t gp_block0;
+  int64_t node_block0;
+};
+
 constexpr int NORM_SLOTS = 6;  // |R_u|^2, |R_e|^2, |f_u|^2, |fref_e|^2, reaction, non-finite count
+constexpr int RED_CHUNKS = 1024;  // stage-one workgroups of the two-stage reductions
 
 }  // namespace lgdm
 
@@ -104,6 +145,7 @@ struct lgdm_ctx {
   double* partials = nullptr;
   int64_t n_partials = 0;
   double* norms_dev = nullptr;     // NORM_SLOTS
+  double* red2 = nullptr;          // stage-one totals of the two-stage reductions
   double* norms_host = nullptr;    // pinned
   double last_norms[lgdm::NORM_SLOTS] = {0, 0, 0, 0, 0, 0};
 
@@ -136,12 +178,18 @@ MatParams make_params(const lgdm_material& m, int dim);
 hipError_t launch_gp_kernel(lgdm_ctx* c, const MatParams& mp);
 hipError_t launch_node_kernel(lgdm_ctx* c, const MatParams& mp, bool want_k);
 hipError_t launch_norm_reduce(lgdm_ctx* c);
+hipError_t launch_norm_reduce_on(lgdm_ctx* c, hipStream_t st);
 hipError_t launch_set_dirichlet(lgdm_ctx* c, double lambda);
 hipError_t launch_damage_from_kappa(lgdm_ctx* c, const MatParams& mp);
 hipError_t launch_element_blocks(lgdm_ctx* c, const MatParams& mp, int64_t e0, int64_t e1,
                                  double* Ke, double* fe);
 hipError_t launch_max_reduce(lgdm_ctx* c, const double* v, int64_t n, double* out_dev);
 int64_t node_kernel_blocks(const lgdm_ctx* c);
+int64_t gp_kernel_blocks(const lgdm_ctx* c);
+GpArgs gp_args(const lgdm_ctx* c);
+NodeArgs node_args(const lgdm_ctx* c);
+hipError_t launch_fused_assembly(hipStream_t st, int dim, bool mixed, const SlotDesc* slots_dev,
+                                 int nslots, int64_t gp_blocks, int64_t node_blocks);
 
 // H6 (krylov.hip)
 struct KrylovResult {
@@ -150,6 +198,18 @@ struct KrylovResult {
   int restarts;
   double rel_u, rel_e;
 };
+// one linear solve as a state machine (see krylov.hip)
+struct KrylovRun {
+  virtual ~KrylovRun() = default;
+  virtual hipError_t start() = 0;
+  virtual hipError_t launch() = 0;
+  virtual hipError_t check() = 0;
+  virtual bool needs_check() const = 0;
+  virtual bool finished() const = 0;
+  virtual const KrylovResult& result() const = 0;
+};
+std::unique_ptr<KrylovRun> make_krylov_run(lgdm_ctx* c, const double* b, double* x,
+                                           const lgdm_solver_opts& o);
 hipError_t krylov_setup(lgdm_ctx* c);  // block-Jacobi from the assembled matrix
 hipError_t krylov_solve(lgdm_ctx* c, const double* b, double* xout, const lgdm_solver_opts& o,
                         KrylovResult& res);

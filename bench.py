@@ -1,18 +1,20 @@
 #!/usr/bin/env python
 """Benchmark of the LGDM hot path on one MI355X.
 
-A step is one Newton iteration of Algorithm 2 along the load path of the
-workload: compute and assemble K and F (Gauss-point kernel + node-row
-assembly kernel), the per-field residual test, the linear solve (BiCGSTAB +
-block-Jacobi) and the update of the primary fields; converged increments
-are committed (Eq. A.2) and the next increment begins, inside the timed
-region.  Inputs are resident in HBM before timing starts.
+A step is one load increment of Algorithm 2 along the load path of the
+workload: Newton iterations (compute and assemble K and F with the
+Gauss-point and node-row assembly kernels, the per-field residual test, the
+linear solve with block-Jacobi-preconditioned IDR(s) or BiCGSTAB, the update
+of the primary fields) until ||R||/||F|| < 1e-8 per field, then the commit of
+the history variable (Eq. A.2).  Inputs are resident in HBM before timing
+starts.
 
-Metric: assembled Gauss points per second (nGP x assemblies / device time
-of the assembly kernels, HIP events on the library's stream) and Newton-step
-ms, in the FP32-mixed precision the workload names, with the plain FP64 path
-run beside it on the same GPU; Newton converges to ||R||/||F|| < 1e-8 per
-field.
+Metric: Gauss points assembled per second of wall time over the timed
+increments (whole job, solves included) and the Newton-step ms, in the
+FP32-mixed precision the workload names, with the plain FP64 path run
+beside it on the same GPU.  Kernel rates (assembly Gauss points per second
+of assembly-kernel time, SpMV and assembly GB/s against the HBM roofline)
+are measured with HIP events on the library's stream.
 
 Prints one JSON line.
 """
@@ -44,67 +46,82 @@ def log(*a):
 
 
 class PathRunner:
-    """Drives Newton iterations along the load path through the C ABI."""
+    """Drives the load path through the C ABI, one converged increment per
+    step: Newton iterations (assembly, residual test, linear solve, update)
+    until ||R||/||F|| < tol per field, then the history commit."""
 
     def __init__(self, ctx, prob, opts, binding):
         self.ctx, self.prob, self.opts, self.b = ctx, prob, opts, binding
         self.inc = 0                  # committed increments
-        self.in_inc = False
-        self.rep = None
-        self.newton_in_inc = 0
         self.verbose = True
 
     def step(self, acc):
-        """Run until one linear solve has happened (one Newton iteration);
-        accumulate the device-time split in acc."""
+        lam = (self.inc + 1) / self.prob.n_increments
+        self.ctx.begin_increment(lam)
+        rep = self.b.IncrementReport()
+        it = 0
         while True:
-            if not self.in_inc:
-                lam = (self.inc + 1) / self.prob.n_increments
-                self.ctx.begin_increment(lam)
-                self.in_inc = True
-                self.rep = self.b.IncrementReport()
-                self.newton_in_inc = 0
-            before = (self.rep.t_assembly_ms, self.rep.t_solve_ms, self.rep.t_update_ms,
-                      self.rep.n_assemblies, self.rep.krylov_iters)
-            conv, r = self.ctx.newton_iteration(self.opts, self.rep)
+            before = (rep.t_assembly_ms, rep.t_solve_ms, rep.t_update_ms, rep.n_assemblies,
+                      rep.krylov_iters, rep.krylov_spmv)
+            conv, r = self.ctx.newton_iteration(self.opts, rep)
             if self.verbose:
-                log("  inc %d it %d |R_u|/|F_u|=%.3e |R_e|/|F_e|=%.3e krylov=%d restarts=%d "
+                log("  inc %d it %d |R_u|/|F_u|=%.3e |R_e|/|F_e|=%.3e krylov=%d spmv=%d restarts=%d "
                     "asm=%.3fms solve=%.1fms" % (
-                        self.inc + 1, self.newton_in_inc, r.res_u / max(r.ref_u, 1e-300),
-                        r.res_e / max(r.ref_e, 1e-300), r.krylov_iters - before[4], r.restarts,
+                        self.inc + 1, it, r.res_u / max(r.ref_u, 1e-300), r.res_e / max(r.ref_e, 1e-300),
+                        r.krylov_iters - before[4], r.krylov_spmv - before[5], r.restarts,
                         r.t_assembly_ms - before[0], r.t_solve_ms - before[1]))
             acc["t_asm"] += r.t_assembly_ms - before[0]
             acc["t_sol"] += r.t_solve_ms - before[1]
             acc["t_upd"] += r.t_update_ms - before[2]
             acc["n_asm"] += r.n_assemblies - before[3]
             acc["krylov"] += r.krylov_iters - before[4]
+            acc["spmv"] += r.krylov_spmv - before[5]
             if conv:
                 self.ctx.commit_increment()
                 self.inc += 1
-                self.in_inc = False
                 acc["increments"] += 1
                 acc["last_rel_u"] = r.res_u / max(r.ref_u, 1e-300)
                 acc["last_rel_e"] = r.res_e / max(r.ref_e, 1e-300)
-                continue
-            self.newton_in_inc += 1
-            if self.newton_in_inc > self.opts.max_newton:
+                return
+            it += 1
+            acc["newton"] += 1
+            if it > self.opts.max_newton:
                 raise RuntimeError("Newton did not converge in increment %d" % (self.inc + 1))
-            return
 
 
 def new_acc():
-    return dict(t_asm=0.0, t_sol=0.0, t_upd=0.0, n_asm=0, krylov=0, increments=0,
+    return dict(t_asm=0.0, t_sol=0.0, t_upd=0.0, n_asm=0, krylov=0, spmv=0, newton=0, increments=0,
                 last_rel_u=None, last_rel_e=None)
 
 
 def algorithmic_bytes(prob, nnz, npairs, s_val):
     """Per launch: assembly (reads x, coords, conn, kappa_n, E-scale; writes
-    CSR values and R) and SpMV (values, node-graph columns, offsets, x, y)."""
+    CSR values and R) and SpMV (values, node-graph columns, the row offset of
+    each node and the node-graph offsets, FP64 x and y)."""
     ndof, nn, ne, ng = prob.ndof, prob.n_nodes, prob.n_elems, prob.n_elems * prob.ngp
     asm = (ndof * 8 + nn * prob.dim * 8 + ne * prob.nen * 4 + ng * 8 + ne * 8
            + nnz * s_val + ndof * 8)
-    spmv = nnz * s_val + npairs * 4 + (ndof + 1) * 4 + (nn + 1) * 4 + ndof * s_val * 2
+    spmv = nnz * s_val + npairs * 4 + nn * 4 + (nn + 1) * 4 + ndof * 8 * 2
     return asm, spmv
+
+
+def committed_traffic(kernel_key, launches_bytes):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE counters (scaled by the same counters
+    of a plain copy of known size), or None when the kernel's source changed
+    since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(kernel_key)
+    if not rec:
+        return None
+    src = os.path.join(ROOT, rec["source"])
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if sha != rec["source_sha256"]:
+        return None
+    return rec["hbm_bytes_per_launch"]
 
 
 def run_precision(prob, precision, args, binding):
@@ -114,19 +131,23 @@ def run_precision(prob, precision, args, binding):
     ctx.setup_problem(prob)
     torch.cuda.synchronize()
     log("setup %.2fs precision=%s ndof=%d nGP=%d" % (time.time() - t0, precision, ctx.ndof, ctx.ngauss))
-    opts = binding.solver_opts(max_newton=30, tol_newton=1e-8, tol_krylov=args.tol_krylov,
-                               max_krylov=args.max_krylov, check_every=32)
+    opts = binding.solver_opts(max_newton=40, tol_newton=1e-8, tol_krylov=args.tol_krylov,
+                               max_krylov=args.max_krylov, check_every=32,
+                               krylov_method=binding.KRYLOV_BICGSTAB if args.krylov == "bicgstab"
+                               else binding.KRYLOV_IDRS, idr_s=args.idr_s,
+                               forcing=binding.FORCING_FIXED if args.fixed_forcing else binding.FORCING_ADAPTIVE)
     runner = PathRunner(ctx, prob, opts, binding)
     warm = new_acc()
     for i in range(args.warmup):
         runner.step(warm)
-        log("warmup step %d done (increment %d, krylov %d)" % (i + 1, runner.inc + 1, warm["krylov"]))
+        log("warmup step %d done (increment %d, spmv %d)" % (i + 1, runner.inc, warm["spmv"]))
     acc = new_acc()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         runner.step(acc)
-        log("step %d done (increment %d, krylov so far %d)" % (i + 1, runner.inc + 1, acc["krylov"]))
+        log("step %d done (increment %d, Newton so far %d, spmv so far %d)"
+            % (i + 1, runner.inc, acc["newton"], acc["spmv"]))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     view, _ = ctx.assemble(-1.0, want_R=False)
@@ -137,18 +158,24 @@ def run_precision(prob, precision, args, binding):
     asm_b, spmv_b = algorithmic_bytes(prob, nnz, npairs, s_val)
     ng = ctx.ngauss
     res = {
-        "gp_per_s": ng * acc["n_asm"] / (acc["t_asm"] / 1e3) if acc["t_asm"] > 0 else None,
-        "ms_per_step": wall * 1e3 / args.steps,
-        "phase_ms_per_step": {"assembly": acc["t_asm"] / args.steps, "solve": acc["t_sol"] / args.steps,
-                              "update": acc["t_upd"] / args.steps},
-        "assemblies": acc["n_asm"], "krylov_iters": acc["krylov"],
-        "krylov_iters_per_step": acc["krylov"] / args.steps,
-        "increments_committed": runner.inc, "increments_in_timed_region": acc["increments"],
+        "gp_per_s": ng * acc["n_asm"] / wall,
+        "ms_per_increment": wall * 1e3 / args.steps,
+        "newton_step_ms": wall * 1e3 / max(acc["newton"], 1),
+        "newton_iterations": acc["newton"], "assemblies": acc["n_asm"],
+        "increments_in_timed_region": acc["increments"], "increments_committed": runner.inc,
+        "assembly_gp_per_s_device": ng * acc["n_asm"] / (acc["t_asm"] / 1e3) if acc["t_asm"] > 0 else None,
+        "phase_ms_per_increment": {"assembly": acc["t_asm"] / args.steps, "solve": acc["t_sol"] / args.steps,
+                                   "update": acc["t_upd"] / args.steps},
+        "krylov_iters": acc["krylov"], "spmv_launches": acc["spmv"],
+        "spmv_per_newton_step": acc["spmv"] / max(acc["newton"], 1),
+        "final_rel_residual": [acc["last_rel_u"], acc["last_rel_e"]],
         "kernel_ms": {"gauss_point": kt[0], "node_assembly": kt[1], "spmv": kt[2], "block_jacobi": kt[3]},
         "assembly_bytes": asm_b, "spmv_bytes": spmv_b,
         "assembly_gbs": asm_b / ((kt[0] + kt[1]) * 1e-3) / 1e9,
         "spmv_gbs": spmv_b / (kt[2] * 1e-3) / 1e9,
         "footprint_gb": ctx.footprint() / 1e9,
+        "solver": {"krylov": args.krylov, "idr_s": args.idr_s if args.krylov == "idr" else None,
+                   "forcing": "fixed" if args.fixed_forcing else "adaptive", "tol_krylov": args.tol_krylov},
     }
     ctx.close()
     del ctx
@@ -201,18 +228,39 @@ def copy_calibration(nbytes=1 << 30):
             "ms": ms, "gbs": 2 * nbytes / (ms * 1e-3) / 1e9}
 
 
+def serving_leg(seconds):
+    """The continuous-batching workload: 256 seeded 2D notched-plate requests
+    (40x20 .. 400x200 Q4, 50-200 increments) with Poisson arrivals at 20/s,
+    mixed precision, served for a bounded wall time."""
+    import lgdm_workloads as W
+    from paper_2301_06503_amd import binding, serving
+    reqs = W.serving_stream(n_requests=256, rate_per_s=20.0, seed=0)
+    loop = serving.ServingLoop(reqs, precision=binding.MIXED, max_slots=64)
+    summ = loop.run(time_limit_s=seconds, realtime=True)
+    loop.close()
+    summ["workload"] = ("256 requests, Poisson arrivals 20/s, 2D notched plates 40x20..400x200 Q4, "
+                        "50-200 increments, mixed precision, 64 slots; served for %.0f s" % seconds)
+    return summ
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c3", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--tol-krylov", type=float, default=1e-6)
+    ap.add_argument("--tol-krylov", type=float, default=1e-6,
+                    help="tightest relative tolerance of a Newton correction")
+    ap.add_argument("--krylov", default="idr", choices=["idr", "bicgstab"])
+    ap.add_argument("--idr-s", type=int, default=4)
+    ap.add_argument("--fixed-forcing", action="store_true",
+                    help="solve every Newton correction to --tol-krylov (default: adaptive forcing)")
     ap.add_argument("--max-krylov", type=int, default=20000)
     ap.add_argument("--kernel-reps", type=int, default=5)
+    ap.add_argument("--serving-seconds", type=float, default=30.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the LGDM hot path here is built and measured on a single "
@@ -229,18 +277,21 @@ def main():
     fp64_res = None
     if prec == binding.MIXED and not args.no_fp64_compare:
         fp64_res = run_precision(prob, binding.FP64, args, binding)
-    # dominant kernel of a Newton step: SpMV (2 per Krylov iteration) vs assembly
+    # dominant kernel of a step: SpMV (every operator application) vs assembly
     kt = main_res["kernel_ms"]
-    spmv_share = 2 * main_res["krylov_iters_per_step"] * kt["spmv"]
-    asm_share = kt["gauss_point"] + kt["node_assembly"]
+    spmv_share = main_res["spmv_launches"] * kt["spmv"]
+    asm_share = main_res["assemblies"] * (kt["gauss_point"] + kt["node_assembly"])
     if spmv_share >= asm_share:
         achieved = main_res["spmv_gbs"]
         kern = "spmv"
     else:
         achieved = main_res["assembly_gbs"]
         kern = "assembly"
+    key = "%s_%s_%s" % (args.config, args.precision, kern)
     roofline = {"bound": "hbm", "kernel": kern, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": committed_traffic(key, None),
+                "algorithmic_bytes": main_res["spmv_bytes"] if kern == "spmv" else main_res["assembly_bytes"]}
     roof_asm = {"bound": "hbm", "kernel": "gauss_point+node_assembly",
                 "achieved": round(main_res["assembly_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(main_res["assembly_gbs"] / HBM_PEAK_GBS, 4)}
@@ -248,6 +299,9 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(prob)
     copy_cal = copy_calibration()
+    serving_res = None
+    if args.serving_seconds > 0:
+        serving_res = serving_leg(args.serving_seconds)
     out = {
         "metric": METRIC,
         "value": main_res["gp_per_s"],
@@ -255,7 +309,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": main_res["ms_per_step"],
+        "ms_per_step": main_res["ms_per_increment"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -263,11 +317,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.config], "name": args.config,
                    "precision": args.precision, "ndof": prob.ndof, "gauss_points": prob.n_elems * prob.ngp,
-                   "tol_newton": 1e-8, "tol_krylov": args.tol_krylov},
+                   "tol_newton": 1e-8, "step": "one load increment: Newton iterations to "
+                   "||R||/||F|| < 1e-8 per field, then the history commit",
+                   "newton_step_ms": main_res["newton_step_ms"],
+                   "fp64_newton_step_ms": fp64_res["newton_step_ms"] if fp64_res else None},
         "roofline": roofline,
         "roofline_assembly": roof_asm,
         "cpu_baseline": cpu,
         "copy_calibration": copy_cal,
+        "serving": serving_res,
         "detail": main_res,
         "fp64": fp64_res,
     }

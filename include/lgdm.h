@@ -88,15 +88,45 @@ typedef struct lgdm_material {
   double thickness;
 } lgdm_material;
 
+/* Krylov method of the linear solve of the Newton system (Eq. 11).  Both are
+ * right-preconditioned with per-node block-Jacobi and work on the same
+ * scaled operator; 0 selects the default, LGDM_KRYLOV_IDRS.
+ *  LGDM_KRYLOV_BICGSTAB  BiCGSTAB (van der Vorst 1992): 2 operator
+ *                        applications per iteration.
+ *  LGDM_KRYLOV_IDRS      IDR(s) (Sonneveld & van Gijzen 2008, biorthogonal
+ *                        variant 2011): one operator application per
+ *                        iteration; s shadow vectors instead of BiCGSTAB's
+ *                        one, which does not break down on the indefinite
+ *                        tangents of the softening branch where BiCGSTAB
+ *                        does. */
+enum { LGDM_KRYLOV_DEFAULT = 0, LGDM_KRYLOV_BICGSTAB = 1, LGDM_KRYLOV_IDRS = 2 };
+
 /* Newton / Krylov options.  Zero-initialised fields take the defaults shown. */
 typedef struct lgdm_solver_opts {
   int32_t max_newton;      /* 30     Newton iterations per increment                */
-  int32_t max_krylov;      /* 20000  BiCGSTAB iterations per linear solve           */
+  int32_t max_krylov;      /* 20000  Krylov iterations per linear solve             */
   double tol_newton;       /* 1e-8   per-field ||R|| <= tol * max(||F||, tiny)      */
   double tol_krylov;       /* 1e-10  per-field ||r|| <= tol * ||b||                 */
   int32_t check_every;     /* 16     Krylov iterations between host convergence reads */
-  int32_t max_restarts;    /* 8      BiCGSTAB restarts after breakdown              */
+  int32_t max_restarts;    /* 8      Krylov restarts after breakdown                */
+  int32_t krylov_method;   /* LGDM_KRYLOV_IDRS                                      */
+  int32_t idr_s;           /* 4      IDR shadow-space dimension: 1, 2, 4 or 8 (other
+                                     values round up to the next of these, max 8) */
+  int32_t forcing;         /* LGDM_FORCING_ADAPTIVE                                 */
+  int32_t reserved;
 } lgdm_solver_opts;
+
+/* Tolerance of the linear solves inside Newton (lgdm_newton_iteration,
+ * lgdm_solve_increment, the batch):
+ *  LGDM_FORCING_ADAPTIVE  per field f, max(tol_krylov, min(0.5, m * tol_newton *
+ *                         ||F_f|| / ||R_f||)) with m = 0.1 (FP64) or 0.01
+ *                         (mixed): corrections far from convergence solve to
+ *                         tol_krylov, the last ones only as far as the Newton
+ *                         test needs.
+ *  LGDM_FORCING_FIXED     every correction to tol_krylov.
+ * lgdm_solve_linear always solves to tol_krylov.  Convergence of Newton is
+ * judged on the FP64 residual either way. */
+enum { LGDM_FORCING_ADAPTIVE = 0, LGDM_FORCING_FIXED = 1 };
 
 /* Per-increment / per-iteration report (the paper's time-per-iteration split
  * into assembly, solve and variable update, Sec. 3.1). */
@@ -113,7 +143,14 @@ typedef struct lgdm_increment_report {
   double t_solve_ms;       /* device time in the linear solves                      */
   double t_update_ms;      /* device time in update / norms / commit               */
   int32_t n_assemblies;
-  int32_t restarts;
+  int32_t restarts;        /* BiCGSTAB restarts after breakdown, summed             */
+  int32_t krylov_status;   /* status of the last linear solve (LGDM_OK, or the
+                              NOT_CONVERGED / BREAKDOWN of an inexact correction
+                              that Newton accepted)                                */
+  int32_t inexact_solves;  /* solves accepted short of tol_krylov                  */
+  double krylov_rel_u;     /* last solve: ||(S(b - A x))_u|| / ||(S b)_u||          */
+  double krylov_rel_e;     /* last solve: the same for the ebar rows                */
+  int64_t krylov_spmv;     /* operator applications (SpMV) in the linear solves     */
 } lgdm_increment_report;
 
 /* View of the assembled tangent.  Device pointers owned by the context. */

@@ -26,6 +26,8 @@ LGDM_ERR_BUSY = 8
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "OOM", 3: "DEVICE", 4: "NOT_CONVERGED", 5: "NAN",
                 6: "BREAKDOWN", 7: "STATE", 8: "BUSY"}
 SLOT_FREE, SLOT_RUNNING, SLOT_FINISHED, SLOT_FAILED = 0, 1, 2, 3
+KRYLOV_DEFAULT, KRYLOV_BICGSTAB, KRYLOV_IDRS = 0, 1, 2
+FORCING_ADAPTIVE, FORCING_FIXED = 0, 1
 
 # every entry point the header declares
 EXPORTS = [
@@ -51,7 +53,9 @@ class Material(ctypes.Structure):
 class SolverOpts(ctypes.Structure):
     _fields_ = [("max_newton", ctypes.c_int32), ("max_krylov", ctypes.c_int32),
                 ("tol_newton", ctypes.c_double), ("tol_krylov", ctypes.c_double),
-                ("check_every", ctypes.c_int32), ("max_restarts", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("max_restarts", ctypes.c_int32),
+                ("krylov_method", ctypes.c_int32), ("idr_s", ctypes.c_int32),
+                ("forcing", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class IncrementReport(ctypes.Structure):
@@ -60,7 +64,10 @@ class IncrementReport(ctypes.Structure):
         (n, ctypes.c_double) for n in ("res_u", "res_e", "ref_u", "ref_e", "du_norm", "de_norm",
                                        "reaction", "max_damage", "t_assembly_ms", "t_solve_ms",
                                        "t_update_ms")] + [
-        ("n_assemblies", ctypes.c_int32), ("restarts", ctypes.c_int32)]
+        ("n_assemblies", ctypes.c_int32), ("restarts", ctypes.c_int32),
+        ("krylov_status", ctypes.c_int32), ("inexact_solves", ctypes.c_int32),
+        ("krylov_rel_u", ctypes.c_double), ("krylov_rel_e", ctypes.c_double),
+        ("krylov_spmv", ctypes.c_int64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

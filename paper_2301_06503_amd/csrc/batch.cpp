@@ -71,17 +71,6 @@ bool converged(const lgdm_ctx* c, double tol) {
          std::sqrt(c->last_norms[1]) <= tol * std::max(std::sqrt(c->last_norms[3]), tiny);
 }
 
-lgdm_solver_opts opts_or_default(const lgdm_solver_opts* o) {
-  lgdm_solver_opts r{};
-  if (o) r = *o;
-  if (r.max_newton <= 0) r.max_newton = 30;
-  if (r.max_krylov <= 0) r.max_krylov = 20000;
-  if (!(r.tol_newton > 0)) r.tol_newton = 1e-8;
-  if (!(r.tol_krylov > 0)) r.tol_krylov = 1e-10;
-  if (r.check_every <= 0) r.check_every = 16;
-  if (r.max_restarts <= 0) r.max_restarts = 8;
-  return r;
-}
 
 void release(lgdm_batch* b, Slot& s) {
   if (s.ctx) {
@@ -124,10 +113,10 @@ lgdm_status lgdm_request_footprint(int32_t dim, int64_t n_nodes, int64_t n_elems
   s += (n_nodes + 1) * 4 * 2 + n_elems * nen * 4 + n_nodes * nbr * 4 + n_nodes * 4;  // graph
   s += n_elems * nen * nen;                                     // positions
   s += (ndof + 1) * 4 + nnz * 4 + nnz * sval;                   // CSR
-  s += ndof * 8 * (4 + 9) + ndof;                               // state, Krylov vectors, flags
+  s += ndof * 8 * (4 + KV_VECS) + ndof;                         // state, Krylov vectors, flags
   s += ng * 8 * 4 + ng * rs * 8;                                // Gauss-point state, records
   s += n_nodes * nd * nd * sval;                                // block-Jacobi
-  s += (int64_t)(2048 * 8 + 1024 * 6 + 256) * 8;               // partials
+  s += ((int64_t)KPART_BLOCKS * KPART_PER_BLOCK + 1024 * 6 + KSCAL_DOUBLES + 64) * 8;  // partials, scalars
   s += ((n_nodes + 3) / 4 + 1) * 6 * 8;
   *bytes = s + (int64_t)64 * 256;                               // allocation rounding
   return LGDM_OK;
@@ -226,7 +215,7 @@ lgdm_status lgdm_batch_admit(lgdm_batch* b, const lgdm_request* r, int32_t* slot
 lgdm_status lgdm_batch_tick(lgdm_batch* b, const lgdm_solver_opts* o, lgdm_tick_report* rep) {
   if (!b) return LGDM_ERR_INVALID_ARG;
   const auto t0 = std::chrono::steady_clock::now();
-  const lgdm_solver_opts op = opts_or_default(o);
+  const lgdm_solver_opts op = fill_opts(o);
   lgdm_tick_report R{};
   BHIP(b, hipSetDevice(b->device), "set device");
   // 1. requests between increments start their next load step
@@ -316,7 +305,9 @@ lgdm_status lgdm_batch_tick(lgdm_batch* b, const lgdm_solver_opts* o, lgdm_tick_
       continue;
     }
     BHIP(b, krylov_setup(c), "block-Jacobi setup");
-    s.run = make_krylov_run(c, c->R, c->delta, op);
+    double tol_u = op.tol_krylov, tol_e = op.tol_krylov;
+    newton_forcing(c, op, tol_u, tol_e);
+    s.run = make_krylov_run(c, c->R, c->delta, op, tol_u, tol_e);
     BHIP(b, s.run->start(), "Krylov start");
     s.solving = true;
     R.solves++;

@@ -104,17 +104,6 @@ lgdm_status assemble_now(lgdm_ctx* c, float* ms) {
   return LGDM_OK;
 }
 
-lgdm_solver_opts fill_opts(const lgdm_solver_opts* o) {
-  lgdm_solver_opts r{};
-  if (o) r = *o;
-  if (r.max_newton <= 0) r.max_newton = 30;
-  if (r.max_krylov <= 0) r.max_krylov = 20000;
-  if (!(r.tol_newton > 0)) r.tol_newton = 1e-8;
-  if (!(r.tol_krylov > 0)) r.tol_krylov = 1e-10;
-  if (r.check_every <= 0) r.check_every = 16;
-  if (r.max_restarts <= 0) r.max_restarts = 8;
-  return r;
-}
 
 void fill_norms(const lgdm_ctx* c, lgdm_increment_report* rep) {
   if (!rep) return;
@@ -133,22 +122,27 @@ bool residual_converged(const lgdm_ctx* c, double tol) {
 }
 
 lgdm_status linear_solve(lgdm_ctx* c, const double* b_dev, double* x_dev, const lgdm_solver_opts& o,
-                         lgdm_increment_report* rep) {
+                         double tol_u, double tol_e, lgdm_increment_report* rep) {
   HIPCHECK(c, krylov_setup(c), "block-Jacobi setup");
   KrylovResult kr{};
-  HIPCHECK(c, krylov_solve(c, b_dev, x_dev, o, kr), "BiCGSTAB");
+  HIPCHECK(c, krylov_solve(c, b_dev, x_dev, o, tol_u, tol_e, kr), "Krylov solve");
   if (rep) {
     rep->krylov_iters += kr.iters;
     rep->restarts += kr.restarts;
+    rep->krylov_status = kr.status;
+    rep->krylov_spmv += kr.spmv;
+    rep->krylov_rel_u = kr.rel_u;
+    rep->krylov_rel_e = kr.rel_e;
+    if (kr.status == LGDM_ERR_NOT_CONVERGED || kr.status == LGDM_ERR_BREAKDOWN) rep->inexact_solves += 1;
   }
   if (kr.status == LGDM_ERR_NAN)
     return fail(c, LGDM_ERR_NAN, "non-finite Krylov scalar after " + std::to_string(kr.iters) +
                                      " iterations (" + std::to_string(kr.restarts) + " restarts)");
   if (kr.status == LGDM_ERR_BREAKDOWN)
-    return fail(c, LGDM_ERR_BREAKDOWN, "BiCGSTAB breakdown persisted after " +
+    return fail(c, LGDM_ERR_BREAKDOWN, "Krylov breakdown persisted after " +
                                            std::to_string(kr.restarts) + " restarts");
   if (kr.status == LGDM_ERR_NOT_CONVERGED)
-    return fail(c, LGDM_ERR_NOT_CONVERGED, "BiCGSTAB reached max_krylov");
+    return fail(c, LGDM_ERR_NOT_CONVERGED, "Krylov solve stopped short of its tolerance");
   return LGDM_OK;
 }
 
@@ -286,12 +280,12 @@ lgdm_status lgdm_upload_mesh(lgdm_ctx* c, int32_t dim, int32_t elem_type, int64_
   c->norms_dev = (double*)dalloc(c, 16 * sizeof(double));
   c->red2 = (double*)dalloc(c, RED_CHUNKS * NORM_SLOTS * sizeof(double));
   c->dof_flags = (uint8_t*)dalloc(c, nd);
-  c->kv = (double*)dalloc(c, 9 * nd * sizeof(double));  // 8 Krylov vectors + best iterate
+  c->kv = (double*)dalloc(c, (size_t)KV_VECS * nd * sizeof(double));
   if (mixed) c->minv32 = (float*)dalloc(c, n_nodes * c->nd * c->nd * sizeof(float));
   else c->minv = (double*)dalloc(c, n_nodes * c->nd * c->nd * sizeof(double));
-  c->n_kpart = 2048 * 8;
+  c->n_kpart = (int64_t)KPART_BLOCKS * KPART_PER_BLOCK;
   c->kpart = (double*)dalloc(c, c->n_kpart * sizeof(double));
-  c->kscal = (double*)dalloc(c, 64 * sizeof(double));
+  c->kscal = (double*)dalloc(c, KSCAL_DOUBLES * sizeof(double));
   c->kcount = (unsigned*)dalloc(c, 16 * sizeof(unsigned));
   if (!c->x || !c->x_save || !c->R || !c->delta || !c->kappa_n || !c->D_n || !c->kappa_t || !c->D_t ||
       !c->rec || (!c->vals && !c->vals32) || !c->partials || !c->norms_dev || !c->red2 || !c->dof_flags ||
@@ -394,7 +388,7 @@ lgdm_status lgdm_solve_linear(lgdm_ctx* c, const double* b, double* delta, const
   double* xdev = (double*)dalloc(c, c->ndof * sizeof(double));
   if (!xdev) return fail(c, LGDM_ERR_OOM, "device allocation failed (solution)");
   if (rep) std::memset(rep, 0, sizeof(*rep));
-  lgdm_status s = linear_solve(c, bdev, xdev, op, rep);
+  lgdm_status s = linear_solve(c, bdev, xdev, op, op.tol_krylov, op.tol_krylov, rep);
   if (s == LGDM_OK) {
     hipError_t e = hipMemcpyAsync(delta, xdev, c->ndof * sizeof(double), hipMemcpyDefault, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -432,7 +426,9 @@ lgdm_status lgdm_newton_iteration(lgdm_ctx* c, const lgdm_solver_opts* o, int32_
     return LGDM_OK;
   }
   HIPCHECK(c, hipEventRecord(c->ev[2], c->stream), "event");
-  s = linear_solve(c, c->R, c->delta, op, rep);
+  double tol_u = op.tol_krylov, tol_e = op.tol_krylov;
+  newton_forcing(c, op, tol_u, tol_e);
+  s = linear_solve(c, c->R, c->delta, op, tol_u, tol_e, rep);
   HIPCHECK(c, hipEventRecord(c->ev[3], c->stream), "event");
   if (!tolerable_in_newton(s)) return s;
   s = LGDM_OK;

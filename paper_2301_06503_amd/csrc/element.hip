@@ -423,6 +423,11 @@ __device__ __forceinline__ void block_and_force(const double* __restrict__ rv, i
 // ---------------------------------------------------------------------------
 constexpr int NODE_BLOCK = 256;
 
+// T: type of the stored CSR values.  The blocks are always formed and summed
+// in FP64 and rounded once at the store: FP32 arithmetic would leave absolute
+// errors of ~1e-7 of the largest entry in every entry (rigid-body and
+// bending modes of the assembled tangent are no longer annihilated to that
+// level), which on slender meshes is the size of the smallest eigenvalues.
 template <int DIM, typename T> struct NodeLds {
   using E = Elem<DIM>;
   static constexpr int NEN = E::NEN, NGP = E::NGP, ND = E::ND, NB = ND * ND;
@@ -432,7 +437,7 @@ template <int DIM, typename T> struct NodeLds {
   static constexpr int GS = RS + 2;                   // per Gauss point (even: 16-byte aligned)
   static constexpr int KS = NGP * GS + 2;             // per element: spreads a node's elements over LDS banks
   static constexpr int REC_D = NPB * NEN * KS;        // phase 1: records, doubles
-  static constexpr int BLK_B = NB * NODE_BLOCK * (int)sizeof(T);
+  static constexpr int BLK_B = NB * NODE_BLOCK * (int)sizeof(double);
   static constexpr int F_B = (DIM + 2) * NODE_BLOCK * 8;
   static constexpr int SLOT_B = NPB * NEN * L * 4;
   static constexpr int P2_D = (BLK_B + F_B + SLOT_B + 7) / 8;   // phase 2, doubles
@@ -465,7 +470,7 @@ __device__ __forceinline__ void node_block(int64_t blk, const NodeArgs& A, const
   __shared__ __align__(16) double smem[LD::SMEM_D];
   __shared__ double s_red[NORM_SLOTS][NPB];
   __shared__ int s_chunks;
-  T* s_blk = reinterpret_cast<T*>(smem);                                   // [NB][NODE_BLOCK]
+  double* s_blk = smem;                                                    // [NB][NODE_BLOCK]
   double* s_f = reinterpret_cast<double*>(reinterpret_cast<char*>(smem) + LD::BLK_B);  // [DIM+2][NODE_BLOCK]
   int* s_slot = reinterpret_cast<int*>(reinterpret_cast<char*>(smem) + LD::BLK_B + LD::F_B);  // [NPB][NEN][L]
 
@@ -488,11 +493,11 @@ __device__ __forceinline__ void node_block(int64_t blk, const NodeArgs& A, const
   __syncthreads();
   const int chunks = s_chunks;
 
-  T acc[ND][ND];
+  double acc[ND][ND];
 #pragma unroll
   for (int i = 0; i < ND; ++i)
 #pragma unroll
-    for (int j = 0; j < ND; ++j) acc[i][j] = (T)0;
+    for (int j = 0; j < ND; ++j) acc[i][j] = 0.0;
   double facc[DIM + 2];
 #pragma unroll
   for (int i = 0; i < DIM + 2; ++i) facc[i] = 0.0;
@@ -519,18 +524,18 @@ __device__ __forceinline__ void node_block(int64_t blk, const NodeArgs& A, const
         for (int q = 0; q < FPL; ++q) srec[g * GS + b * FPL + q] = src[g * RS + q];
     }
     __syncthreads();
-    T blk[ND][ND];
+    double blk[ND][ND];
 #pragma unroll
     for (int i = 0; i < ND; ++i)
 #pragma unroll
-      for (int j = 0; j < ND; ++j) blk[i][j] = (T)0;
+      for (int j = 0; j < ND; ++j) blk[i][j] = 0.0;
     double f[DIM + 2];
 #pragma unroll
     for (int i = 0; i < DIM + 2; ++i) f[i] = 0.0;
     if (act) {
       const bool wf = (b == 0);
 #pragma unroll 1
-      for (int g = 0; g < NGP; ++g) block_and_force<DIM, T>(srec + g * GS, g, la, b, mp, WANT_K, wf, blk, f);
+      for (int g = 0; g < NGP; ++g) block_and_force<DIM, double>(srec + g * GS, g, la, b, mp, WANT_K, wf, blk, f);
     }
     __syncthreads();
     // phase 2: blocks to LDS, position -> local node table
@@ -582,12 +587,12 @@ __device__ __forceinline__ void node_block(int64_t blk, const NodeArgs& A, const
 #pragma unroll
       for (int c = 0; c < ND; ++c) {
         const int64_t col = nbn * ND + c;
-        T v = acc[r][c];
+        double v = acc[r][c];
         if (rd)
-          v = (col == row) ? (T)1 : (T)0;
+          v = (col == row) ? 1.0 : 0.0;
         else if (flags[col] & 1)
-          v = (T)0;
-        vals[rb + r * rowlen + (int64_t)l * ND + c] = v;
+          v = 0.0;
+        vals[rb + r * rowlen + (int64_t)l * ND + c] = (T)v;
       }
     }
   }

@@ -34,18 +34,18 @@ namespace lgdm {
 namespace {
 
 constexpr int BS = 256;
-constexpr int MAX_GRID = 2048;
+constexpr int MAX_GRID = KPART_BLOCKS;
 
 // device scalar slots
 enum {
   K_RHO = 0, K_RHO_OLD, K_ALPHA, K_OMEGA, K_BETA, K_RU, K_RE, K_BU, K_BE, K_DONE, K_STATUS,
-  K_ITER, K_TOL2, K_SE, K_RH2, K_B2, K_BRK, K_NSLOTS = 24
+  K_ITER, K_TOL2, K_SE, K_RH2, K_B2, K_BRK, K_TOL2E, K_NSLOTS = 24
 };
 // status values
 enum { KS_RUN = 0, KS_CONV = 1, KS_BREAK = 2, KS_NAN = 3 };
 // a recurrence scalar below this fraction of the norms it is made of is a
 // breakdown (~1e2 ulp of the FP64 Krylov vectors)
-template <typename T> constexpr double break_rel() { return 1e-14; }
+constexpr double BREAK_REL = 1e-14;
 // residual at this fraction of |S b| is at the FP64 precision floor: stop
 constexpr double FLOOR_REL2 = 1e-30;
 // a field is judged against max(|b_field|, FIELD_FLOOR |b|): the scaled fields
@@ -55,6 +55,9 @@ constexpr double FIELD_FLOOR2 = 1e-6;
 // iterations without a new best residual after which a solve has stagnated
 // (the FP32 operator of a mixed context bounds the attainable residual)
 constexpr int STALL_ITERS = 500;
+// IDR(s) minimal-residual step: omega is enlarged until the cosine of the
+// angle between t and r it implies is at least this (van Gijzen & Sonneveld)
+constexpr double IDR_KAPPA = 0.7;
 
 struct Vecs {
   void* r;
@@ -98,13 +101,26 @@ __device__ __forceinline__ void write_partials(double (&v)[NQ], double* part, do
     for (int q = 0; q < NQ; ++q) part[blockIdx.x * NQ + q] = v[q];
 }
 
+// Entry j of the q-th IDR shadow vector: a uniform deviate in [-1, 1) from
+// the splitmix64 output function (Steele, Lea & Flood, OOPSLA 2014) applied
+// to the counter (q + 1) * 2^40 + j.  Computed where it is used, never stored.
+__device__ __forceinline__ double shadow_entry(int q, int64_t j) {
+  uint64_t z = ((uint64_t)(q + 1) << 40) ^ (uint64_t)j;
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return (double)(z >> 11) * 0x1.0p-52 - 1.0;
+}
+
 // y = S A x (+ optional dots).  One group of G lanes per node a computes the
 // ND rows of the node together: lane v takes column v of the node's row block
 // (neighbour q = v / ND, component c = v % ND), gathers x once and multiplies
 // it into the ND rows (coalesced reads of each row), then the group reduces
 // its ND sums.  Grid-stride over nodes.
-// MODE 0: no dots; 1: dot(rh, y), |y|^2; 2: dot(y, s), |y|^2
-template <typename T, int ND, int G, int UNR, int MODE>
+// MODE 0: no dots; 1: dot(rh, y), |y|^2; 2: dot(y, s), |y|^2;
+// 3: the NP shadow-vector dots P_q . y and |y|^2 (IDR)
+template <typename T, int ND, int G, int UNR, int MODE, int NP = 0>
 __global__ void __launch_bounds__(BS) spmv_kernel(int64_t n_nodes, const int32_t* __restrict__ row_ptr,
                                                   const int32_t* __restrict__ nbr_ptr,
                                                   const int32_t* __restrict__ nbr,
@@ -113,13 +129,16 @@ __global__ void __launch_bounds__(BS) spmv_kernel(int64_t n_nodes, const int32_t
                                                   double* __restrict__ y, const double* __restrict__ w,
                                                   const double* __restrict__ sc,
                                                   double* __restrict__ part) {
-  __shared__ double sm[2][BS];
+  constexpr int NQ = MODE == 3 ? NP + 1 : 2;
+  __shared__ double sm[NQ][BS];
   if (sc[K_DONE] != 0.0) return;
   const double se = sc[K_SE];
   const int lane = threadIdx.x % G;
   const int64_t grp = ((int64_t)blockIdx.x * BS + threadIdx.x) / G;
   const int64_t ngrp = (int64_t)gridDim.x * BS / G;
-  double d0 = 0.0, d1 = 0.0;
+  double d[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) d[q] = 0.0;
   for (int64_t a = grp; a < n_nodes; a += ngrp) {
     const int32_t p0 = nbr_ptr[a];
     const int len = (nbr_ptr[a + 1] - p0) * ND;
@@ -165,18 +184,22 @@ __global__ void __launch_bounds__(BS) spmv_kernel(int64_t n_nodes, const int32_t
       const double yt = mine * (lane == ND - 1 ? se : 1.0);
       y[row] = yt;
       if (MODE == 1) {
-        d0 += w[row] * yt;
-        d1 += yt * yt;
+        d[0] += w[row] * yt;
+        d[1] += yt * yt;
       }
       if (MODE == 2) {
-        d0 += yt * w[row];
-        d1 += yt * yt;
+        d[0] += yt * w[row];
+        d[1] += yt * yt;
+      }
+      if (MODE == 3) {
+#pragma unroll
+        for (int q = 0; q < NP; ++q) d[q] += shadow_entry(q, row) * yt;
+        d[NP] += yt * yt;
       }
     }
   }
   if (MODE == 0) return;
-  double v2[2] = {d0, d1};
-  write_partials<2>(v2, part, sm);
+  write_partials<NQ>(d, part, sm);
 }
 
 // finishing reductions (one workgroup): fixed-order sums of the partials and
@@ -227,7 +250,7 @@ __global__ void __launch_bounds__(BS) scalar_kernel(int nblk, const double* __re
       return;
     }
     const double r2 = acc[1] + acc[2];
-    if ((acc[1] <= tol2 * sc[K_BU] && acc[2] <= tol2 * sc[K_BE]) || r2 <= FLOOR_REL2 * sc[K_B2]) {
+    if ((acc[1] <= tol2 * sc[K_BU] && acc[2] <= sc[K_TOL2E] * sc[K_BE]) || r2 <= FLOOR_REL2 * sc[K_B2]) {
       sc[K_STATUS] = KS_CONV;
       sc[K_DONE] = 1.0;
       return;
@@ -257,7 +280,7 @@ __global__ void __launch_bounds__(BS) scalar_kernel(int nblk, const double* __re
     if (!isfinite(acc[0])) {
       sc[K_STATUS] = KS_NAN;
       sc[K_DONE] = 1.0;
-    } else if (btot == 0.0 || (acc[1] <= tol2 * sc[K_BU] && acc[2] <= tol2 * sc[K_BE]) ||
+    } else if (btot == 0.0 || (acc[1] <= tol2 * sc[K_BU] && acc[2] <= sc[K_TOL2E] * sc[K_BE]) ||
                acc[0] <= FLOOR_REL2 * btot) {
       sc[K_STATUS] = KS_CONV;
       sc[K_DONE] = 1.0;
@@ -466,18 +489,360 @@ __global__ void __launch_bounds__(256) pair_sum_kernel(int nblk, const double* _
   }
 }
 
-__global__ void set_scalars_kernel(double* sc, double tol2, double se, double brk) {
+// tol2u, tol2e: squared relative tolerances of the u and ebar rows
+__global__ void set_scalars_kernel(double* sc, double tol2u, double tol2e, double se, double brk) {
   if (threadIdx.x == 0) {
     for (int i = 0; i < K_NSLOTS; ++i) sc[i] = 0.0;
-    sc[K_TOL2] = tol2;
+    sc[K_TOL2] = tol2u;
+    sc[K_TOL2E] = tol2e;
     sc[K_SE] = se;
     sc[K_BRK] = brk;
   }
 }
 
-inline int64_t grid_for(int64_t work) {
+// ---------------------------------------------------------------------------
+// IDR(s): induced dimension reduction (Sonneveld & van Gijzen, SIAM J. Sci.
+// Comput. 31, 2008), in the biorthogonal form of van Gijzen & Sonneveld (ACM
+// TOMS 38, 2011), right-preconditioned with the same block-Jacobi and the same
+// scaled operator S K as BiCGSTAB (IDR(1) and BiCGSTAB span the same
+// spaces).  Each cycle takes s steps that keep the new residual orthogonal to
+// s shadow vectors P (generated by shadow_entry, never stored), then one
+// minimal-residual step.  State: residual r, s direction pairs (G_k, U_k =
+// M^-1-side vectors with G_k = S K U_k), the lower-triangular s x s matrix
+// M = P^T G and f = P^T r.  A shadow space of s > 1 vectors replaces the
+// single Lanczos shadow vector whose (near-)orthogonality to r breaks
+// BiCGSTAB down on the indefinite tangents of the softening branch.
+//
+// The biorthogonalisation of a new G_k against G_0..G_{k-1} uses one fused
+// set of dot products P^T g and a forward substitution with M (the
+// coefficients the sequential form computes one at a time).
+
+// scalar slots of IDR(s), after the ones it shares with BiCGSTAB
+constexpr int I_OM = 24, I_BETA = 25, I_RR = 26, I_F = 32, I_C = 40, I_A = 48, I_M = 64;
+constexpr int I_LD = 8;  // leading dimension of M in the slots
+
+template <int NQ>
+__device__ __forceinline__ void finish_partials(int nblk, const double* __restrict__ part,
+                                                double (&acc)[NQ], double (*sm)[BS]) {
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += BS)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] += part[i * NQ + q];
+  block_sum<NQ>(acc, sm);
+}
+
+// store the residual norms and decide convergence (one thread)
+__device__ __forceinline__ bool idr_norms(double* sc, double ru, double re) {
+  sc[K_RU] = ru;
+  sc[K_RE] = re;
+  sc[I_RR] = ru + re;
+  if (!isfinite(ru) || !isfinite(re)) {
+    sc[K_STATUS] = KS_NAN;
+    sc[K_DONE] = 1.0;
+    return true;
+  }
+  if ((ru <= sc[K_TOL2] * sc[K_BU] && re <= sc[K_TOL2E] * sc[K_BE]) || ru + re <= FLOOR_REL2 * sc[K_B2]) {
+    sc[K_STATUS] = KS_CONV;
+    sc[K_DONE] = 1.0;
+    return true;
+  }
+  return false;
+}
+
+// c = M[k0:s, k0:s]^-1 f[k0:s] by forward substitution (one thread)
+template <int S>
+__device__ __forceinline__ void idr_coeffs(double* sc, int k0) {
+  for (int j = 0; j < S - k0; ++j) {
+    double v = sc[I_F + k0 + j];
+    for (int l = 0; l < j; ++l) v -= sc[I_M + (k0 + j) * I_LD + (k0 + l)] * sc[I_C + l];
+    sc[I_C + j] = v / sc[I_M + (k0 + j) * I_LD + (k0 + j)];
+  }
+}
+
+// r = S b - y; partials |r_u|^2, |r_e|^2, |(Sb)_u|^2, |(Sb)_e|^2, P^T r
+template <int ND, int S>
+__global__ void __launch_bounds__(BS) idr_init_kernel(int64_t n, const double* __restrict__ b,
+                                                      const double* __restrict__ y, int use_y,
+                                                      double* __restrict__ r, const double* __restrict__ sc,
+                                                      double* __restrict__ part) {
+  __shared__ double sm[4 + S][BS];
+  const double se = sc[K_SE];
+  double d[4 + S];
+#pragma unroll
+  for (int q = 0; q < 4 + S; ++q) d[q] = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+    const bool fe = (i % ND == ND - 1);
+    const double sb = b[i] * (fe ? se : 1.0);
+    const double rd = sb - (use_y ? y[i] : 0.0);
+    r[i] = rd;
+    d[fe ? 1 : 0] += rd * rd;
+    d[fe ? 3 : 2] += sb * sb;
+#pragma unroll
+    for (int q = 0; q < S; ++q) d[4 + q] += shadow_entry(q, i) * rd;
+  }
+  write_partials<4 + S>(d, part, sm);
+}
+
+template <int S>
+__global__ void __launch_bounds__(BS) idr_init_scalar(int nblk, const double* __restrict__ part,
+                                                      double* __restrict__ sc) {
+  __shared__ double sm[4 + S][BS];
+  double acc[4 + S];
+  finish_partials<4 + S>(nblk, part, acc, sm);
+  if (threadIdx.x != 0) return;
+  const double btot = acc[2] + acc[3];
+  sc[K_BU] = fmax(acc[2], FIELD_FLOOR2 * btot);
+  sc[K_BE] = fmax(acc[3], FIELD_FLOOR2 * btot);
+  sc[K_B2] = btot;
+  for (int i = 0; i < I_LD * I_LD; ++i) sc[I_M + i] = (i / I_LD == i % I_LD) ? 1.0 : 0.0;
+  for (int q = 0; q < S; ++q) sc[I_F + q] = acc[4 + q];
+  sc[I_OM] = 1.0;
+  sc[K_STATUS] = KS_RUN;
+  sc[K_DONE] = 0.0;
+  if (btot == 0.0) {
+    sc[K_RU] = sc[K_RE] = 0.0;
+    sc[K_STATUS] = KS_CONV;
+    sc[K_DONE] = 1.0;
+    return;
+  }
+  if (idr_norms(sc, acc[0], acc[1])) return;
+  idr_coeffs<S>(sc, 0);
+}
+
+// step k: v = r - sum_j c_j G_{k+j};  U_k = sum_j c_j U_{k+j} + omega M^-1 v.
+// In the first cycle after a (re)start every G, U term is zero (fresh).
+template <typename T, int ND, int S>
+__global__ void __launch_bounds__(BS) idr_dir_kernel(int64_t n_nodes, int k, int fresh,
+                                                     const T* __restrict__ minv, const double* __restrict__ r,
+                                                     const double* __restrict__ Gv, double* __restrict__ Uv,
+                                                     int64_t n, const double* __restrict__ sc) {
+  if (sc[K_DONE] != 0.0) return;
+  const int nc = fresh ? 0 : S - k;
+  double cc[S];
+#pragma unroll
+  for (int j = 0; j < S; ++j) cc[j] = j < nc ? sc[I_C + j] : 0.0;
+  const double om = sc[I_OM];
+  for (int64_t a = (int64_t)blockIdx.x * BS + threadIdx.x; a < n_nodes; a += (int64_t)gridDim.x * BS) {
+    double v[ND];
+#pragma unroll
+    for (int i = 0; i < ND; ++i) {
+      const int64_t row = a * ND + i;
+      double s = r[row];
+#pragma unroll
+      for (int j = 0; j < S; ++j)
+        if (j < nc) s -= cc[j] * Gv[(int64_t)(k + j) * n + row];
+      v[i] = s;
+    }
+    const T* m = minv + a * ND * ND;
+#pragma unroll
+    for (int i = 0; i < ND; ++i) {
+      const int64_t row = a * ND + i;
+      double vh = 0.0;
+#pragma unroll
+      for (int j = 0; j < ND; ++j) vh += (double)m[i * ND + j] * v[j];
+      double u = om * vh;
+#pragma unroll
+      for (int j = 0; j < S; ++j)
+        if (j < nc) u += cc[j] * Uv[(int64_t)(k + j) * n + row];
+      Uv[(int64_t)k * n + row] = u;
+    }
+  }
+}
+
+// after g = S K U_k with partials P^T g, |g|^2: the biorthogonalisation
+// coefficients a (P_i . G_k' = 0 for i < k), column k of M, beta = f_k / M_kk,
+// f -= beta M[:, k], and the coefficients c of step k + 1
+template <int S>
+__global__ void __launch_bounds__(BS) idr_g_scalar(int nblk, const double* __restrict__ part,
+                                                   double* __restrict__ sc, int k, double pnorm2) {
+  __shared__ double sm[S + 1][BS];
+  double acc[S + 1];
+  if (sc[K_DONE] != 0.0) return;
+  finish_partials<S + 1>(nblk, part, acc, sm);
+  if (threadIdx.x != 0) return;
+  for (int i = 0; i < k; ++i) {
+    double v = acc[i];
+    for (int l = 0; l < i; ++l) v -= sc[I_M + i * I_LD + l] * sc[I_A + l];
+    sc[I_A + i] = v / sc[I_M + i * I_LD + i];
+  }
+  for (int l = k; l < S; ++l) {
+    double v = acc[l];
+    for (int i = 0; i < k; ++i) v -= sc[I_A + i] * sc[I_M + l * I_LD + i];
+    sc[I_M + l * I_LD + k] = v;
+  }
+  sc[K_ITER] += 1.0;
+  const double mkk = sc[I_M + k * I_LD + k];
+  if (!isfinite(mkk) || !isfinite(acc[S])) {
+    sc[K_STATUS] = KS_NAN;
+    sc[K_DONE] = 1.0;
+    return;
+  }
+  if (mkk == 0.0 || fabs(mkk) <= sc[K_BRK] * sqrt(acc[S] * pnorm2)) {
+    sc[K_STATUS] = KS_BREAK;  // the new direction is (nearly) orthogonal to P_k
+    sc[K_DONE] = 1.0;
+    return;
+  }
+  const double beta = sc[I_F + k] / mkk;
+  sc[I_BETA] = beta;
+  for (int l = k + 1; l < S; ++l) sc[I_F + l] -= beta * sc[I_M + l * I_LD + k];
+  if (k + 1 < S) idr_coeffs<S>(sc, k + 1);
+}
+
+// G_k -= sum_{i<k} a_i G_i, U_k likewise; r -= beta G_k; x += beta U_k;
+// LAST (k = s - 1): v = M^-1 r for the minimal-residual step.  Partials
+// |r_u|^2, |r_e|^2.
+template <typename T, int ND, int S, bool LAST>
+__global__ void __launch_bounds__(BS) idr_upd_kernel(int64_t n_nodes, int k, const T* __restrict__ minv,
+                                                     double* __restrict__ Gv, double* __restrict__ Uv,
+                                                     double* __restrict__ r, double* __restrict__ x,
+                                                     double* __restrict__ v, int64_t n,
+                                                     const double* __restrict__ sc, double* __restrict__ part) {
+  __shared__ double sm[2][BS];
+  if (sc[K_DONE] != 0.0) return;
+  double aa[S];
+#pragma unroll
+  for (int i = 0; i < S; ++i) aa[i] = i < k ? sc[I_A + i] : 0.0;
+  const double beta = sc[I_BETA];
+  double d[2] = {0.0, 0.0};
+  for (int64_t a = (int64_t)blockIdx.x * BS + threadIdx.x; a < n_nodes; a += (int64_t)gridDim.x * BS) {
+    double rn[ND];
+#pragma unroll
+    for (int i = 0; i < ND; ++i) {
+      const int64_t row = a * ND + i;
+      double g = Gv[(int64_t)k * n + row], u = Uv[(int64_t)k * n + row];
+      if (k > 0) {
+#pragma unroll
+        for (int j = 0; j < S; ++j)
+          if (j < k) {
+            g -= aa[j] * Gv[(int64_t)j * n + row];
+            u -= aa[j] * Uv[(int64_t)j * n + row];
+          }
+        Gv[(int64_t)k * n + row] = g;
+        Uv[(int64_t)k * n + row] = u;
+      }
+      rn[i] = r[row] - beta * g;
+      r[row] = rn[i];
+      x[row] += beta * u;
+      d[i == ND - 1 ? 1 : 0] += rn[i] * rn[i];
+    }
+    if (LAST) {
+      const T* m = minv + a * ND * ND;
+#pragma unroll
+      for (int i = 0; i < ND; ++i) {
+        double vh = 0.0;
+#pragma unroll
+        for (int j = 0; j < ND; ++j) vh += (double)m[i * ND + j] * rn[j];
+        v[a * ND + i] = vh;
+      }
+    }
+  }
+  write_partials<2>(d, part, sm);
+}
+
+__global__ void __launch_bounds__(BS) idr_r_scalar(int nblk, const double* __restrict__ part,
+                                                   double* __restrict__ sc) {
+  __shared__ double sm[2][BS];
+  double acc[2];
+  if (sc[K_DONE] != 0.0) return;
+  finish_partials<2>(nblk, part, acc, sm);
+  if (threadIdx.x != 0) return;
+  idr_norms(sc, acc[0], acc[1]);
+}
+
+// omega of the minimal-residual step from t . r and t . t, kept away from
+// zero when t and r are far from parallel (the angle safeguard of IDR(s))
+__global__ void __launch_bounds__(BS) idr_om_scalar(int nblk, const double* __restrict__ part,
+                                                    double* __restrict__ sc) {
+  __shared__ double sm[2][BS];
+  double acc[2];
+  if (sc[K_DONE] != 0.0) return;
+  finish_partials<2>(nblk, part, acc, sm);
+  if (threadIdx.x != 0) return;
+  const double ts = acc[0], tt = acc[1], rr = sc[I_RR];
+  sc[K_ITER] += 1.0;
+  if (!isfinite(ts) || !isfinite(tt)) {
+    sc[K_STATUS] = KS_NAN;
+    sc[K_DONE] = 1.0;
+    return;
+  }
+  if (!(tt > 0.0) || ts == 0.0) {
+    sc[K_STATUS] = KS_BREAK;
+    sc[K_DONE] = 1.0;
+    return;
+  }
+  double om = ts / tt;
+  const double cosang = fabs(ts) / sqrt(tt * rr);
+  if (cosang < IDR_KAPPA) om *= IDR_KAPPA / cosang;
+  sc[I_OM] = om;
+}
+
+// r -= omega t; x += omega v; partials |r_u|^2, |r_e|^2, P^T r
+template <int ND, int S>
+__global__ void __launch_bounds__(BS) idr_om_kernel(int64_t n, double* __restrict__ r, double* __restrict__ x,
+                                                    const double* __restrict__ v, const double* __restrict__ t,
+                                                    const double* __restrict__ sc, double* __restrict__ part) {
+  __shared__ double sm[2 + S][BS];
+  if (sc[K_DONE] != 0.0) return;
+  const double om = sc[I_OM];
+  double d[2 + S];
+#pragma unroll
+  for (int q = 0; q < 2 + S; ++q) d[q] = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+    const double rd = r[i] - om * t[i];
+    r[i] = rd;
+    x[i] += om * v[i];
+    d[(i % ND == ND - 1) ? 1 : 0] += rd * rd;
+#pragma unroll
+    for (int q = 0; q < S; ++q) d[2 + q] += shadow_entry(q, i) * rd;
+  }
+  write_partials<2 + S>(d, part, sm);
+}
+
+template <int S>
+__global__ void __launch_bounds__(BS) idr_f_scalar(int nblk, const double* __restrict__ part,
+                                                   double* __restrict__ sc) {
+  __shared__ double sm[2 + S][BS];
+  double acc[2 + S];
+  if (sc[K_DONE] != 0.0) return;
+  finish_partials<2 + S>(nblk, part, acc, sm);
+  if (threadIdx.x != 0) return;
+  if (idr_norms(sc, acc[0], acc[1])) return;
+  for (int q = 0; q < S; ++q) sc[I_F + q] = acc[2 + q];
+  idr_coeffs<S>(sc, 0);
+}
+
+// compute units of the current device
+inline int device_cus() {
+  static int cus[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cus[dev] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v < 1) v = 256;
+    cus[dev] = v;
+  }
+  return cus[dev];
+}
+
+// Workgroups of BS threads for `work` threads' worth of items of `kernel`:
+// at most the workgroups the device holds at once (a grid-stride kernel
+// launched with more leaves a tail round on part of the device) and at most
+// MAX_GRID (the partial-sum buffer), with the items spread evenly.
+template <typename K> int64_t grid_of(K kernel, int64_t work) {
+  static int per_cu = 0;  // per kernel; the kernels' resources do not depend on the device
+  if (per_cu == 0) {
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kernel, BS, 0) != hipSuccess || b < 1) b = 1;
+    per_cu = b;
+  }
+  int64_t cap = (int64_t)per_cu * device_cus();
+  if (cap > MAX_GRID) cap = MAX_GRID;
   int64_t g = (work + BS - 1) / BS;
-  if (g > MAX_GRID) g = MAX_GRID;
+  if (g > cap) {
+    const int64_t iters = (work + cap * BS - 1) / (cap * BS);
+    g = (work + iters * BS - 1) / (iters * BS);
+  }
   return g < 1 ? 1 : g;
 }
 
@@ -500,15 +865,17 @@ struct Solver {
   double* vec(void* p) { return static_cast<double*>(p); }
 
   void spmv(const double* x, double* y, int mode, const double* w) {
-    const int64_t g = grid_for(nn * G);
     if (mode == 0) {
+      const int64_t g = grid_of(spmv_kernel<T, ND, G, UNR, 0>, nn * G);
       spmv_kernel<T, ND, G, UNR, 0><<<g, BS, 0, c->stream>>>(nn, c->row_ptr, c->nbr_ptr, c->nbr, vals, x, y,
                                                         w, sc, c->kpart);
     } else if (mode == 1) {
+      const int64_t g = grid_of(spmv_kernel<T, ND, G, UNR, 1>, nn * G);
       spmv_kernel<T, ND, G, UNR, 1><<<g, BS, 0, c->stream>>>(nn, c->row_ptr, c->nbr_ptr, c->nbr, vals, x, y,
                                                         w, sc, c->kpart);
       scalar_kernel<1, 2><<<1, BS, 0, c->stream>>>((int)g, c->kpart, sc);
     } else {
+      const int64_t g = grid_of(spmv_kernel<T, ND, G, UNR, 2>, nn * G);
       spmv_kernel<T, ND, G, UNR, 2><<<g, BS, 0, c->stream>>>(nn, c->row_ptr, c->nbr_ptr, c->nbr, vals, x, y,
                                                         w, sc, c->kpart);
       scalar_kernel<2, 2><<<1, BS, 0, c->stream>>>((int)g, c->kpart, sc);
@@ -516,22 +883,121 @@ struct Solver {
   }
 
   void init(const double* b, bool use_y, const double* y) {
-    const int64_t g = grid_for(n);
+    const int64_t g = grid_of(init_kernel<ND>, n);
     init_kernel<ND><<<g, BS, 0, c->stream>>>(n, b, y, use_y ? 1 : 0, vec(V.r), vec(V.rh), vec(V.p),
                                              vec(V.v), sc, c->kpart);
     scalar_kernel<4, 5><<<1, BS, 0, c->stream>>>((int)g, c->kpart, sc);
   }
 
   void iteration(double* x) {
-    const int64_t gn = grid_for(nn);
-    pupdate_kernel<T, ND><<<gn, BS, 0, c->stream>>>(nn, minv, vec(V.r), vec(V.p), vec(V.v), vec(V.ph), sc);
+    pupdate_kernel<T, ND><<<grid_of(pupdate_kernel<T, ND>, nn), BS, 0, c->stream>>>(
+        nn, minv, vec(V.r), vec(V.p), vec(V.v), vec(V.ph), sc);
     spmv(vec(V.ph), vec(V.v), 1, vec(V.rh));
-    supdate_kernel<T, ND><<<gn, BS, 0, c->stream>>>(nn, minv, vec(V.r), vec(V.v), vec(V.s), vec(V.sh), sc);
+    supdate_kernel<T, ND><<<grid_of(supdate_kernel<T, ND>, nn), BS, 0, c->stream>>>(
+        nn, minv, vec(V.r), vec(V.v), vec(V.s), vec(V.sh), sc);
     spmv(vec(V.sh), vec(V.t), 2, vec(V.s));
-    const int64_t g = grid_for(n);
+    const int64_t g = grid_of(xupdate_kernel<ND>, n);
     xupdate_kernel<ND><<<g, BS, 0, c->stream>>>(n, x, vec(V.ph), vec(V.sh), vec(V.s), vec(V.t),
                                                 vec(V.r), vec(V.rh), sc, c->kpart);
     scalar_kernel<3, 3><<<1, BS, 0, c->stream>>>((int)g, c->kpart, sc);
+  }
+
+  // the interface a Krylov run drives
+  static constexpr int SPMV_PER_ITER = 2;
+  void bind(lgdm_ctx* ctx) {
+    c = ctx;
+    n = c->ndof;
+    nn = c->n_nodes;
+    vals = F32 ? (const T*)c->vals32 : (const T*)c->vals;
+    minv = F32 ? (const T*)c->minv32 : (const T*)c->minv;
+    void** vp[8] = {&V.r, &V.rh, &V.p, &V.v, &V.s, &V.t, &V.ph, &V.sh};
+    for (int i = 0; i < 8; ++i) *vp[i] = c->kv + (int64_t)i * c->ndof;
+    sc = c->kscal;
+  }
+  void begin(const double* b) { init(b, false, nullptr); }
+  void restart(const double* b, const double* x) {
+    spmv(x, vec(V.t), 0, nullptr);
+    init(b, true, vec(V.t));
+  }
+  void iterate(double* x, int iters) {
+    for (int i = 0; i < iters; ++i) iteration(x);
+  }
+};
+
+// IDR(s) driver: per cycle, s steps of {direction, SpMV + P^T g, update}
+// and one minimal-residual step; scalars as for BiCGSTAB.
+template <typename T, int ND, int S>
+struct Idr {
+  static constexpr bool F32 = std::is_same<T, float>::value;
+  static constexpr int G = Solver<T, ND>::G;
+  static constexpr int UNR = Solver<T, ND>::UNR;
+  static constexpr int SPMV_PER_ITER = 1;
+  lgdm_ctx* c = nullptr;
+  const T* vals = nullptr;
+  const T* minv = nullptr;
+  double* sc = nullptr;
+  double *r = nullptr, *v = nullptr, *t = nullptr, *Gv = nullptr, *Uv = nullptr;
+  int64_t n = 0, nn = 0;
+  bool fresh = true;
+
+  void bind(lgdm_ctx* ctx) {
+    c = ctx;
+    n = c->ndof;
+    nn = c->n_nodes;
+    vals = F32 ? (const T*)c->vals32 : (const T*)c->vals;
+    minv = F32 ? (const T*)c->minv32 : (const T*)c->minv;
+    r = c->kv;
+    v = c->kv + n;
+    t = c->kv + 2 * n;
+    Gv = c->kv + 3 * n;
+    Uv = c->kv + (3 + S) * n;
+    sc = c->kscal;
+  }
+  int64_t spmv_grid() const { return grid_of(spmv_kernel<T, ND, G, UNR, 3, S>, nn * G); }
+  void init(const double* b, const double* y) {
+    const int64_t g = grid_of(idr_init_kernel<ND, S>, n);
+    idr_init_kernel<ND, S><<<g, BS, 0, c->stream>>>(n, b, y, y ? 1 : 0, r, sc, c->kpart);
+    idr_init_scalar<S><<<1, BS, 0, c->stream>>>((int)g, c->kpart, sc);
+    fresh = true;
+  }
+  void begin(const double* b) { init(b, nullptr); }
+  void restart(const double* b, const double* x) {
+    spmv_kernel<T, ND, G, UNR, 0><<<grid_of(spmv_kernel<T, ND, G, UNR, 0>, nn * G), BS, 0, c->stream>>>(
+        nn, c->row_ptr, c->nbr_ptr, c->nbr, vals, x, t, nullptr, sc, c->kpart);
+    init(b, t);
+  }
+  void cycle(double* x) {
+    const int64_t gd = grid_of(idr_dir_kernel<T, ND, S>, nn), gs = spmv_grid();
+    const int64_t gu = grid_of(idr_upd_kernel<T, ND, S, false>, nn);
+    const int64_t gl = grid_of(idr_upd_kernel<T, ND, S, true>, nn);
+    const int64_t gm = grid_of(spmv_kernel<T, ND, G, UNR, 2>, nn * G), g = grid_of(idr_om_kernel<ND, S>, n);
+    const double pnorm2 = (double)n / 3.0;  // E|P_k|^2 of uniform [-1, 1) entries
+    for (int k = 0; k < S; ++k) {
+      idr_dir_kernel<T, ND, S><<<gd, BS, 0, c->stream>>>(nn, k, fresh ? 1 : 0, minv, r, Gv, Uv, n, sc);
+      double* gk = Gv + (int64_t)k * n;
+      spmv_kernel<T, ND, G, UNR, 3, S><<<gs, BS, 0, c->stream>>>(nn, c->row_ptr, c->nbr_ptr, c->nbr, vals,
+                                                                 Uv + (int64_t)k * n, gk, nullptr, sc,
+                                                                 c->kpart);
+      idr_g_scalar<S><<<1, BS, 0, c->stream>>>((int)gs, c->kpart, sc, k, pnorm2);
+      if (k + 1 < S)
+        idr_upd_kernel<T, ND, S, false><<<gu, BS, 0, c->stream>>>(nn, k, minv, Gv, Uv, r, x, v, n, sc,
+                                                                   c->kpart);
+      else
+        idr_upd_kernel<T, ND, S, true><<<gl, BS, 0, c->stream>>>(nn, k, minv, Gv, Uv, r, x, v, n, sc,
+                                                                  c->kpart);
+      idr_r_scalar<<<1, BS, 0, c->stream>>>((int)(k + 1 < S ? gu : gl), c->kpart, sc);
+    }
+    spmv_kernel<T, ND, G, UNR, 2><<<gm, BS, 0, c->stream>>>(nn, c->row_ptr, c->nbr_ptr, c->nbr, vals, v, t, r,
+                                                            sc, c->kpart);
+    idr_om_scalar<<<1, BS, 0, c->stream>>>((int)gm, c->kpart, sc);
+    idr_om_kernel<ND, S><<<g, BS, 0, c->stream>>>(n, r, x, v, t, sc, c->kpart);
+    idr_f_scalar<S><<<1, BS, 0, c->stream>>>((int)g, c->kpart, sc);
+    fresh = false;
+  }
+  // `iters` operator applications, rounded up to whole cycles of s + 1
+  void iterate(double* x, int iters) {
+    const int ncyc = (iters + S) / (S + 1);
+    for (int i = 0; i < (ncyc > 0 ? ncyc : 1); ++i) cycle(x);
   }
 };
 
@@ -540,15 +1006,15 @@ struct Solver {
 // convergence, restart, stagnation) and launch() (enqueues check_every
 // iterations) until finished().  Several runs on different streams can be
 // interleaved by the host so their kernels overlap on the device.
-template <typename T, int ND>
+template <typename Method>
 struct KrylovRunImpl final : KrylovRun {
-  Solver<T, ND> S;
+  Method S;
   lgdm_ctx* c;
   const double* b;
   double* xout;
   lgdm_solver_opts o;
   KrylovResult res{};
-  double tol = 0, se = 0;
+  double tol_u = 0, tol_e = 0, se = 0;
   int every = 16;
   int64_t done_iters = 0;
   bool true_residual = true;   // the scalars describe b - A x computed directly
@@ -559,20 +1025,14 @@ struct KrylovRunImpl final : KrylovRun {
   bool have_best = false;
   bool fin = false;
 
-  KrylovRunImpl(lgdm_ctx* ctx, const double* b_, double* x_, const lgdm_solver_opts& o_)
+  KrylovRunImpl(lgdm_ctx* ctx, const double* b_, double* x_, const lgdm_solver_opts& o_, double tu,
+                double te)
       : c(ctx), b(b_), xout(x_), o(o_) {
-    S.c = c;
-    S.n = c->ndof;
-    S.nn = c->n_nodes;
-    const bool mixed = std::is_same<T, float>::value;
-    S.vals = mixed ? (const T*)c->vals32 : (const T*)c->vals;
-    S.minv = mixed ? (const T*)c->minv32 : (const T*)c->minv;
-    void** vp[8] = {&S.V.r, &S.V.rh, &S.V.p, &S.V.v, &S.V.s, &S.V.t, &S.V.ph, &S.V.sh};
-    for (int i = 0; i < 8; ++i) *vp[i] = c->kv + (int64_t)i * c->ndof;
-    S.sc = c->kscal;
-    xbest = c->kv + 8 * c->ndof;
-    tol = o.tol_krylov;
-    if (mixed && tol < 1e-8) tol = 1e-8;  // FP32 matrix; Newton refines on the FP64 residual
+    S.bind(c);
+    xbest = c->kv + (int64_t)(KV_VECS - 1) * c->ndof;
+    // an FP32 matrix gains nothing below 1e-8; Newton refines on the FP64 residual
+    tol_u = Method::F32 && tu < 1e-8 ? 1e-8 : tu;
+    tol_e = Method::F32 && te < 1e-8 ? 1e-8 : te;
     se = c->mat.E / c->mat.h;
     every = o.check_every > 0 ? o.check_every : 16;
     res.status = LGDM_ERR_NOT_CONVERGED;
@@ -587,16 +1047,16 @@ struct KrylovRunImpl final : KrylovRun {
 
   // restart the recurrences from the current iterate with its true residual
   void restart_from_x() {
-    set_scalars_kernel<<<1, 64, 0, c->stream>>>(S.sc, tol * tol, se, break_rel<T>());
-    S.spmv(xout, S.vec(S.V.t), 0, nullptr);
-    S.init(b, true, S.vec(S.V.t));
+    set_scalars_kernel<<<1, 64, 0, c->stream>>>(S.sc, tol_u * tol_u, tol_e * tol_e, se, BREAK_REL);
+    S.restart(b, xout);
+    res.spmv += 1;
   }
 
   hipError_t start() override {
-    set_scalars_kernel<<<1, 64, 0, c->stream>>>(S.sc, tol * tol, se, break_rel<T>());
+    set_scalars_kernel<<<1, 64, 0, c->stream>>>(S.sc, tol_u * tol_u, tol_e * tol_e, se, BREAK_REL);
     hipError_t e = hipMemsetAsync(xout, 0, c->ndof * sizeof(double), c->stream);
     if (e != hipSuccess) return e;
-    S.init(b, false, nullptr);
+    S.begin(b);
     // read the scalars of the initial residual asynchronously
     return hipMemcpyAsync(c->kscal_host, S.sc, K_NSLOTS * sizeof(double), hipMemcpyDeviceToHost,
                           c->stream);
@@ -604,7 +1064,7 @@ struct KrylovRunImpl final : KrylovRun {
 
   hipError_t launch() override {
     if (fin) return hipSuccess;
-    for (int i = 0; i < every; ++i) S.iteration(xout);
+    S.iterate(xout, every);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return hipMemcpyAsync(c->kscal_host, S.sc, K_NSLOTS * sizeof(double), hipMemcpyDeviceToHost,
@@ -619,6 +1079,7 @@ struct KrylovRunImpl final : KrylovRun {
     if (e != hipSuccess) return e;
     const double* h = c->kscal_host;
     res.iters = done_iters + (int64_t)h[K_ITER];
+    res.spmv = res.iters * Method::SPMV_PER_ITER + res.restarts + replacements;
     const double bu = h[K_BU] > 0 ? h[K_BU] : 1.0, be = h[K_BE] > 0 ? h[K_BE] : 1.0;
     res.rel_u = std::sqrt(h[K_RU] / bu);
     res.rel_e = std::sqrt(h[K_RE] / be);
@@ -651,6 +1112,9 @@ struct KrylovRunImpl final : KrylovRun {
       }
       // breakdown: restart from the current iterate with the true residual
       if (res.restarts >= o.max_restarts || res.iters >= o.max_krylov) {
+        // the current iterate is kept unless an earlier one was better
+        if (have_best && !(std::max(res.rel_u / tol_u, res.rel_e / tol_e) <= best))
+          return_best(LGDM_ERR_BREAKDOWN);
         res.status = LGDM_ERR_BREAKDOWN;
         fin = true;
         return hipSuccess;
@@ -664,7 +1128,7 @@ struct KrylovRunImpl final : KrylovRun {
                             c->stream);
     }
     true_residual = false;
-    const double score = std::max(res.rel_u, res.rel_e);
+    const double score = std::max(res.rel_u / tol_u, res.rel_e / tol_e);
     if (std::isfinite(score) && score < best * (1.0 - 1e-3)) {
       best = score;
       stall = 0;
@@ -687,8 +1151,15 @@ struct KrylovRunImpl final : KrylovRun {
 
 template <typename T, int ND>
 std::unique_ptr<KrylovRun> make_run_impl(lgdm_ctx* c, const double* b, double* x,
-                                         const lgdm_solver_opts& o) {
-  return std::unique_ptr<KrylovRun>(new KrylovRunImpl<T, ND>(c, b, x, o));
+                                         const lgdm_solver_opts& o, double tu, double te) {
+  if (o.krylov_method == LGDM_KRYLOV_BICGSTAB)
+    return std::unique_ptr<KrylovRun>(new KrylovRunImpl<Solver<T, ND>>(c, b, x, o, tu, te));
+  switch (o.idr_s) {
+    case 1: return std::unique_ptr<KrylovRun>(new KrylovRunImpl<Idr<T, ND, 1>>(c, b, x, o, tu, te));
+    case 2: return std::unique_ptr<KrylovRun>(new KrylovRunImpl<Idr<T, ND, 2>>(c, b, x, o, tu, te));
+    case 8: return std::unique_ptr<KrylovRun>(new KrylovRunImpl<Idr<T, ND, 8>>(c, b, x, o, tu, te));
+    default: return std::unique_ptr<KrylovRun>(new KrylovRunImpl<Idr<T, ND, 4>>(c, b, x, o, tu, te));
+  }
 }
 
 template <typename T, int ND> hipError_t setup_impl(lgdm_ctx* c) {
@@ -705,6 +1176,22 @@ template <typename T, int ND> hipError_t setup_impl(lgdm_ctx* c) {
 
 }  // namespace
 
+// defaults of zero-initialised solver options
+lgdm_solver_opts fill_opts(const lgdm_solver_opts* o) {
+  lgdm_solver_opts r{};
+  if (o) r = *o;
+  if (r.max_newton <= 0) r.max_newton = 30;
+  if (r.max_krylov <= 0) r.max_krylov = 20000;
+  if (!(r.tol_newton > 0)) r.tol_newton = 1e-8;
+  if (!(r.tol_krylov > 0)) r.tol_krylov = 1e-10;
+  if (r.check_every <= 0) r.check_every = 16;
+  if (r.max_restarts <= 0) r.max_restarts = 8;
+  if (r.krylov_method != LGDM_KRYLOV_BICGSTAB) r.krylov_method = LGDM_KRYLOV_IDRS;
+  if (r.forcing != LGDM_FORCING_FIXED) r.forcing = LGDM_FORCING_ADAPTIVE;
+  r.idr_s = r.idr_s <= 0 ? 4 : (r.idr_s <= 1 ? 1 : (r.idr_s <= 2 ? 2 : (r.idr_s <= 4 ? 4 : 8)));
+  return r;
+}
+
 hipError_t krylov_setup(lgdm_ctx* c) {
   switch (c->nd) {
     case 2: return setup_impl<double, 2>(c);
@@ -714,18 +1201,21 @@ hipError_t krylov_setup(lgdm_ctx* c) {
 }
 
 std::unique_ptr<KrylovRun> make_krylov_run(lgdm_ctx* c, const double* b, double* x,
-                                           const lgdm_solver_opts& o) {
+                                           const lgdm_solver_opts& o, double tol_u, double tol_e) {
   const bool mixed = c->precision == LGDM_MIXED;
   switch (c->nd) {
-    case 2: return mixed ? make_run_impl<float, 2>(c, b, x, o) : make_run_impl<double, 2>(c, b, x, o);
-    case 3: return mixed ? make_run_impl<float, 3>(c, b, x, o) : make_run_impl<double, 3>(c, b, x, o);
-    default: return mixed ? make_run_impl<float, 4>(c, b, x, o) : make_run_impl<double, 4>(c, b, x, o);
+    case 2: return mixed ? make_run_impl<float, 2>(c, b, x, o, tol_u, tol_e)
+                         : make_run_impl<double, 2>(c, b, x, o, tol_u, tol_e);
+    case 3: return mixed ? make_run_impl<float, 3>(c, b, x, o, tol_u, tol_e)
+                         : make_run_impl<double, 3>(c, b, x, o, tol_u, tol_e);
+    default: return mixed ? make_run_impl<float, 4>(c, b, x, o, tol_u, tol_e)
+                          : make_run_impl<double, 4>(c, b, x, o, tol_u, tol_e);
   }
 }
 
 hipError_t krylov_solve(lgdm_ctx* c, const double* b, double* xout, const lgdm_solver_opts& o,
-                        KrylovResult& res) {
-  std::unique_ptr<KrylovRun> run = make_krylov_run(c, b, xout, o);
+                        double tol_u, double tol_e, KrylovResult& res) {
+  std::unique_ptr<KrylovRun> run = make_krylov_run(c, b, xout, o, tol_u, tol_e);
   hipError_t e = run->start();
   while (e == hipSuccess) {
     e = run->check();
@@ -736,16 +1226,34 @@ hipError_t krylov_solve(lgdm_ctx* c, const double* b, double* xout, const lgdm_s
   return e;
 }
 
+// Inexact Newton: the relative tolerances of one Newton correction, per
+// field.  A correction needs no smaller linear residual than a fraction of
+// what the field may keep at convergence: tol_f = max(tol_krylov,
+// min(0.5, c * tol_newton * |F_f| / |R_f|)), so the early corrections solve to
+// tol_krylov and the last one only as far as the Newton test needs.  With an
+// FP32-stored operator the linear residual left in a correction comes back
+// amplified in the next FP64 residual (by up to the FP32 rounding of the
+// tangent times its condition number), so mixed contexts keep a tenfold
+// margin more (c = 0.01 against 0.1).
+void newton_forcing(lgdm_ctx* c, const lgdm_solver_opts& o, double& tol_u, double& tol_e) {
+  tol_u = tol_e = o.tol_krylov;
+  if (o.forcing == LGDM_FORCING_FIXED) return;
+  const double margin = c->precision == LGDM_MIXED ? 0.01 : 0.1;
+  const double ru = std::sqrt(c->last_norms[0]), re = std::sqrt(c->last_norms[1]);
+  const double fu = std::sqrt(c->last_norms[2]), fe = std::sqrt(c->last_norms[3]);
+  if (ru > 0) tol_u = std::max(o.tol_krylov, std::min(0.5, margin * o.tol_newton * fu / ru));
+  if (re > 0) tol_e = std::max(o.tol_krylov, std::min(0.5, margin * o.tol_newton * fe / re));
+}
+
 template <typename T, int ND> hipError_t spmv_only_impl(lgdm_ctx* c, const double* x) {
-  Solver<T, ND> S;
-  S.c = c;
-  S.n = c->ndof;
-  S.nn = c->n_nodes;
-  const bool mixed = std::is_same<T, float>::value;
-  S.vals = mixed ? (const T*)c->vals32 : (const T*)c->vals;
-  S.sc = c->kscal;
-  set_scalars_kernel<<<1, 64, 0, c->stream>>>(S.sc, 0.0, c->mat.E / c->mat.h, break_rel<T>());
-  S.spmv(x, c->kv, 0, nullptr);
+  // the operator application of an IDR(4) step (SpMV with its four shadow
+  // dot products and |y|^2), the launch that dominates a default solve
+  using I = Idr<T, ND, 4>;
+  I S;
+  S.bind(c);
+  set_scalars_kernel<<<1, 64, 0, c->stream>>>(S.sc, 0.0, 0.0, c->mat.E / c->mat.h, BREAK_REL);
+  spmv_kernel<T, ND, I::G, I::UNR, 3, 4><<<S.spmv_grid(), BS, 0, c->stream>>>(
+      S.nn, c->row_ptr, c->nbr_ptr, c->nbr, S.vals, x, S.t, nullptr, S.sc, c->kpart);
   return hipGetLastError();
 }
 

@@ -87,6 +87,13 @@ struct SlotDesc {
 
 constexpr int NORM_SLOTS = 6;  // |R_u|^2, |R_e|^2, |f_u|^2, |fref_e|^2, reaction, non-finite count
 constexpr int RED_CHUNKS = 1024;  // stage-one workgroups of the two-stage reductions
+// Krylov workspace: IDR(8) needs r, v, t and 8 + 8 direction vectors; the
+// last vector holds the best iterate.  BiCGSTAB uses the first 8.
+constexpr int IDR_SMAX = 8;
+constexpr int KV_VECS = 3 + 2 * IDR_SMAX + 1;
+constexpr int KSCAL_DOUBLES = 128;     // device scalar slots of a solve
+constexpr int KPART_PER_BLOCK = 16;    // partial sums per workgroup (at most 4 + IDR_SMAX)
+constexpr int KPART_BLOCKS = 2048;     // workgroups of a Krylov vector kernel, at most
 
 }  // namespace lgdm
 
@@ -150,7 +157,7 @@ struct lgdm_ctx {
   double last_norms[lgdm::NORM_SLOTS] = {0, 0, 0, 0, 0, 0};
 
   // Krylov workspace (H6)
-  double* kv = nullptr;            // 8 FP64 Krylov vectors + the best iterate, ndof each
+  double* kv = nullptr;            // KV_VECS FP64 Krylov vectors (the last: best iterate), ndof each
   double* minv = nullptr;          // block-Jacobi inverses [n_nodes * nd * nd]
   float* minv32 = nullptr;
   double* kpart = nullptr;         // per-block partial sums
@@ -197,6 +204,7 @@ struct KrylovResult {
   int64_t iters;
   int restarts;
   double rel_u, rel_e;
+  int64_t spmv;        // operator applications
 };
 // one linear solve as a state machine (see krylov.hip)
 struct KrylovRun {
@@ -209,10 +217,13 @@ struct KrylovRun {
   virtual const KrylovResult& result() const = 0;
 };
 std::unique_ptr<KrylovRun> make_krylov_run(lgdm_ctx* c, const double* b, double* x,
-                                           const lgdm_solver_opts& o);
+                                           const lgdm_solver_opts& o, double tol_u, double tol_e);
+// per-field relative tolerances of the next Newton correction
+void newton_forcing(lgdm_ctx* c, const lgdm_solver_opts& o, double& tol_u, double& tol_e);
+lgdm_solver_opts fill_opts(const lgdm_solver_opts* o);  // defaults for zero fields
 hipError_t krylov_setup(lgdm_ctx* c);  // block-Jacobi from the assembled matrix
 hipError_t krylov_solve(lgdm_ctx* c, const double* b, double* xout, const lgdm_solver_opts& o,
-                        KrylovResult& res);
+                        double tol_u, double tol_e, KrylovResult& res);
 hipError_t launch_spmv_only(lgdm_ctx* c, const double* x, double* scratch);  // y = S K x
 hipError_t launch_axpy(lgdm_ctx* c, double* y, const double* x, double a, int64_t n);
 hipError_t launch_field_norms(lgdm_ctx* c, const double* v, double* out_dev);  // |v_u|^2, |v_e|^2

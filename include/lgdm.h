@@ -174,8 +174,10 @@ const char* lgdm_last_error(const lgdm_ctx* ctx);
 
 /* Route the context's device allocations through a caller allocator (e.g.
  * PyTorch's caching allocator).  alloc(bytes, user) returns a device pointer
- * or NULL; free(ptr, user) releases it.  Must be called before
- * lgdm_upload_mesh.  Without it the library uses hipMalloc / hipFree. */
+ * aligned to at least 32 bytes, or NULL; free(ptr, user) releases it.  Must
+ * be called before lgdm_upload_mesh, which fails with LGDM_ERR_INVALID_ARG if
+ * an allocation is not 32-byte aligned.  Without it the library uses
+ * hipMalloc / hipFree. */
 lgdm_status lgdm_set_allocator(lgdm_ctx* ctx, void* (*alloc)(size_t, void*),
                                void (*free_fn)(void*, void*), void* user);
 

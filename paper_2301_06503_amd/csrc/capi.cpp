@@ -293,6 +293,13 @@ lgdm_status lgdm_upload_mesh(lgdm_ctx* c, int32_t dim, int32_t elem_type, int64_
     free_mesh(c);
     return fail(c, LGDM_ERR_OOM, "device allocation failed (state / matrix / solver)");
   }
+  // the SpMV reads blocks of the CSR values and of x as 4-wide vectors
+  for (const void* p : {(const void*)c->x, (const void*)c->delta, (const void*)c->kv, (const void*)c->vals,
+                        (const void*)c->vals32, (const void*)c->minv, (const void*)c->minv32})
+    if (reinterpret_cast<uintptr_t>(p) % 32 != 0) {
+      free_mesh(c);
+      return fail(c, LGDM_ERR_INVALID_ARG, "the allocator returned memory not aligned to 32 bytes");
+    }
   HIPCHECK(c, zero(c, c->x, nd * sizeof(double)), "zero");
   HIPCHECK(c, zero(c, c->x_save, nd * sizeof(double)), "zero");
   HIPCHECK(c, zero(c, c->R, nd * sizeof(double)), "zero");

@@ -113,14 +113,79 @@ __device__ __forceinline__ double shadow_entry(int q, int64_t j) {
   return (double)(z >> 11) * 0x1.0p-52 - 1.0;
 }
 
+// ND consecutive values as one load: 4-wide vectors for the 3D blocks (the
+// row blocks of a node start at multiples of 16 values and every vector the
+// library allocates is 32-byte aligned), element by element otherwise
+template <typename T, int ND> struct Quad {
+  T v[ND];
+  __device__ __forceinline__ void load(const T* __restrict__ p) {
+#pragma unroll
+    for (int c = 0; c < ND; ++c) v[c] = p[c];
+  }
+  __device__ __forceinline__ void store(T* __restrict__ p) const {
+#pragma unroll
+    for (int c = 0; c < ND; ++c) p[c] = v[c];
+  }
+};
+template <> struct Quad<float, 4> {
+  float v[4];
+  __device__ __forceinline__ void load(const float* __restrict__ p) {
+    const float4 q = *reinterpret_cast<const float4*>(p);
+    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+  }
+};
+template <> struct Quad<double, 4> {
+  double v[4];
+  __device__ __forceinline__ void load(const double* __restrict__ p) {
+    const double4 q = *reinterpret_cast<const double4*>(p);
+    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+  }
+  __device__ __forceinline__ void store(double* __restrict__ p) const {
+    *reinterpret_cast<double4*>(p) = make_double4(v[0], v[1], v[2], v[3]);
+  }
+};
+
+// Sum the ND per-lane values acc over the G lanes of a group.  Returns the
+// row this lane holds the total of, or -1.  ND = 4: each of the first two
+// butterfly stages exchanges only the half of the values the partner keeps
+// (7 exchanges instead of 4 log2 G); rows end in lanes 0, G/4, G/2, 3G/4.
+template <int ND, int G>
+__device__ __forceinline__ int group_rows(double (&acc)[ND], int lane, double& total) {
+  if (ND == 4 && G >= 4) {
+    const bool h1 = lane & (G / 2);
+    double k0 = h1 ? acc[2] : acc[0], k1 = h1 ? acc[3] : acc[1];
+    const double s0 = h1 ? acc[0] : acc[2], s1 = h1 ? acc[1] : acc[3];
+    k0 += __shfl_xor(s0, G / 2, G);
+    k1 += __shfl_xor(s1, G / 2, G);
+    const bool h2 = lane & (G / 4);
+    double k = h2 ? k1 : k0;
+    const double s = h2 ? k0 : k1;
+    k += __shfl_xor(s, G / 4, G);
+#pragma unroll
+    for (int o = G / 8; o > 0; o >>= 1) k += __shfl_xor(k, o, G);
+    total = k;
+    return (lane % (G / 4)) == 0 ? (h1 ? 2 : 0) + (h2 ? 1 : 0) : -1;
+  }
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1)
+#pragma unroll
+    for (int r = 0; r < ND; ++r) acc[r] += __shfl_xor(acc[r], o, G);
+  total = acc[0];
+#pragma unroll
+  for (int r = 1; r < ND; ++r)
+    if (lane == r) total = acc[r];
+  return lane < ND ? lane : -1;
+}
+
 // y = S A x (+ optional dots).  One group of G lanes per node a computes the
-// ND rows of the node together: lane v takes column v of the node's row block
-// (neighbour q = v / ND, component c = v % ND), gathers x once and multiplies
-// it into the ND rows (coalesced reads of each row), then the group reduces
-// its ND sums.  Grid-stride over nodes.
+// ND rows of the node together.  Lane q takes neighbour q of a (ascending):
+// it reads the neighbour's ND entries of x and, from each of the node's ND
+// rows, the ND values of the (row, neighbour) block (row r of node a lists
+// neighbour q's columns at r * len + q * ND), so x is gathered once per
+// neighbour and every read is ND values wide.  Grid-stride over nodes.
 // MODE 0: no dots; 1: dot(rh, y), |y|^2; 2: dot(y, s), |y|^2;
 // 3: the NP shadow-vector dots P_q . y and |y|^2 (IDR)
-template <typename T, int ND, int G, int UNR, int MODE, int NP = 0>
+template <typename T, int ND, int G, int MODE, int NP = 0>
 __global__ void __launch_bounds__(BS) spmv_kernel(int64_t n_nodes, const int32_t* __restrict__ row_ptr,
                                                   const int32_t* __restrict__ nbr_ptr,
                                                   const int32_t* __restrict__ nbr,
@@ -141,47 +206,30 @@ __global__ void __launch_bounds__(BS) spmv_kernel(int64_t n_nodes, const int32_t
   for (int q = 0; q < NQ; ++q) d[q] = 0.0;
   for (int64_t a = grp; a < n_nodes; a += ngrp) {
     const int32_t p0 = nbr_ptr[a];
-    const int len = (nbr_ptr[a + 1] - p0) * ND;
+    const int nnb = nbr_ptr[a + 1] - p0;
+    const int len = nnb * ND;
     const T* __restrict__ rv = vals + row_ptr[a * ND];
-    const int32_t* __restrict__ nb = nbr + p0;
     // stored values of type T (FP32 in mixed contexts), FP64 arithmetic:
     // the operator is the fixed linear map of the stored matrix
     double acc[ND];
 #pragma unroll
     for (int r = 0; r < ND; ++r) acc[r] = 0.0;
-    for (int v0 = lane; v0 < len; v0 += UNR * G) {
-      double xv[UNR];
-      T mv[UNR][ND];
+    for (int q = lane; q < nnb; q += G) {
+      Quad<double, ND> xq;
+      xq.load(x + (int64_t)nbr[p0 + q] * ND);
 #pragma unroll
-      for (int u = 0; u < UNR; ++u) {
-        const int v = v0 + u * G;
-        if (v < len) {
-          const int q = v / ND, c = v - q * ND;
-          xv[u] = x[(int64_t)nb[q] * ND + c];
+      for (int r = 0; r < ND; ++r) {
+        Quad<T, ND> m;
+        m.load(rv + r * len + q * ND);
 #pragma unroll
-          for (int r = 0; r < ND; ++r) mv[u][r] = rv[r * len + v];
-        } else {
-          xv[u] = 0.0;
-#pragma unroll
-          for (int r = 0; r < ND; ++r) mv[u][r] = (T)0;
-        }
+        for (int cc = 0; cc < ND; ++cc) acc[r] += (double)m.v[cc] * xq.v[cc];
       }
-#pragma unroll
-      for (int u = 0; u < UNR; ++u)
-#pragma unroll
-        for (int r = 0; r < ND; ++r) acc[r] += (double)mv[u][r] * xv[u];
     }
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1)
-#pragma unroll
-      for (int r = 0; r < ND; ++r) acc[r] += __shfl_xor(acc[r], o, G);
-    if (lane < ND) {
-      double mine = acc[0];
-#pragma unroll
-      for (int r = 1; r < ND; ++r)
-        if (lane == r) mine = acc[r];
-      const int64_t row = a * ND + lane;
-      const double yt = mine * (lane == ND - 1 ? se : 1.0);
+    double total;
+    const int rr = group_rows<ND, G>(acc, lane, total);
+    if (rr >= 0) {
+      const int64_t row = a * ND + rr;
+      const double yt = total * (rr == ND - 1 ? se : 1.0);
       y[row] = yt;
       if (MODE == 1) {
         d[0] += w[row] * yt;
@@ -610,43 +658,50 @@ __global__ void __launch_bounds__(BS) idr_init_scalar(int nblk, const double* __
   idr_coeffs<S>(sc, 0);
 }
 
-// step k: v = r - sum_j c_j G_{k+j};  U_k = sum_j c_j U_{k+j} + omega M^-1 v.
-// In the first cycle after a (re)start every G, U term is zero (fresh).
-template <typename T, int ND, int S>
-__global__ void __launch_bounds__(BS) idr_dir_kernel(int64_t n_nodes, int k, int fresh,
-                                                     const T* __restrict__ minv, const double* __restrict__ r,
-                                                     const double* __restrict__ Gv, double* __restrict__ Uv,
-                                                     int64_t n, const double* __restrict__ sc) {
+// step K: v = r - sum_j c_j G_{K+j};  U_K = sum_j c_j U_{K+j} + omega M^-1 v.
+// In the first cycle after a (re)start every G, U term is zero (FRESH).
+// One thread per node; the node's ND entries of each vector are one load.
+template <typename T, int ND, int S, int K, bool FRESH>
+__global__ void __launch_bounds__(BS) idr_dir_kernel(int64_t n_nodes, const T* __restrict__ minv,
+                                                     const double* __restrict__ r, const double* __restrict__ Gv,
+                                                     double* __restrict__ Uv, int64_t n,
+                                                     const double* __restrict__ sc) {
   if (sc[K_DONE] != 0.0) return;
-  const int nc = fresh ? 0 : S - k;
-  double cc[S];
+  constexpr int NC = FRESH ? 0 : S - K;
+  double cc[NC > 0 ? NC : 1];
 #pragma unroll
-  for (int j = 0; j < S; ++j) cc[j] = j < nc ? sc[I_C + j] : 0.0;
+  for (int j = 0; j < NC; ++j) cc[j] = sc[I_C + j];
   const double om = sc[I_OM];
   for (int64_t a = (int64_t)blockIdx.x * BS + threadIdx.x; a < n_nodes; a += (int64_t)gridDim.x * BS) {
-    double v[ND];
+    const int64_t o = a * ND;
+    Quad<double, ND> v;
+    v.load(r + o);
 #pragma unroll
-    for (int i = 0; i < ND; ++i) {
-      const int64_t row = a * ND + i;
-      double s = r[row];
+    for (int j = 0; j < NC; ++j) {
+      Quad<double, ND> g;
+      g.load(Gv + (int64_t)(K + j) * n + o);
 #pragma unroll
-      for (int j = 0; j < S; ++j)
-        if (j < nc) s -= cc[j] * Gv[(int64_t)(k + j) * n + row];
-      v[i] = s;
+      for (int i = 0; i < ND; ++i) v.v[i] -= cc[j] * g.v[i];
     }
-    const T* m = minv + a * ND * ND;
+    Quad<T, ND> m[ND];
+#pragma unroll
+    for (int i = 0; i < ND; ++i) m[i].load(minv + a * ND * ND + i * ND);
+    Quad<double, ND> u;
 #pragma unroll
     for (int i = 0; i < ND; ++i) {
-      const int64_t row = a * ND + i;
       double vh = 0.0;
 #pragma unroll
-      for (int j = 0; j < ND; ++j) vh += (double)m[i * ND + j] * v[j];
-      double u = om * vh;
-#pragma unroll
-      for (int j = 0; j < S; ++j)
-        if (j < nc) u += cc[j] * Uv[(int64_t)(k + j) * n + row];
-      Uv[(int64_t)k * n + row] = u;
+      for (int jj = 0; jj < ND; ++jj) vh += (double)m[i].v[jj] * v.v[jj];
+      u.v[i] = om * vh;
     }
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      Quad<double, ND> uj;
+      uj.load(Uv + (int64_t)(K + j) * n + o);
+#pragma unroll
+      for (int i = 0; i < ND; ++i) u.v[i] += cc[j] * uj.v[i];
+    }
+    u.store(Uv + (int64_t)K * n + o);
   }
 }
 
@@ -689,52 +744,67 @@ __global__ void __launch_bounds__(BS) idr_g_scalar(int nblk, const double* __res
   if (k + 1 < S) idr_coeffs<S>(sc, k + 1);
 }
 
-// G_k -= sum_{i<k} a_i G_i, U_k likewise; r -= beta G_k; x += beta U_k;
-// LAST (k = s - 1): v = M^-1 r for the minimal-residual step.  Partials
-// |r_u|^2, |r_e|^2.
-template <typename T, int ND, int S, bool LAST>
-__global__ void __launch_bounds__(BS) idr_upd_kernel(int64_t n_nodes, int k, const T* __restrict__ minv,
+// G_K -= sum_{i<K} a_i G_i, U_K likewise; r -= beta G_K; x += beta U_K;
+// the last step (K = s - 1) also forms v = M^-1 r for the minimal-residual
+// step.  Partials |r_u|^2, |r_e|^2.
+template <typename T, int ND, int S, int K>
+__global__ void __launch_bounds__(BS) idr_upd_kernel(int64_t n_nodes, const T* __restrict__ minv,
                                                      double* __restrict__ Gv, double* __restrict__ Uv,
                                                      double* __restrict__ r, double* __restrict__ x,
                                                      double* __restrict__ v, int64_t n,
                                                      const double* __restrict__ sc, double* __restrict__ part) {
+  constexpr bool LAST = (K == S - 1);
   __shared__ double sm[2][BS];
   if (sc[K_DONE] != 0.0) return;
-  double aa[S];
+  double aa[K > 0 ? K : 1];
 #pragma unroll
-  for (int i = 0; i < S; ++i) aa[i] = i < k ? sc[I_A + i] : 0.0;
+  for (int i = 0; i < K; ++i) aa[i] = sc[I_A + i];
   const double beta = sc[I_BETA];
   double d[2] = {0.0, 0.0};
   for (int64_t a = (int64_t)blockIdx.x * BS + threadIdx.x; a < n_nodes; a += (int64_t)gridDim.x * BS) {
-    double rn[ND];
+    const int64_t o = a * ND;
+    Quad<double, ND> g, u;
+    g.load(Gv + (int64_t)K * n + o);
+    u.load(Uv + (int64_t)K * n + o);
+    if (K > 0) {
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        Quad<double, ND> gj, uj;
+        gj.load(Gv + (int64_t)j * n + o);
+        uj.load(Uv + (int64_t)j * n + o);
+#pragma unroll
+        for (int i = 0; i < ND; ++i) {
+          g.v[i] -= aa[j] * gj.v[i];
+          u.v[i] -= aa[j] * uj.v[i];
+        }
+      }
+      g.store(Gv + (int64_t)K * n + o);
+      u.store(Uv + (int64_t)K * n + o);
+    }
+    Quad<double, ND> rn, xn;
+    rn.load(r + o);
+    xn.load(x + o);
 #pragma unroll
     for (int i = 0; i < ND; ++i) {
-      const int64_t row = a * ND + i;
-      double g = Gv[(int64_t)k * n + row], u = Uv[(int64_t)k * n + row];
-      if (k > 0) {
-#pragma unroll
-        for (int j = 0; j < S; ++j)
-          if (j < k) {
-            g -= aa[j] * Gv[(int64_t)j * n + row];
-            u -= aa[j] * Uv[(int64_t)j * n + row];
-          }
-        Gv[(int64_t)k * n + row] = g;
-        Uv[(int64_t)k * n + row] = u;
-      }
-      rn[i] = r[row] - beta * g;
-      r[row] = rn[i];
-      x[row] += beta * u;
-      d[i == ND - 1 ? 1 : 0] += rn[i] * rn[i];
+      rn.v[i] -= beta * g.v[i];
+      xn.v[i] += beta * u.v[i];
+      d[i == ND - 1 ? 1 : 0] += rn.v[i] * rn.v[i];
     }
+    rn.store(r + o);
+    xn.store(x + o);
     if (LAST) {
-      const T* m = minv + a * ND * ND;
+      Quad<T, ND> m[ND];
+#pragma unroll
+      for (int i = 0; i < ND; ++i) m[i].load(minv + a * ND * ND + i * ND);
+      Quad<double, ND> vh;
 #pragma unroll
       for (int i = 0; i < ND; ++i) {
-        double vh = 0.0;
+        double acc = 0.0;
 #pragma unroll
-        for (int j = 0; j < ND; ++j) vh += (double)m[i * ND + j] * rn[j];
-        v[a * ND + i] = vh;
+        for (int jj = 0; jj < ND; ++jj) acc += (double)m[i].v[jj] * rn.v[jj];
+        vh.v[i] = acc;
       }
+      vh.store(v + o);
     }
   }
   write_partials<2>(d, part, sm);
@@ -848,13 +918,11 @@ template <typename K> int64_t grid_of(K kernel, int64_t work) {
 
 template <typename T, int ND>
 struct Solver {
-  // lanes per node in the SpMV and unroll depth: row blocks hold up to
-  // 27 x 4 (hex8), 9 x 3 (quad4) and 3 x 2 (line2) columns, so G * UNR
-  // covers a hex8 row block in one unrolled pass (measured on the 3D beam:
-  // FP32 values favour a full wave per node, FP64 two nodes per wave)
+  // lanes per node in the SpMV (one per neighbour): nodes have up to 27
+  // (hex8), 9 (quad4) and 3 (line2) neighbours; on the 3D beam 16 lanes
+  // (two passes, four nodes per wave) beat 32 by a few per cent
   static constexpr bool F32 = std::is_same<T, float>::value;
-  static constexpr int G = ND == 4 ? (F32 ? 64 : 32) : (ND == 3 ? 8 : 2);
-  static constexpr int UNR = ND == 4 ? (F32 ? 2 : 4) : 4;
+  static constexpr int G = ND == 4 ? 16 : (ND == 3 ? 16 : 4);
   lgdm_ctx* c;
   const T* vals;
   const T* minv;
@@ -866,17 +934,17 @@ struct Solver {
 
   void spmv(const double* x, double* y, int mode, const double* w) {
     if (mode == 0) {
-      const int64_t g = grid_of(spmv_kernel<T, ND, G, UNR, 0>, nn * G);
-      spmv_kernel<T, ND, G, UNR, 0><<<g, BS, 0, c->stream>>>(nn, c->row_ptr, c->nbr_ptr, c->nbr, vals, x, y,
+      const int64_t g = grid_of(spmv_kernel<T, ND, G, 0>, nn * G);
+      spmv_kernel<T, ND, G, 0><<<g, BS, 0, c->stream>>>(nn, c->row_ptr, c->nbr_ptr, c->nbr, vals, x, y,
                                                         w, sc, c->kpart);
     } else if (mode == 1) {
-      const int64_t g = grid_of(spmv_kernel<T, ND, G, UNR, 1>, nn * G);
-      spmv_kernel<T, ND, G, UNR, 1><<<g, BS, 0, c->stream>>>(nn, c->row_ptr, c->nbr_ptr, c->nbr, vals, x, y,
+      const int64_t g = grid_of(spmv_kernel<T, ND, G, 1>, nn * G);
+      spmv_kernel<T, ND, G, 1><<<g, BS, 0, c->stream>>>(nn, c->row_ptr, c->nbr_ptr, c->nbr, vals, x, y,
                                                         w, sc, c->kpart);
       scalar_kernel<1, 2><<<1, BS, 0, c->stream>>>((int)g, c->kpart, sc);
     } else {
-      const int64_t g = grid_of(spmv_kernel<T, ND, G, UNR, 2>, nn * G);
-      spmv_kernel<T, ND, G, UNR, 2><<<g, BS, 0, c->stream>>>(nn, c->row_ptr, c->nbr_ptr, c->nbr, vals, x, y,
+      const int64_t g = grid_of(spmv_kernel<T, ND, G, 2>, nn * G);
+      spmv_kernel<T, ND, G, 2><<<g, BS, 0, c->stream>>>(nn, c->row_ptr, c->nbr_ptr, c->nbr, vals, x, y,
                                                         w, sc, c->kpart);
       scalar_kernel<2, 2><<<1, BS, 0, c->stream>>>((int)g, c->kpart, sc);
     }
@@ -930,7 +998,6 @@ template <typename T, int ND, int S>
 struct Idr {
   static constexpr bool F32 = std::is_same<T, float>::value;
   static constexpr int G = Solver<T, ND>::G;
-  static constexpr int UNR = Solver<T, ND>::UNR;
   static constexpr int SPMV_PER_ITER = 1;
   lgdm_ctx* c = nullptr;
   const T* vals = nullptr;
@@ -953,7 +1020,7 @@ struct Idr {
     Uv = c->kv + (3 + S) * n;
     sc = c->kscal;
   }
-  int64_t spmv_grid() const { return grid_of(spmv_kernel<T, ND, G, UNR, 3, S>, nn * G); }
+  int64_t spmv_grid() const { return grid_of(spmv_kernel<T, ND, G, 3, S>, nn * G); }
   void init(const double* b, const double* y) {
     const int64_t g = grid_of(idr_init_kernel<ND, S>, n);
     idr_init_kernel<ND, S><<<g, BS, 0, c->stream>>>(n, b, y, y ? 1 : 0, r, sc, c->kpart);
@@ -962,32 +1029,37 @@ struct Idr {
   }
   void begin(const double* b) { init(b, nullptr); }
   void restart(const double* b, const double* x) {
-    spmv_kernel<T, ND, G, UNR, 0><<<grid_of(spmv_kernel<T, ND, G, UNR, 0>, nn * G), BS, 0, c->stream>>>(
+    spmv_kernel<T, ND, G, 0><<<grid_of(spmv_kernel<T, ND, G, 0>, nn * G), BS, 0, c->stream>>>(
         nn, c->row_ptr, c->nbr_ptr, c->nbr, vals, x, t, nullptr, sc, c->kpart);
     init(b, t);
   }
-  void cycle(double* x) {
-    const int64_t gd = grid_of(idr_dir_kernel<T, ND, S>, nn), gs = spmv_grid();
-    const int64_t gu = grid_of(idr_upd_kernel<T, ND, S, false>, nn);
-    const int64_t gl = grid_of(idr_upd_kernel<T, ND, S, true>, nn);
-    const int64_t gm = grid_of(spmv_kernel<T, ND, G, UNR, 2>, nn * G), g = grid_of(idr_om_kernel<ND, S>, n);
-    const double pnorm2 = (double)n / 3.0;  // E|P_k|^2 of uniform [-1, 1) entries
-    for (int k = 0; k < S; ++k) {
-      idr_dir_kernel<T, ND, S><<<gd, BS, 0, c->stream>>>(nn, k, fresh ? 1 : 0, minv, r, Gv, Uv, n, sc);
-      double* gk = Gv + (int64_t)k * n;
-      spmv_kernel<T, ND, G, UNR, 3, S><<<gs, BS, 0, c->stream>>>(nn, c->row_ptr, c->nbr_ptr, c->nbr, vals,
-                                                                 Uv + (int64_t)k * n, gk, nullptr, sc,
-                                                                 c->kpart);
-      idr_g_scalar<S><<<1, BS, 0, c->stream>>>((int)gs, c->kpart, sc, k, pnorm2);
-      if (k + 1 < S)
-        idr_upd_kernel<T, ND, S, false><<<gu, BS, 0, c->stream>>>(nn, k, minv, Gv, Uv, r, x, v, n, sc,
-                                                                   c->kpart);
-      else
-        idr_upd_kernel<T, ND, S, true><<<gl, BS, 0, c->stream>>>(nn, k, minv, Gv, Uv, r, x, v, n, sc,
-                                                                  c->kpart);
-      idr_r_scalar<<<1, BS, 0, c->stream>>>((int)(k + 1 < S ? gu : gl), c->kpart, sc);
+  // the s steps of a cycle, each with its compile-time index K
+  template <int K> void steps(double* x, int64_t gs, double pnorm2) {
+    if constexpr (K < S) {
+      if (fresh) {
+        auto kd = idr_dir_kernel<T, ND, S, K, true>;
+        kd<<<grid_of(kd, nn), BS, 0, c->stream>>>(nn, minv, r, Gv, Uv, n, sc);
+      } else {
+        auto kd = idr_dir_kernel<T, ND, S, K, false>;
+        kd<<<grid_of(kd, nn), BS, 0, c->stream>>>(nn, minv, r, Gv, Uv, n, sc);
+      }
+      spmv_kernel<T, ND, G, 3, S><<<gs, BS, 0, c->stream>>>(nn, c->row_ptr, c->nbr_ptr, c->nbr, vals,
+                                                            Uv + (int64_t)K * n, Gv + (int64_t)K * n, nullptr,
+                                                            sc, c->kpart);
+      idr_g_scalar<S><<<1, BS, 0, c->stream>>>((int)gs, c->kpart, sc, K, pnorm2);
+      auto ku = idr_upd_kernel<T, ND, S, K>;
+      const int64_t gu = grid_of(ku, nn);
+      ku<<<gu, BS, 0, c->stream>>>(nn, minv, Gv, Uv, r, x, v, n, sc, c->kpart);
+      idr_r_scalar<<<1, BS, 0, c->stream>>>((int)gu, c->kpart, sc);
+      steps<K + 1>(x, gs, pnorm2);
     }
-    spmv_kernel<T, ND, G, UNR, 2><<<gm, BS, 0, c->stream>>>(nn, c->row_ptr, c->nbr_ptr, c->nbr, vals, v, t, r,
+  }
+  void cycle(double* x) {
+    const int64_t gs = spmv_grid();
+    const int64_t gm = grid_of(spmv_kernel<T, ND, G, 2>, nn * G), g = grid_of(idr_om_kernel<ND, S>, n);
+    const double pnorm2 = (double)n / 3.0;  // E|P_k|^2 of uniform [-1, 1) entries
+    steps<0>(x, gs, pnorm2);
+    spmv_kernel<T, ND, G, 2><<<gm, BS, 0, c->stream>>>(nn, c->row_ptr, c->nbr_ptr, c->nbr, vals, v, t, r,
                                                             sc, c->kpart);
     idr_om_scalar<<<1, BS, 0, c->stream>>>((int)gm, c->kpart, sc);
     idr_om_kernel<ND, S><<<g, BS, 0, c->stream>>>(n, r, x, v, t, sc, c->kpart);
@@ -1252,7 +1324,7 @@ template <typename T, int ND> hipError_t spmv_only_impl(lgdm_ctx* c, const doubl
   I S;
   S.bind(c);
   set_scalars_kernel<<<1, 64, 0, c->stream>>>(S.sc, 0.0, 0.0, c->mat.E / c->mat.h, BREAK_REL);
-  spmv_kernel<T, ND, I::G, I::UNR, 3, 4><<<S.spmv_grid(), BS, 0, c->stream>>>(
+  spmv_kernel<T, ND, I::G, 3, 4><<<S.spmv_grid(), BS, 0, c->stream>>>(
       S.nn, c->row_ptr, c->nbr_ptr, c->nbr, S.vals, x, S.t, nullptr, S.sc, c->kpart);
   return hipGetLastError();
 }

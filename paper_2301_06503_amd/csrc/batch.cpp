@@ -1,8 +1,9 @@
 // Continuous batching of LGDM simulation requests on one device: slots with
 // resident per-request state, admission by HBM footprint, one fused launch of
-// each element kernel per tick over all running requests, and per-slot
-// BiCGSTAB runs on per-slot streams interleaved by the host so that their
-// kernels overlap on the device.
+// each element kernel per tick over all running requests, and one batched
+// IDR(s) run over all the requests' linear solves (each kernel one launch
+// over every request; BiCGSTAB runs instead go per request on per-slot
+// streams, interleaved by the host).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,6 +34,7 @@ struct Slot {
   int last_status = LGDM_OK;
   std::unique_ptr<KrylovRun> run;
   bool solving = false;
+  double tol_u = 0.0, tol_e = 0.0;
   KrylovResult kres{};
 };
 
@@ -48,6 +50,7 @@ struct lgdm_batch {
   SlotDesc* desc_host = nullptr;  // pinned
   SlotDesc* desc_dev = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  BatchSolveBuffers bsolve;     // the batched IDR(s) solves of a tick
   std::string err;
 };
 
@@ -145,7 +148,8 @@ lgdm_status lgdm_batch_create(lgdm_batch** out, int32_t device, void* hip_stream
   b->budget = hbm_budget_bytes;
   if (hipHostMalloc((void**)&b->desc_host, max_slots * sizeof(SlotDesc), hipHostMallocDefault) != hipSuccess ||
       hipMalloc((void**)&b->desc_dev, max_slots * sizeof(SlotDesc)) != hipSuccess ||
-      hipEventCreate(&b->ev0) != hipSuccess || hipEventCreate(&b->ev1) != hipSuccess) {
+      hipEventCreate(&b->ev0) != hipSuccess || hipEventCreate(&b->ev1) != hipSuccess ||
+      batch_solve_alloc(b->bsolve, max_slots) != hipSuccess) {
     lgdm_batch_destroy(b);
     return LGDM_ERR_DEVICE;
   }
@@ -162,6 +166,7 @@ lgdm_status lgdm_batch_destroy(lgdm_batch* b) {
   if (b->desc_dev) (void)hipFree(b->desc_dev);
   if (b->ev0) (void)hipEventDestroy(b->ev0);
   if (b->ev1) (void)hipEventDestroy(b->ev1);
+  batch_solve_free(b->bsolve);
   delete b;
   return LGDM_OK;
 }
@@ -307,35 +312,74 @@ lgdm_status lgdm_batch_tick(lgdm_batch* b, const lgdm_solver_opts* o, lgdm_tick_
     BHIP(b, krylov_setup(c), "block-Jacobi setup");
     double tol_u = op.tol_krylov, tol_e = op.tol_krylov;
     newton_forcing(c, op, tol_u, tol_e);
-    s.run = make_krylov_run(c, c->R, c->delta, op, tol_u, tol_e);
-    BHIP(b, s.run->start(), "Krylov start");
+    if (op.krylov_method == LGDM_KRYLOV_BICGSTAB) {
+      s.run = make_krylov_run(c, c->R, c->delta, op, tol_u, tol_e);
+      BHIP(b, s.run->start(), "Krylov start");
+    }
+    s.tol_u = tol_u;
+    s.tol_e = tol_e;
     s.solving = true;
     R.solves++;
   }
-  // 4. interleave the solves: each slot's iterations go to its own stream
-  bool pending = true;
-  while (pending) {
-    pending = false;
+  // 4. the solves
+  if (op.krylov_method == LGDM_KRYLOV_BICGSTAB) {
+    // one run per request on its own stream, interleaved by the host
+    bool pending = true;
+    while (pending) {
+      pending = false;
+      for (int i : act) {
+        Slot& s = b->slots[i];
+        if (!s.solving || !s.run) continue;
+        BHIP(b, s.run->check(), "Krylov check");
+        if (s.run->finished()) continue;
+        pending = true;
+        if (!s.run->needs_check()) BHIP(b, s.run->launch(), "Krylov iterations");
+      }
+    }
     for (int i : act) {
       Slot& s = b->slots[i];
-      if (!s.solving || !s.run) continue;
-      BHIP(b, s.run->check(), "Krylov check");
-      if (s.run->finished()) continue;
-      pending = true;
-      if (!s.run->needs_check()) BHIP(b, s.run->launch(), "Krylov iterations");
+      if (!s.solving) continue;
+      s.kres = s.run->result();
+      s.run.reset();
+    }
+  } else {
+    // IDR(s): one batched run, every kernel one launch over all requests
+    std::vector<lgdm_ctx*> cs;
+    std::vector<double> tu, te;
+    std::vector<int> who;
+    for (int i : act) {
+      Slot& s = b->slots[i];
+      if (!s.solving) continue;
+      BHIP(b, hipStreamSynchronize(s.stream), "block-Jacobi setup");
+      cs.push_back(s.ctx);
+      tu.push_back(s.tol_u);
+      te.push_back(s.tol_e);
+      who.push_back(i);
+    }
+    if (!cs.empty()) {
+      std::unique_ptr<BatchRun> run = make_batch_run(b->stream, cs, tu, te, op, b->bsolve);
+      if (!run) return bfail(b, LGDM_ERR_INVALID_ARG, "batched solve: requests of mixed type");
+      BHIP(b, run->start(), "batched Krylov start");
+      while (!run->finished()) BHIP(b, run->advance(), "batched Krylov iterations");
+      // the last round may have enqueued copies of best iterates
+      BHIP(b, hipStreamSynchronize(b->stream), "batched Krylov");
+      for (size_t j = 0; j < who.size(); ++j) b->slots[who[j]].kres = run->result((int)j);
     }
   }
   // 5. Newton update of the solved requests
   for (int i : act) {
     Slot& s = b->slots[i];
     if (!s.solving) continue;
-    s.kres = s.run->result();
-    s.run.reset();
     s.solving = false;
     R.krylov_iters += s.kres.iters;
     s.krylov_total += s.kres.iters;
     if (s.kres.status == LGDM_ERR_NAN) {
       fail_slot(s, LGDM_ERR_NAN);
+      continue;
+    }
+    if (s.kres.status != LGDM_OK && !s.kres.improved) {
+      // a correction no better than none would repeat this iteration unchanged
+      fail_slot(s, LGDM_ERR_NOT_CONVERGED);
       continue;
     }
     BHIP(b, launch_axpy(s.ctx, s.ctx->x, s.ctx->delta, 1.0, s.ctx->ndof), "update");

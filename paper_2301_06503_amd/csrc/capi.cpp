@@ -126,6 +126,7 @@ lgdm_status linear_solve(lgdm_ctx* c, const double* b_dev, double* x_dev, const 
   HIPCHECK(c, krylov_setup(c), "block-Jacobi setup");
   KrylovResult kr{};
   HIPCHECK(c, krylov_solve(c, b_dev, x_dev, o, tol_u, tol_e, kr), "Krylov solve");
+  c->last_solve_improved = kr.status == LGDM_OK || kr.improved;
   if (rep) {
     rep->krylov_iters += kr.iters;
     rep->restarts += kr.restarts;
@@ -438,6 +439,9 @@ lgdm_status lgdm_newton_iteration(lgdm_ctx* c, const lgdm_solver_opts* o, int32_
   s = linear_solve(c, c->R, c->delta, op, tol_u, tol_e, rep);
   HIPCHECK(c, hipEventRecord(c->ev[3], c->stream), "event");
   if (!tolerable_in_newton(s)) return s;
+  // a correction no better than none would repeat this iteration unchanged
+  if (!c->last_solve_improved)
+    return fail(c, LGDM_ERR_NOT_CONVERGED, "the linear solve made no progress on the Newton system");
   s = LGDM_OK;
   // Algorithm 2: u_i = u_{i-1} + delta u, ebar_i = ebar_{i-1} + delta ebar
   HIPCHECK(c, launch_axpy(c, c->x, c->delta, 1.0, c->ndof), "update");

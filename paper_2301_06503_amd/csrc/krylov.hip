@@ -23,6 +23,7 @@
 //    the inner operator is the fixed linear map of the FP32 matrix: an FP32
 //    accumulation would make it a noisy map whose rounding, once the Newton
 //    residual is smooth, exceeds K p and stalls the refinement.
+#include <algorithm>
 #include <cmath>
 #include <memory>
 #include <type_traits>
@@ -52,8 +53,9 @@ constexpr double FLOOR_REL2 = 1e-30;
 // have comparable magnitudes, and a field whose right-hand side is far below
 // the other's cannot be resolved below the operator's rounding of the other
 constexpr double FIELD_FLOOR2 = 1e-6;
-// iterations without a new best residual after which a solve has stagnated
-// (the FP32 operator of a mixed context bounds the attainable residual)
+// iterations without a new best residual after which a solve has stagnated:
+// at least this many, and at least as many as the solve has run (IDR(s)
+// residuals can plateau for hundreds of steps before they drop)
 constexpr int STALL_ITERS = 500;
 // IDR(s) minimal-residual step: omega is enlarged until the cosine of the
 // angle between t and r it implies is at least this (van Gijzen & Sonneveld)
@@ -94,11 +96,11 @@ __device__ __forceinline__ void block_sum(double (&v)[NQ], double (*sm)[BS]) {
 // write this block's fixed-order partial sums (the scalar kernel that
 // follows on the stream finishes the reduction)
 template <int NQ>
-__device__ __forceinline__ void write_partials(double (&v)[NQ], double* part, double (*sm)[BS]) {
+__device__ __forceinline__ void write_partials(double (&v)[NQ], double* part, int64_t blk, double (*sm)[BS]) {
   block_sum<NQ>(v, sm);
   if (threadIdx.x == 0)
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) part[blockIdx.x * NQ + q] = v[q];
+    for (int q = 0; q < NQ; ++q) part[blk * NQ + q] = v[q];
 }
 
 // Entry j of the q-th IDR shadow vector: a uniform deviate in [-1, 1) from
@@ -185,22 +187,22 @@ __device__ __forceinline__ int group_rows(double (&acc)[ND], int lane, double& t
 // neighbour and every read is ND values wide.  Grid-stride over nodes.
 // MODE 0: no dots; 1: dot(rh, y), |y|^2; 2: dot(y, s), |y|^2;
 // 3: the NP shadow-vector dots P_q . y and |y|^2 (IDR)
+// workgroup blk of nblk (the kernels below pass their block, the batched
+// ones the block within the request)
 template <typename T, int ND, int G, int MODE, int NP = 0>
-__global__ void __launch_bounds__(BS) spmv_kernel(int64_t n_nodes, const int32_t* __restrict__ row_ptr,
-                                                  const int32_t* __restrict__ nbr_ptr,
-                                                  const int32_t* __restrict__ nbr,
-                                                  const T* __restrict__ vals,
-                                                  const double* __restrict__ x,
-                                                  double* __restrict__ y, const double* __restrict__ w,
-                                                  const double* __restrict__ sc,
-                                                  double* __restrict__ part) {
+__device__ __forceinline__ void spmv_body(int64_t blk, int64_t nblk, int64_t n_nodes,
+                                          const int32_t* __restrict__ row_ptr,
+                                          const int32_t* __restrict__ nbr_ptr, const int32_t* __restrict__ nbr,
+                                          const T* __restrict__ vals, const double* __restrict__ x,
+                                          double* __restrict__ y, const double* __restrict__ w,
+                                          const double* __restrict__ sc, double* __restrict__ part) {
   constexpr int NQ = MODE == 3 ? NP + 1 : 2;
   __shared__ double sm[NQ][BS];
   if (sc[K_DONE] != 0.0) return;
   const double se = sc[K_SE];
   const int lane = threadIdx.x % G;
-  const int64_t grp = ((int64_t)blockIdx.x * BS + threadIdx.x) / G;
-  const int64_t ngrp = (int64_t)gridDim.x * BS / G;
+  const int64_t grp = (blk * BS + threadIdx.x) / G;
+  const int64_t ngrp = nblk * BS / G;
   double d[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) d[q] = 0.0;
@@ -247,7 +249,19 @@ __global__ void __launch_bounds__(BS) spmv_kernel(int64_t n_nodes, const int32_t
     }
   }
   if (MODE == 0) return;
-  write_partials<NQ>(d, part, sm);
+  write_partials<NQ>(d, part, blk, sm);
+}
+
+template <typename T, int ND, int G, int MODE, int NP = 0>
+__global__ void __launch_bounds__(BS) spmv_kernel(int64_t n_nodes, const int32_t* __restrict__ row_ptr,
+                                                  const int32_t* __restrict__ nbr_ptr,
+                                                  const int32_t* __restrict__ nbr,
+                                                  const T* __restrict__ vals,
+                                                  const double* __restrict__ x,
+                                                  double* __restrict__ y, const double* __restrict__ w,
+                                                  const double* __restrict__ sc,
+                                                  double* __restrict__ part) {
+  spmv_body<T, ND, G, MODE, NP>(blockIdx.x, gridDim.x, n_nodes, row_ptr, nbr_ptr, nbr, vals, x, y, w, sc, part);
 }
 
 // finishing reductions (one workgroup): fixed-order sums of the partials and
@@ -413,7 +427,7 @@ __global__ void __launch_bounds__(BS) xupdate_kernel(int64_t n, double* __restri
     if (i % ND == ND - 1) d[2] += rd * rd;
     else d[1] += rd * rd;
   }
-  write_partials<3>(d, part, sm);
+  write_partials<3>(d, part, blockIdx.x, sm);
 }
 
 // r = S b - y, rh = r, p = v = 0; partials of rho and the field norms of r and S b
@@ -443,7 +457,7 @@ __global__ void __launch_bounds__(BS) init_kernel(int64_t n, const double* __res
       d[3] += sb * sb;
     }
   }
-  write_partials<5>(d, part, sm);
+  write_partials<5>(d, part, blockIdx.x, sm);
 }
 
 // block-Jacobi: invert the scaled diagonal node blocks (Gauss-Jordan with
@@ -566,15 +580,15 @@ __global__ void set_scalars_kernel(double* sc, double tol2u, double tol2e, doubl
 // coefficients the sequential form computes one at a time).
 
 // scalar slots of IDR(s), after the ones it shares with BiCGSTAB
-constexpr int I_OM = 24, I_BETA = 25, I_RR = 26, I_F = 32, I_C = 40, I_A = 48, I_M = 64;
+constexpr int I_OM = 24, I_BETA = 25, I_RR = 26, I_FRESH = 27, I_F = 32, I_C = 40, I_A = 48, I_M = 64;
 constexpr int I_LD = 8;  // leading dimension of M in the slots
 
 template <int NQ>
-__device__ __forceinline__ void finish_partials(int nblk, const double* __restrict__ part,
+__device__ __forceinline__ void finish_partials(int64_t nblk, const double* __restrict__ part,
                                                 double (&acc)[NQ], double (*sm)[BS]) {
 #pragma unroll
   for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
-  for (int i = threadIdx.x; i < nblk; i += BS)
+  for (int64_t i = threadIdx.x; i < nblk; i += BS)
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q] += part[i * NQ + q];
   block_sum<NQ>(acc, sm);
@@ -608,33 +622,36 @@ __device__ __forceinline__ void idr_coeffs(double* sc, int k0) {
   }
 }
 
+// Each IDR kernel is a device body taking its workgroup blk of nblk, so that
+// a single-request kernel (blockIdx.x of gridDim.x) and a batched kernel over
+// many requests (the block within its request) run the same code.
+
 // r = S b - y; partials |r_u|^2, |r_e|^2, |(Sb)_u|^2, |(Sb)_e|^2, P^T r
 template <int ND, int S>
-__global__ void __launch_bounds__(BS) idr_init_kernel(int64_t n, const double* __restrict__ b,
-                                                      const double* __restrict__ y, int use_y,
-                                                      double* __restrict__ r, const double* __restrict__ sc,
-                                                      double* __restrict__ part) {
+__device__ __forceinline__ void idr_init_body(int64_t blk, int64_t nblk, int64_t n, const double* __restrict__ b,
+                                              const double* __restrict__ y, double* __restrict__ r,
+                                              const double* __restrict__ sc, double* __restrict__ part) {
   __shared__ double sm[4 + S][BS];
   const double se = sc[K_SE];
   double d[4 + S];
 #pragma unroll
   for (int q = 0; q < 4 + S; ++q) d[q] = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+  for (int64_t i = blk * BS + threadIdx.x; i < n; i += nblk * BS) {
     const bool fe = (i % ND == ND - 1);
     const double sb = b[i] * (fe ? se : 1.0);
-    const double rd = sb - (use_y ? y[i] : 0.0);
+    const double rd = sb - (y ? y[i] : 0.0);
     r[i] = rd;
     d[fe ? 1 : 0] += rd * rd;
     d[fe ? 3 : 2] += sb * sb;
 #pragma unroll
     for (int q = 0; q < S; ++q) d[4 + q] += shadow_entry(q, i) * rd;
   }
-  write_partials<4 + S>(d, part, sm);
+  write_partials<4 + S>(d, part, blk, sm);
 }
 
 template <int S>
-__global__ void __launch_bounds__(BS) idr_init_scalar(int nblk, const double* __restrict__ part,
-                                                      double* __restrict__ sc) {
+__device__ __forceinline__ void idr_init_scalar_body(int64_t nblk, const double* __restrict__ part,
+                                                     double* __restrict__ sc) {
   __shared__ double sm[4 + S][BS];
   double acc[4 + S];
   finish_partials<4 + S>(nblk, part, acc, sm);
@@ -646,6 +663,7 @@ __global__ void __launch_bounds__(BS) idr_init_scalar(int nblk, const double* __
   for (int i = 0; i < I_LD * I_LD; ++i) sc[I_M + i] = (i / I_LD == i % I_LD) ? 1.0 : 0.0;
   for (int q = 0; q < S; ++q) sc[I_F + q] = acc[4 + q];
   sc[I_OM] = 1.0;
+  sc[I_FRESH] = 1.0;
   sc[K_STATUS] = KS_RUN;
   sc[K_DONE] = 0.0;
   if (btot == 0.0) {
@@ -659,20 +677,18 @@ __global__ void __launch_bounds__(BS) idr_init_scalar(int nblk, const double* __
 }
 
 // step K: v = r - sum_j c_j G_{K+j};  U_K = sum_j c_j U_{K+j} + omega M^-1 v.
-// In the first cycle after a (re)start every G, U term is zero (FRESH).
-// One thread per node; the node's ND entries of each vector are one load.
-template <typename T, int ND, int S, int K, bool FRESH>
-__global__ void __launch_bounds__(BS) idr_dir_kernel(int64_t n_nodes, const T* __restrict__ minv,
-                                                     const double* __restrict__ r, const double* __restrict__ Gv,
-                                                     double* __restrict__ Uv, int64_t n,
-                                                     const double* __restrict__ sc) {
-  if (sc[K_DONE] != 0.0) return;
-  constexpr int NC = FRESH ? 0 : S - K;
+// In the first cycle after a (re)start every G, U term is zero (the fresh
+// flag).  One thread per node; the node's ND entries of each vector are one load.
+template <typename T, int ND, int S, int K, int NC>
+__device__ __forceinline__ void idr_dir_nodes(int64_t blk, int64_t nblk, int64_t n_nodes,
+                                              const T* __restrict__ minv, const double* __restrict__ r,
+                                              const double* __restrict__ Gv, double* __restrict__ Uv, int64_t n,
+                                              const double* __restrict__ sc) {
   double cc[NC > 0 ? NC : 1];
 #pragma unroll
   for (int j = 0; j < NC; ++j) cc[j] = sc[I_C + j];
   const double om = sc[I_OM];
-  for (int64_t a = (int64_t)blockIdx.x * BS + threadIdx.x; a < n_nodes; a += (int64_t)gridDim.x * BS) {
+  for (int64_t a = blk * BS + threadIdx.x; a < n_nodes; a += nblk * BS) {
     const int64_t o = a * ND;
     Quad<double, ND> v;
     v.load(r + o);
@@ -705,12 +721,24 @@ __global__ void __launch_bounds__(BS) idr_dir_kernel(int64_t n_nodes, const T* _
   }
 }
 
+template <typename T, int ND, int S, int K>
+__device__ __forceinline__ void idr_dir_body(int64_t blk, int64_t nblk, int64_t n_nodes,
+                                             const T* __restrict__ minv, const double* __restrict__ r,
+                                             const double* __restrict__ Gv, double* __restrict__ Uv, int64_t n,
+                                             const double* __restrict__ sc) {
+  if (sc[K_DONE] != 0.0) return;
+  if (sc[I_FRESH] != 0.0)
+    idr_dir_nodes<T, ND, S, K, 0>(blk, nblk, n_nodes, minv, r, Gv, Uv, n, sc);
+  else
+    idr_dir_nodes<T, ND, S, K, S - K>(blk, nblk, n_nodes, minv, r, Gv, Uv, n, sc);
+}
+
 // after g = S K U_k with partials P^T g, |g|^2: the biorthogonalisation
 // coefficients a (P_i . G_k' = 0 for i < k), column k of M, beta = f_k / M_kk,
 // f -= beta M[:, k], and the coefficients c of step k + 1
 template <int S>
-__global__ void __launch_bounds__(BS) idr_g_scalar(int nblk, const double* __restrict__ part,
-                                                   double* __restrict__ sc, int k, double pnorm2) {
+__device__ __forceinline__ void idr_g_scalar_body(int64_t nblk, const double* __restrict__ part,
+                                                  double* __restrict__ sc, int k, double pnorm2) {
   __shared__ double sm[S + 1][BS];
   double acc[S + 1];
   if (sc[K_DONE] != 0.0) return;
@@ -748,11 +776,11 @@ __global__ void __launch_bounds__(BS) idr_g_scalar(int nblk, const double* __res
 // the last step (K = s - 1) also forms v = M^-1 r for the minimal-residual
 // step.  Partials |r_u|^2, |r_e|^2.
 template <typename T, int ND, int S, int K>
-__global__ void __launch_bounds__(BS) idr_upd_kernel(int64_t n_nodes, const T* __restrict__ minv,
-                                                     double* __restrict__ Gv, double* __restrict__ Uv,
-                                                     double* __restrict__ r, double* __restrict__ x,
-                                                     double* __restrict__ v, int64_t n,
-                                                     const double* __restrict__ sc, double* __restrict__ part) {
+__device__ __forceinline__ void idr_upd_body(int64_t blk, int64_t nblk, int64_t n_nodes,
+                                             const T* __restrict__ minv, double* __restrict__ Gv,
+                                             double* __restrict__ Uv, double* __restrict__ r,
+                                             double* __restrict__ x, double* __restrict__ v, int64_t n,
+                                             const double* __restrict__ sc, double* __restrict__ part) {
   constexpr bool LAST = (K == S - 1);
   __shared__ double sm[2][BS];
   if (sc[K_DONE] != 0.0) return;
@@ -761,7 +789,7 @@ __global__ void __launch_bounds__(BS) idr_upd_kernel(int64_t n_nodes, const T* _
   for (int i = 0; i < K; ++i) aa[i] = sc[I_A + i];
   const double beta = sc[I_BETA];
   double d[2] = {0.0, 0.0};
-  for (int64_t a = (int64_t)blockIdx.x * BS + threadIdx.x; a < n_nodes; a += (int64_t)gridDim.x * BS) {
+  for (int64_t a = blk * BS + threadIdx.x; a < n_nodes; a += nblk * BS) {
     const int64_t o = a * ND;
     Quad<double, ND> g, u;
     g.load(Gv + (int64_t)K * n + o);
@@ -807,11 +835,11 @@ __global__ void __launch_bounds__(BS) idr_upd_kernel(int64_t n_nodes, const T* _
       vh.store(v + o);
     }
   }
-  write_partials<2>(d, part, sm);
+  write_partials<2>(d, part, blk, sm);
 }
 
-__global__ void __launch_bounds__(BS) idr_r_scalar(int nblk, const double* __restrict__ part,
-                                                   double* __restrict__ sc) {
+__device__ __forceinline__ void idr_r_scalar_body(int64_t nblk, const double* __restrict__ part,
+                                                  double* __restrict__ sc) {
   __shared__ double sm[2][BS];
   double acc[2];
   if (sc[K_DONE] != 0.0) return;
@@ -822,8 +850,8 @@ __global__ void __launch_bounds__(BS) idr_r_scalar(int nblk, const double* __res
 
 // omega of the minimal-residual step from t . r and t . t, kept away from
 // zero when t and r are far from parallel (the angle safeguard of IDR(s))
-__global__ void __launch_bounds__(BS) idr_om_scalar(int nblk, const double* __restrict__ part,
-                                                    double* __restrict__ sc) {
+__device__ __forceinline__ void idr_om_scalar_body(int64_t nblk, const double* __restrict__ part,
+                                                   double* __restrict__ sc) {
   __shared__ double sm[2][BS];
   double acc[2];
   if (sc[K_DONE] != 0.0) return;
@@ -849,16 +877,17 @@ __global__ void __launch_bounds__(BS) idr_om_scalar(int nblk, const double* __re
 
 // r -= omega t; x += omega v; partials |r_u|^2, |r_e|^2, P^T r
 template <int ND, int S>
-__global__ void __launch_bounds__(BS) idr_om_kernel(int64_t n, double* __restrict__ r, double* __restrict__ x,
-                                                    const double* __restrict__ v, const double* __restrict__ t,
-                                                    const double* __restrict__ sc, double* __restrict__ part) {
+__device__ __forceinline__ void idr_om_body(int64_t blk, int64_t nblk, int64_t n, double* __restrict__ r,
+                                            double* __restrict__ x, const double* __restrict__ v,
+                                            const double* __restrict__ t, const double* __restrict__ sc,
+                                            double* __restrict__ part) {
   __shared__ double sm[2 + S][BS];
   if (sc[K_DONE] != 0.0) return;
   const double om = sc[I_OM];
   double d[2 + S];
 #pragma unroll
   for (int q = 0; q < 2 + S; ++q) d[q] = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+  for (int64_t i = blk * BS + threadIdx.x; i < n; i += nblk * BS) {
     const double rd = r[i] - om * t[i];
     r[i] = rd;
     x[i] += om * v[i];
@@ -866,20 +895,160 @@ __global__ void __launch_bounds__(BS) idr_om_kernel(int64_t n, double* __restric
 #pragma unroll
     for (int q = 0; q < S; ++q) d[2 + q] += shadow_entry(q, i) * rd;
   }
-  write_partials<2 + S>(d, part, sm);
+  write_partials<2 + S>(d, part, blk, sm);
 }
 
 template <int S>
-__global__ void __launch_bounds__(BS) idr_f_scalar(int nblk, const double* __restrict__ part,
-                                                   double* __restrict__ sc) {
+__device__ __forceinline__ void idr_f_scalar_body(int64_t nblk, const double* __restrict__ part,
+                                                  double* __restrict__ sc) {
   __shared__ double sm[2 + S][BS];
   double acc[2 + S];
   if (sc[K_DONE] != 0.0) return;
   finish_partials<2 + S>(nblk, part, acc, sm);
   if (threadIdx.x != 0) return;
+  sc[I_FRESH] = 0.0;
   if (idr_norms(sc, acc[0], acc[1])) return;
   for (int q = 0; q < S; ++q) sc[I_F + q] = acc[2 + q];
   idr_coeffs<S>(sc, 0);
+}
+
+// --- single-request kernels ------------------------------------------------
+template <int ND, int S>
+__global__ void __launch_bounds__(BS) idr_init_kernel(int64_t n, const double* __restrict__ b,
+                                                      const double* __restrict__ y, double* __restrict__ r,
+                                                      const double* __restrict__ sc, double* __restrict__ part) {
+  idr_init_body<ND, S>(blockIdx.x, gridDim.x, n, b, y, r, sc, part);
+}
+template <int S>
+__global__ void __launch_bounds__(BS) idr_init_scalar(int nblk, const double* __restrict__ part,
+                                                      double* __restrict__ sc) {
+  idr_init_scalar_body<S>(nblk, part, sc);
+}
+template <typename T, int ND, int S, int K>
+__global__ void __launch_bounds__(BS) idr_dir_kernel(int64_t n_nodes, const T* __restrict__ minv,
+                                                     const double* __restrict__ r, const double* __restrict__ Gv,
+                                                     double* __restrict__ Uv, int64_t n,
+                                                     const double* __restrict__ sc) {
+  idr_dir_body<T, ND, S, K>(blockIdx.x, gridDim.x, n_nodes, minv, r, Gv, Uv, n, sc);
+}
+template <int S>
+__global__ void __launch_bounds__(BS) idr_g_scalar(int nblk, const double* __restrict__ part,
+                                                   double* __restrict__ sc, int k, double pnorm2) {
+  idr_g_scalar_body<S>(nblk, part, sc, k, pnorm2);
+}
+template <typename T, int ND, int S, int K>
+__global__ void __launch_bounds__(BS) idr_upd_kernel(int64_t n_nodes, const T* __restrict__ minv,
+                                                     double* __restrict__ Gv, double* __restrict__ Uv,
+                                                     double* __restrict__ r, double* __restrict__ x,
+                                                     double* __restrict__ v, int64_t n,
+                                                     const double* __restrict__ sc, double* __restrict__ part) {
+  idr_upd_body<T, ND, S, K>(blockIdx.x, gridDim.x, n_nodes, minv, Gv, Uv, r, x, v, n, sc, part);
+}
+__global__ void __launch_bounds__(BS) idr_r_scalar(int nblk, const double* __restrict__ part,
+                                                   double* __restrict__ sc) {
+  idr_r_scalar_body(nblk, part, sc);
+}
+__global__ void __launch_bounds__(BS) idr_om_scalar(int nblk, const double* __restrict__ part,
+                                                    double* __restrict__ sc) {
+  idr_om_scalar_body(nblk, part, sc);
+}
+template <int ND, int S>
+__global__ void __launch_bounds__(BS) idr_om_kernel(int64_t n, double* __restrict__ r, double* __restrict__ x,
+                                                    const double* __restrict__ v, const double* __restrict__ t,
+                                                    const double* __restrict__ sc, double* __restrict__ part) {
+  idr_om_body<ND, S>(blockIdx.x, gridDim.x, n, r, x, v, t, sc, part);
+}
+template <int S>
+__global__ void __launch_bounds__(BS) idr_f_scalar(int nblk, const double* __restrict__ part,
+                                                   double* __restrict__ sc) {
+  idr_f_scalar_body<S>(nblk, part, sc);
+}
+
+// --- batched kernels: one launch over the requests of a serving batch -------
+// Request j owns the workgroups [blk0[f], blk0[f] + nblk[f]) of a launch of
+// family f (per node, SpMV, per dof), sized from its own dimensions only, so
+// every reduction of a request has the same order alone and in any mix.
+enum { FAM_NODE = 0, FAM_SPMV = 1, FAM_DOF = 2 };
+
+struct KSlot {
+  int64_t nn, n;
+  const int32_t* row_ptr;
+  const int32_t* nbr_ptr;
+  const int32_t* nbr;
+  const void* vals;
+  const void* minv;
+  double* x;
+  double* r;
+  double* v;
+  double* t;
+  double* G;
+  double* U;
+  double* sc;
+  int64_t blk0[3];
+  int64_t nblk[3];
+};
+
+__device__ __forceinline__ int find_kslot(const KSlot* __restrict__ ks, int nks, int fam, int64_t blk) {
+  int lo = 0, hi = nks - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (ks[mid].blk0[fam] <= blk) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename T, int ND, int S, int K>
+__global__ void __launch_bounds__(BS) idr_dir_batch(const KSlot* __restrict__ ks, int nks) {
+  const KSlot& q = ks[find_kslot(ks, nks, FAM_NODE, blockIdx.x)];
+  idr_dir_body<T, ND, S, K>(blockIdx.x - q.blk0[FAM_NODE], q.nblk[FAM_NODE], q.nn, (const T*)q.minv, q.r, q.G,
+                            q.U, q.n, q.sc);
+}
+template <typename T, int ND, int G, int MODE, int NP>
+__global__ void __launch_bounds__(BS) spmv_batch(const KSlot* __restrict__ ks, int nks, int k,
+                                                 double* __restrict__ part) {
+  const KSlot& q = ks[find_kslot(ks, nks, FAM_SPMV, blockIdx.x)];
+  const double* x = MODE == 3 ? q.U + (int64_t)k * q.n : q.v;
+  double* y = MODE == 3 ? q.G + (int64_t)k * q.n : q.t;
+  spmv_body<T, ND, G, MODE, NP>(blockIdx.x - q.blk0[FAM_SPMV], q.nblk[FAM_SPMV], q.nn, q.row_ptr, q.nbr_ptr,
+                                q.nbr, (const T*)q.vals, x, y, MODE == 2 ? q.r : nullptr, q.sc,
+                                part + q.blk0[FAM_SPMV] * (MODE == 3 ? NP + 1 : 2));
+}
+template <int S>
+__global__ void __launch_bounds__(BS) idr_g_scalar_batch(const KSlot* __restrict__ ks, int k,
+                                                         const double* __restrict__ part) {
+  const KSlot& q = ks[blockIdx.x];
+  idr_g_scalar_body<S>(q.nblk[FAM_SPMV], part + q.blk0[FAM_SPMV] * (S + 1), q.sc, k, (double)q.n / 3.0);
+}
+template <typename T, int ND, int S, int K>
+__global__ void __launch_bounds__(BS) idr_upd_batch(const KSlot* __restrict__ ks, int nks,
+                                                    double* __restrict__ part) {
+  const KSlot& q = ks[find_kslot(ks, nks, FAM_NODE, blockIdx.x)];
+  idr_upd_body<T, ND, S, K>(blockIdx.x - q.blk0[FAM_NODE], q.nblk[FAM_NODE], q.nn, (const T*)q.minv, q.G, q.U,
+                            q.r, q.x, q.v, q.n, q.sc, part + q.blk0[FAM_NODE] * 2);
+}
+__global__ void __launch_bounds__(BS) idr_r_scalar_batch(const KSlot* __restrict__ ks,
+                                                         const double* __restrict__ part) {
+  const KSlot& q = ks[blockIdx.x];
+  idr_r_scalar_body(q.nblk[FAM_NODE], part + q.blk0[FAM_NODE] * 2, q.sc);
+}
+__global__ void __launch_bounds__(BS) idr_om_scalar_batch(const KSlot* __restrict__ ks,
+                                                          const double* __restrict__ part) {
+  const KSlot& q = ks[blockIdx.x];
+  idr_om_scalar_body(q.nblk[FAM_SPMV], part + q.blk0[FAM_SPMV] * 2, q.sc);
+}
+template <int ND, int S>
+__global__ void __launch_bounds__(BS) idr_om_batch(const KSlot* __restrict__ ks, int nks,
+                                                   double* __restrict__ part) {
+  const KSlot& q = ks[find_kslot(ks, nks, FAM_DOF, blockIdx.x)];
+  idr_om_body<ND, S>(blockIdx.x - q.blk0[FAM_DOF], q.nblk[FAM_DOF], q.n, q.r, q.x, q.v, q.t, q.sc,
+                     part + q.blk0[FAM_DOF] * (2 + S));
+}
+template <int S>
+__global__ void __launch_bounds__(BS) idr_f_scalar_batch(const KSlot* __restrict__ ks,
+                                                          const double* __restrict__ part) {
+  const KSlot& q = ks[blockIdx.x];
+  idr_f_scalar_body<S>(q.nblk[FAM_DOF], part + q.blk0[FAM_DOF] * (2 + S), q.sc);
 }
 
 // compute units of the current device
@@ -924,10 +1093,12 @@ struct Solver {
   static constexpr bool F32 = std::is_same<T, float>::value;
   static constexpr int G = ND == 4 ? 16 : (ND == 3 ? 16 : 4);
   lgdm_ctx* c;
+  hipStream_t st;
   const T* vals;
   const T* minv;
   Vecs V;
   double* sc;
+  double* kp;
   int64_t n, nn;
 
   double* vec(void* p) { return static_cast<double*>(p); }
@@ -935,52 +1106,54 @@ struct Solver {
   void spmv(const double* x, double* y, int mode, const double* w) {
     if (mode == 0) {
       const int64_t g = grid_of(spmv_kernel<T, ND, G, 0>, nn * G);
-      spmv_kernel<T, ND, G, 0><<<g, BS, 0, c->stream>>>(nn, c->row_ptr, c->nbr_ptr, c->nbr, vals, x, y,
-                                                        w, sc, c->kpart);
+      spmv_kernel<T, ND, G, 0><<<g, BS, 0, st>>>(nn, c->row_ptr, c->nbr_ptr, c->nbr, vals, x, y,
+                                                        w, sc, kp);
     } else if (mode == 1) {
       const int64_t g = grid_of(spmv_kernel<T, ND, G, 1>, nn * G);
-      spmv_kernel<T, ND, G, 1><<<g, BS, 0, c->stream>>>(nn, c->row_ptr, c->nbr_ptr, c->nbr, vals, x, y,
-                                                        w, sc, c->kpart);
-      scalar_kernel<1, 2><<<1, BS, 0, c->stream>>>((int)g, c->kpart, sc);
+      spmv_kernel<T, ND, G, 1><<<g, BS, 0, st>>>(nn, c->row_ptr, c->nbr_ptr, c->nbr, vals, x, y,
+                                                        w, sc, kp);
+      scalar_kernel<1, 2><<<1, BS, 0, st>>>((int)g, kp, sc);
     } else {
       const int64_t g = grid_of(spmv_kernel<T, ND, G, 2>, nn * G);
-      spmv_kernel<T, ND, G, 2><<<g, BS, 0, c->stream>>>(nn, c->row_ptr, c->nbr_ptr, c->nbr, vals, x, y,
-                                                        w, sc, c->kpart);
-      scalar_kernel<2, 2><<<1, BS, 0, c->stream>>>((int)g, c->kpart, sc);
+      spmv_kernel<T, ND, G, 2><<<g, BS, 0, st>>>(nn, c->row_ptr, c->nbr_ptr, c->nbr, vals, x, y,
+                                                        w, sc, kp);
+      scalar_kernel<2, 2><<<1, BS, 0, st>>>((int)g, kp, sc);
     }
   }
 
   void init(const double* b, bool use_y, const double* y) {
     const int64_t g = grid_of(init_kernel<ND>, n);
-    init_kernel<ND><<<g, BS, 0, c->stream>>>(n, b, y, use_y ? 1 : 0, vec(V.r), vec(V.rh), vec(V.p),
-                                             vec(V.v), sc, c->kpart);
-    scalar_kernel<4, 5><<<1, BS, 0, c->stream>>>((int)g, c->kpart, sc);
+    init_kernel<ND><<<g, BS, 0, st>>>(n, b, y, use_y ? 1 : 0, vec(V.r), vec(V.rh), vec(V.p),
+                                             vec(V.v), sc, kp);
+    scalar_kernel<4, 5><<<1, BS, 0, st>>>((int)g, kp, sc);
   }
 
   void iteration(double* x) {
-    pupdate_kernel<T, ND><<<grid_of(pupdate_kernel<T, ND>, nn), BS, 0, c->stream>>>(
+    pupdate_kernel<T, ND><<<grid_of(pupdate_kernel<T, ND>, nn), BS, 0, st>>>(
         nn, minv, vec(V.r), vec(V.p), vec(V.v), vec(V.ph), sc);
     spmv(vec(V.ph), vec(V.v), 1, vec(V.rh));
-    supdate_kernel<T, ND><<<grid_of(supdate_kernel<T, ND>, nn), BS, 0, c->stream>>>(
+    supdate_kernel<T, ND><<<grid_of(supdate_kernel<T, ND>, nn), BS, 0, st>>>(
         nn, minv, vec(V.r), vec(V.v), vec(V.s), vec(V.sh), sc);
     spmv(vec(V.sh), vec(V.t), 2, vec(V.s));
     const int64_t g = grid_of(xupdate_kernel<ND>, n);
-    xupdate_kernel<ND><<<g, BS, 0, c->stream>>>(n, x, vec(V.ph), vec(V.sh), vec(V.s), vec(V.t),
-                                                vec(V.r), vec(V.rh), sc, c->kpart);
-    scalar_kernel<3, 3><<<1, BS, 0, c->stream>>>((int)g, c->kpart, sc);
+    xupdate_kernel<ND><<<g, BS, 0, st>>>(n, x, vec(V.ph), vec(V.sh), vec(V.s), vec(V.t),
+                                                vec(V.r), vec(V.rh), sc, kp);
+    scalar_kernel<3, 3><<<1, BS, 0, st>>>((int)g, kp, sc);
   }
 
   // the interface a Krylov run drives
   static constexpr int SPMV_PER_ITER = 2;
-  void bind(lgdm_ctx* ctx) {
+  void bind(lgdm_ctx* ctx, hipStream_t stream, double* scal, double* part) {
     c = ctx;
+    st = stream;
     n = c->ndof;
     nn = c->n_nodes;
     vals = F32 ? (const T*)c->vals32 : (const T*)c->vals;
     minv = F32 ? (const T*)c->minv32 : (const T*)c->minv;
     void** vp[8] = {&V.r, &V.rh, &V.p, &V.v, &V.s, &V.t, &V.ph, &V.sh};
     for (int i = 0; i < 8; ++i) *vp[i] = c->kv + (int64_t)i * c->ndof;
-    sc = c->kscal;
+    sc = scal;
+    kp = part;
   }
   void begin(const double* b) { init(b, false, nullptr); }
   void restart(const double* b, const double* x) {
@@ -1000,15 +1173,17 @@ struct Idr {
   static constexpr int G = Solver<T, ND>::G;
   static constexpr int SPMV_PER_ITER = 1;
   lgdm_ctx* c = nullptr;
+  hipStream_t st = nullptr;
   const T* vals = nullptr;
   const T* minv = nullptr;
   double* sc = nullptr;
+  double* kp = nullptr;
   double *r = nullptr, *v = nullptr, *t = nullptr, *Gv = nullptr, *Uv = nullptr;
   int64_t n = 0, nn = 0;
-  bool fresh = true;
 
-  void bind(lgdm_ctx* ctx) {
+  void bind(lgdm_ctx* ctx, hipStream_t stream, double* scal, double* part) {
     c = ctx;
+    st = stream;
     n = c->ndof;
     nn = c->n_nodes;
     vals = F32 ? (const T*)c->vals32 : (const T*)c->vals;
@@ -1018,39 +1193,33 @@ struct Idr {
     t = c->kv + 2 * n;
     Gv = c->kv + 3 * n;
     Uv = c->kv + (3 + S) * n;
-    sc = c->kscal;
+    sc = scal;
+    kp = part;
   }
   int64_t spmv_grid() const { return grid_of(spmv_kernel<T, ND, G, 3, S>, nn * G); }
   void init(const double* b, const double* y) {
     const int64_t g = grid_of(idr_init_kernel<ND, S>, n);
-    idr_init_kernel<ND, S><<<g, BS, 0, c->stream>>>(n, b, y, y ? 1 : 0, r, sc, c->kpart);
-    idr_init_scalar<S><<<1, BS, 0, c->stream>>>((int)g, c->kpart, sc);
-    fresh = true;
+    idr_init_kernel<ND, S><<<g, BS, 0, st>>>(n, b, y, r, sc, kp);
+    idr_init_scalar<S><<<1, BS, 0, st>>>((int)g, kp, sc);
   }
   void begin(const double* b) { init(b, nullptr); }
   void restart(const double* b, const double* x) {
-    spmv_kernel<T, ND, G, 0><<<grid_of(spmv_kernel<T, ND, G, 0>, nn * G), BS, 0, c->stream>>>(
-        nn, c->row_ptr, c->nbr_ptr, c->nbr, vals, x, t, nullptr, sc, c->kpart);
+    spmv_kernel<T, ND, G, 0><<<grid_of(spmv_kernel<T, ND, G, 0>, nn * G), BS, 0, st>>>(
+        nn, c->row_ptr, c->nbr_ptr, c->nbr, vals, x, t, nullptr, sc, kp);
     init(b, t);
   }
   // the s steps of a cycle, each with its compile-time index K
   template <int K> void steps(double* x, int64_t gs, double pnorm2) {
     if constexpr (K < S) {
-      if (fresh) {
-        auto kd = idr_dir_kernel<T, ND, S, K, true>;
-        kd<<<grid_of(kd, nn), BS, 0, c->stream>>>(nn, minv, r, Gv, Uv, n, sc);
-      } else {
-        auto kd = idr_dir_kernel<T, ND, S, K, false>;
-        kd<<<grid_of(kd, nn), BS, 0, c->stream>>>(nn, minv, r, Gv, Uv, n, sc);
-      }
-      spmv_kernel<T, ND, G, 3, S><<<gs, BS, 0, c->stream>>>(nn, c->row_ptr, c->nbr_ptr, c->nbr, vals,
-                                                            Uv + (int64_t)K * n, Gv + (int64_t)K * n, nullptr,
-                                                            sc, c->kpart);
-      idr_g_scalar<S><<<1, BS, 0, c->stream>>>((int)gs, c->kpart, sc, K, pnorm2);
+      auto kd = idr_dir_kernel<T, ND, S, K>;
+      kd<<<grid_of(kd, nn), BS, 0, st>>>(nn, minv, r, Gv, Uv, n, sc);
+      spmv_kernel<T, ND, G, 3, S><<<gs, BS, 0, st>>>(nn, c->row_ptr, c->nbr_ptr, c->nbr, vals,
+                                                     Uv + (int64_t)K * n, Gv + (int64_t)K * n, nullptr, sc, kp);
+      idr_g_scalar<S><<<1, BS, 0, st>>>((int)gs, kp, sc, K, pnorm2);
       auto ku = idr_upd_kernel<T, ND, S, K>;
       const int64_t gu = grid_of(ku, nn);
-      ku<<<gu, BS, 0, c->stream>>>(nn, minv, Gv, Uv, r, x, v, n, sc, c->kpart);
-      idr_r_scalar<<<1, BS, 0, c->stream>>>((int)gu, c->kpart, sc);
+      ku<<<gu, BS, 0, st>>>(nn, minv, Gv, Uv, r, x, v, n, sc, kp);
+      idr_r_scalar<<<1, BS, 0, st>>>((int)gu, kp, sc);
       steps<K + 1>(x, gs, pnorm2);
     }
   }
@@ -1059,17 +1228,112 @@ struct Idr {
     const int64_t gm = grid_of(spmv_kernel<T, ND, G, 2>, nn * G), g = grid_of(idr_om_kernel<ND, S>, n);
     const double pnorm2 = (double)n / 3.0;  // E|P_k|^2 of uniform [-1, 1) entries
     steps<0>(x, gs, pnorm2);
-    spmv_kernel<T, ND, G, 2><<<gm, BS, 0, c->stream>>>(nn, c->row_ptr, c->nbr_ptr, c->nbr, vals, v, t, r,
-                                                            sc, c->kpart);
-    idr_om_scalar<<<1, BS, 0, c->stream>>>((int)gm, c->kpart, sc);
-    idr_om_kernel<ND, S><<<g, BS, 0, c->stream>>>(n, r, x, v, t, sc, c->kpart);
-    idr_f_scalar<S><<<1, BS, 0, c->stream>>>((int)g, c->kpart, sc);
-    fresh = false;
+    spmv_kernel<T, ND, G, 2><<<gm, BS, 0, st>>>(nn, c->row_ptr, c->nbr_ptr, c->nbr, vals, v, t, r, sc, kp);
+    idr_om_scalar<<<1, BS, 0, st>>>((int)gm, kp, sc);
+    idr_om_kernel<ND, S><<<g, BS, 0, st>>>(n, r, x, v, t, sc, kp);
+    idr_f_scalar<S><<<1, BS, 0, st>>>((int)g, kp, sc);
   }
-  // `iters` operator applications, rounded up to whole cycles of s + 1
-  void iterate(double* x, int iters) {
+  // at least `iters` operator applications, in whole cycles of s + 1
+  static int cycles_for(int iters) {
     const int ncyc = (iters + S) / (S + 1);
-    for (int i = 0; i < (ncyc > 0 ? ncyc : 1); ++i) cycle(x);
+    return ncyc > 0 ? ncyc : 1;
+  }
+  void iterate(double* x, int iters) {
+    for (int i = 0, n_cyc = cycles_for(iters); i < n_cyc; ++i) cycle(x);
+  }
+};
+
+// The host side of one solve, shared by single and batched runs: reads the
+// device scalars after some iterations and decides what happens next.
+struct RunControl {
+  enum Action { NONE, RESTART, RETURN_BEST };
+  KrylovResult res{};
+  double tol_u = 0, tol_e = 0;
+  int64_t done_iters = 0;      // iterations before the last restart
+  int replacements = 0;        // restarts that replaced a converged recurrence residual
+  double best = INFINITY;      // best per-field residual / tolerance so far
+  int64_t stall = 0;
+  bool have_best = false;
+  bool fin = false;
+  int spmv_per_iter = 1;
+
+  void setup(double tu, double te, bool f32, int per_iter) {
+    // an FP32 matrix gains nothing below 1e-8; Newton refines on the FP64 residual
+    tol_u = f32 && tu < 1e-8 ? 1e-8 : tu;
+    tol_e = f32 && te < 1e-8 ? 1e-8 : te;
+    spmv_per_iter = per_iter;
+    res.status = LGDM_ERR_NOT_CONVERGED;
+  }
+  double score() const { return std::max(res.rel_u / tol_u, res.rel_e / tol_e); }
+
+  // h: the scalars after `ran` more iterations were enqueued.  save_best is
+  // set when the current iterate is the best so far and must be copied.
+  Action decide(const double* h, const lgdm_solver_opts& o, int64_t ran, bool& save_best) {
+    save_best = false;
+    const int64_t it = (int64_t)h[K_ITER];
+    res.iters = done_iters + it;
+    res.spmv = res.iters * spmv_per_iter + res.restarts + replacements;
+    const double bu = h[K_BU] > 0 ? h[K_BU] : 1.0, be = h[K_BE] > 0 ? h[K_BE] : 1.0;
+    res.rel_u = std::sqrt(h[K_RU] / bu);
+    res.rel_e = std::sqrt(h[K_RE] / be);
+    const int st = (int)h[K_STATUS];
+    if (h[K_DONE] != 0.0) {
+      if (st == KS_CONV) {
+        // accept a converged true residual (no iteration since the last
+        // (re)start); a converged recurrence residual is first replaced by
+        // the true one, which it can drift from
+        if (it == 0 || replacements >= 4) {
+          res.status = LGDM_OK;
+          res.improved = true;
+          fin = true;
+          return NONE;
+        }
+        replacements++;
+        done_iters = res.iters;
+        return RESTART;
+      }
+      if (st == KS_NAN) {
+        fin = true;
+        if (have_best) {
+          res.status = LGDM_ERR_NOT_CONVERGED;
+          return RETURN_BEST;
+        }
+        res.status = LGDM_ERR_NAN;
+        return NONE;
+      }
+      // breakdown: restart from the current iterate with its true residual
+      if (res.restarts >= o.max_restarts || res.iters >= o.max_krylov) {
+        res.status = LGDM_ERR_BREAKDOWN;
+        fin = true;
+        // the current iterate is kept unless an earlier one was better
+        if (have_best && !(score() <= best)) return RETURN_BEST;
+        res.improved = res.iters > 0 && std::isfinite(score());
+        return NONE;
+      }
+      res.restarts++;
+      done_iters = res.iters;
+      return RESTART;
+    }
+    const double sc = score();
+    if (std::isfinite(sc) && sc < best * (1.0 - 1e-3)) {
+      best = sc;
+      stall = 0;
+      res.improved = have_best;  // the first best is the zero start itself
+      have_best = true;
+      save_best = true;
+      if (res.iters >= o.max_krylov) {  // the current iterate is the best: keep it
+        res.status = LGDM_ERR_NOT_CONVERGED;
+        fin = true;
+      }
+      return NONE;
+    }
+    stall += ran;
+    if (stall >= std::max<int64_t>(STALL_ITERS, res.iters) || res.iters >= o.max_krylov) {
+      res.status = LGDM_ERR_NOT_CONVERGED;
+      fin = true;
+      return RETURN_BEST;
+    }
+    return NONE;
   }
 };
 
@@ -1085,141 +1349,251 @@ struct KrylovRunImpl final : KrylovRun {
   const double* b;
   double* xout;
   lgdm_solver_opts o;
-  KrylovResult res{};
-  double tol_u = 0, tol_e = 0, se = 0;
+  RunControl rc;
+  double se = 0;
   int every = 16;
-  int64_t done_iters = 0;
-  bool true_residual = true;   // the scalars describe b - A x computed directly
-  int replacements = 0;
   double* xbest = nullptr;     // best iterate so far (per-field relative residual)
-  double best = INFINITY;
-  int stall = 0;
-  bool have_best = false;
-  bool fin = false;
+  bool pending_read = false;   // a restart's scalars are in flight: check again before launching
+  int64_t ran = 0;             // iterations enqueued since the last check
 
   KrylovRunImpl(lgdm_ctx* ctx, const double* b_, double* x_, const lgdm_solver_opts& o_, double tu,
                 double te)
       : c(ctx), b(b_), xout(x_), o(o_) {
-    S.bind(c);
+    S.bind(c, c->stream, c->kscal, c->kpart);
     xbest = c->kv + (int64_t)(KV_VECS - 1) * c->ndof;
-    // an FP32 matrix gains nothing below 1e-8; Newton refines on the FP64 residual
-    tol_u = Method::F32 && tu < 1e-8 ? 1e-8 : tu;
-    tol_e = Method::F32 && te < 1e-8 ? 1e-8 : te;
+    rc.setup(tu, te, Method::F32, Method::SPMV_PER_ITER);
     se = c->mat.E / c->mat.h;
     every = o.check_every > 0 ? o.check_every : 16;
-    res.status = LGDM_ERR_NOT_CONVERGED;
   }
 
-  void return_best(int status) {
-    if (have_best)
-      (void)hipMemcpyAsync(xout, xbest, c->ndof * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
-    res.status = status;
-    fin = true;
-  }
-
-  // restart the recurrences from the current iterate with its true residual
-  void restart_from_x() {
-    set_scalars_kernel<<<1, 64, 0, c->stream>>>(S.sc, tol_u * tol_u, tol_e * tol_e, se, BREAK_REL);
-    S.restart(b, xout);
-    res.spmv += 1;
+  hipError_t read_scalars() {
+    return hipMemcpyAsync(c->kscal_host, S.sc, K_NSLOTS * sizeof(double), hipMemcpyDeviceToHost, c->stream);
   }
 
   hipError_t start() override {
-    set_scalars_kernel<<<1, 64, 0, c->stream>>>(S.sc, tol_u * tol_u, tol_e * tol_e, se, BREAK_REL);
+    set_scalars_kernel<<<1, 64, 0, c->stream>>>(S.sc, rc.tol_u * rc.tol_u, rc.tol_e * rc.tol_e, se, BREAK_REL);
     hipError_t e = hipMemsetAsync(xout, 0, c->ndof * sizeof(double), c->stream);
     if (e != hipSuccess) return e;
     S.begin(b);
-    // read the scalars of the initial residual asynchronously
-    return hipMemcpyAsync(c->kscal_host, S.sc, K_NSLOTS * sizeof(double), hipMemcpyDeviceToHost,
-                          c->stream);
+    ran = 0;
+    return read_scalars();
   }
 
   hipError_t launch() override {
-    if (fin) return hipSuccess;
+    if (rc.fin) return hipSuccess;
     S.iterate(xout, every);
+    ran = every;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return hipMemcpyAsync(c->kscal_host, S.sc, K_NSLOTS * sizeof(double), hipMemcpyDeviceToHost,
-                          c->stream);
+    return read_scalars();
   }
 
   // reads the scalars enqueued by the last start()/launch(); restart and
   // replacement kernels are enqueued here and read at the next check
   hipError_t check() override {
-    if (fin) return hipSuccess;
+    if (rc.fin) return hipSuccess;
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return e;
-    const double* h = c->kscal_host;
-    res.iters = done_iters + (int64_t)h[K_ITER];
-    res.spmv = res.iters * Method::SPMV_PER_ITER + res.restarts + replacements;
-    const double bu = h[K_BU] > 0 ? h[K_BU] : 1.0, be = h[K_BE] > 0 ? h[K_BE] : 1.0;
-    res.rel_u = std::sqrt(h[K_RU] / bu);
-    res.rel_e = std::sqrt(h[K_RE] / be);
-    const int st = (int)h[K_STATUS];
     pending_read = false;
-    if (h[K_DONE] != 0.0) {
-      if (st == KS_CONV) {
-        // accept only a converged true residual; a converged recurrence
-        // residual is first replaced by the true one (it can drift)
-        if (true_residual || replacements >= 4) {
-          res.status = LGDM_OK;
-          fin = true;
-          return hipSuccess;
-        }
-        replacements++;
-        done_iters = res.iters;
-        restart_from_x();
-        true_residual = true;
-        pending_read = true;
-        return hipMemcpyAsync(c->kscal_host, S.sc, K_NSLOTS * sizeof(double), hipMemcpyDeviceToHost,
-                              c->stream);
-      }
-      if (st == KS_NAN) {
-        if (have_best) return_best(LGDM_ERR_NOT_CONVERGED);
-        else {
-          res.status = LGDM_ERR_NAN;
-          fin = true;
-        }
-        return hipSuccess;
-      }
-      // breakdown: restart from the current iterate with the true residual
-      if (res.restarts >= o.max_restarts || res.iters >= o.max_krylov) {
-        // the current iterate is kept unless an earlier one was better
-        if (have_best && !(std::max(res.rel_u / tol_u, res.rel_e / tol_e) <= best))
-          return_best(LGDM_ERR_BREAKDOWN);
-        res.status = LGDM_ERR_BREAKDOWN;
-        fin = true;
-        return hipSuccess;
-      }
-      res.restarts++;
-      done_iters = res.iters;
-      restart_from_x();
-      true_residual = true;
-      pending_read = true;
-      return hipMemcpyAsync(c->kscal_host, S.sc, K_NSLOTS * sizeof(double), hipMemcpyDeviceToHost,
-                            c->stream);
-    }
-    true_residual = false;
-    const double score = std::max(res.rel_u / tol_u, res.rel_e / tol_e);
-    if (std::isfinite(score) && score < best * (1.0 - 1e-3)) {
-      best = score;
-      stall = 0;
-      have_best = true;
+    bool save_best = false;
+    const RunControl::Action a = rc.decide(c->kscal_host, o, ran, save_best);
+    ran = 0;
+    if (save_best) {
       e = hipMemcpyAsync(xbest, xout, c->ndof * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
       if (e != hipSuccess) return e;
-    } else if ((stall += every) >= STALL_ITERS) {
-      return_best(LGDM_ERR_NOT_CONVERGED);
-      return hipSuccess;
     }
-    if (res.iters >= o.max_krylov) return_best(LGDM_ERR_NOT_CONVERGED);
+    if (a == RunControl::RETURN_BEST && rc.have_best)
+      return hipMemcpyAsync(xout, xbest, c->ndof * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+    if (a == RunControl::RESTART) {
+      set_scalars_kernel<<<1, 64, 0, c->stream>>>(S.sc, rc.tol_u * rc.tol_u, rc.tol_e * rc.tol_e, se,
+                                                  BREAK_REL);
+      S.restart(b, xout);
+      pending_read = true;
+      return read_scalars();
+    }
     return hipSuccess;
   }
 
-  bool pending_read = false;   // a restart's scalars are in flight: check again before launching
   bool needs_check() const override { return pending_read; }
-  bool finished() const override { return fin; }
-  const KrylovResult& result() const override { return res; }
+  bool finished() const override { return rc.fin; }
+  const KrylovResult& result() const override { return rc.res; }
 };
+
+// ---------------------------------------------------------------------------
+// Batched IDR(s) over the requests of a serving batch.  Starts and restarts
+// of single requests use the single-request kernels; every cycle is one
+// launch per kernel over all running requests.  Per-request workgroup counts
+// depend only on the request's own size (capped), so its reductions, and
+// therefore its results, are the same alone and in any mix.
+constexpr int64_t CAP_NODE = 256, CAP_SPMV = 512, CAP_DOF = 256;
+constexpr int64_t BATCH_PART_PER_REQUEST = CAP_SPMV * KPART_PER_BLOCK;
+
+template <typename T, int ND, int S>
+struct BatchIdr final : BatchRun {
+  static constexpr int G = Solver<T, ND>::G;
+  hipStream_t st;
+  std::vector<lgdm_ctx*> ctx;
+  std::vector<RunControl> rc;
+  std::vector<Idr<T, ND, S>> one;
+  std::vector<double> se;
+  lgdm_solver_opts o;
+  BatchSolveBuffers& B;
+  KSlot* tab_host;
+  KSlot* tab_dev;
+  int nrun = 0;                // requests in the device table
+  int64_t tot[3] = {0, 0, 0};  // workgroups per launch family
+  int every = 16;
+  bool table_stale = true;
+
+  BatchIdr(hipStream_t s, const std::vector<lgdm_ctx*>& c, const std::vector<double>& tu,
+           const std::vector<double>& te, const lgdm_solver_opts& o_, BatchSolveBuffers& buf)
+      : st(s), ctx(c), rc(c.size()), one(c.size()), se(c.size()), o(o_), B(buf) {
+    tab_host = static_cast<KSlot*>(B.table_host);
+    tab_dev = static_cast<KSlot*>(B.table_dev);
+    every = o.check_every > 0 ? o.check_every : 16;
+    for (size_t j = 0; j < ctx.size(); ++j) {
+      one[j].bind(ctx[j], st, B.sc_dev + (int64_t)j * KSCAL_DOUBLES, ctx[j]->kpart);
+      rc[j].setup(tu[j], te[j], Idr<T, ND, S>::F32, 1);
+      se[j] = ctx[j]->mat.E / ctx[j]->mat.h;
+    }
+  }
+  double* sc(size_t j) { return B.sc_dev + (int64_t)j * KSCAL_DOUBLES; }
+  double* xbest(size_t j) { return ctx[j]->kv + (int64_t)(KV_VECS - 1) * ctx[j]->ndof; }
+
+  void reset_scalars(size_t j) {
+    set_scalars_kernel<<<1, 64, 0, st>>>(sc(j), rc[j].tol_u * rc[j].tol_u, rc[j].tol_e * rc[j].tol_e, se[j],
+                                         BREAK_REL);
+  }
+
+  // device table of the running requests
+  hipError_t build_table() {
+    nrun = 0;
+    tot[0] = tot[1] = tot[2] = 0;
+    for (size_t j = 0; j < ctx.size(); ++j) {
+      if (rc[j].fin) continue;
+      const Idr<T, ND, S>& q = one[j];
+      KSlot& k = tab_host[nrun++];
+      k.nn = q.nn;
+      k.n = q.n;
+      k.row_ptr = ctx[j]->row_ptr;
+      k.nbr_ptr = ctx[j]->nbr_ptr;
+      k.nbr = ctx[j]->nbr;
+      k.vals = q.vals;
+      k.minv = q.minv;
+      k.x = ctx[j]->delta;
+      k.r = q.r;
+      k.v = q.v;
+      k.t = q.t;
+      k.G = q.Gv;
+      k.U = q.Uv;
+      k.sc = q.sc;
+      const int64_t nb[3] = {std::min<int64_t>(std::max<int64_t>((q.nn + BS - 1) / BS, 1), CAP_NODE),
+                             std::min<int64_t>(std::max<int64_t>((q.nn * G + BS - 1) / BS, 1), CAP_SPMV),
+                             std::min<int64_t>(std::max<int64_t>((q.n + BS - 1) / BS, 1), CAP_DOF)};
+      for (int f = 0; f < 3; ++f) {
+        k.blk0[f] = tot[f];
+        k.nblk[f] = nb[f];
+        tot[f] += nb[f];
+      }
+    }
+    table_stale = false;
+    if (nrun == 0) return hipSuccess;
+    return hipMemcpyAsync(tab_dev, tab_host, nrun * sizeof(KSlot), hipMemcpyHostToDevice, st);
+  }
+
+  template <int K> void steps() {
+    if constexpr (K < S) {
+      idr_dir_batch<T, ND, S, K><<<tot[FAM_NODE], BS, 0, st>>>(tab_dev, nrun);
+      spmv_batch<T, ND, G, 3, S><<<tot[FAM_SPMV], BS, 0, st>>>(tab_dev, nrun, K, B.part);
+      idr_g_scalar_batch<S><<<nrun, BS, 0, st>>>(tab_dev, K, B.part);
+      idr_upd_batch<T, ND, S, K><<<tot[FAM_NODE], BS, 0, st>>>(tab_dev, nrun, B.part);
+      idr_r_scalar_batch<<<nrun, BS, 0, st>>>(tab_dev, B.part);
+      steps<K + 1>();
+    }
+  }
+  void cycle() {
+    steps<0>();
+    spmv_batch<T, ND, G, 2, 0><<<tot[FAM_SPMV], BS, 0, st>>>(tab_dev, nrun, 0, B.part);
+    idr_om_scalar_batch<<<nrun, BS, 0, st>>>(tab_dev, B.part);
+    idr_om_batch<ND, S><<<tot[FAM_DOF], BS, 0, st>>>(tab_dev, nrun, B.part);
+    idr_f_scalar_batch<S><<<nrun, BS, 0, st>>>(tab_dev, B.part);
+  }
+
+  // read every request's scalars and act on them
+  hipError_t decide_all(int64_t ran) {
+    hipError_t e = hipMemcpyAsync(B.sc_host, B.sc_dev, ctx.size() * KSCAL_DOUBLES * sizeof(double),
+                                  hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    for (size_t j = 0; j < ctx.size(); ++j) {
+      if (rc[j].fin) continue;
+      bool save = false;
+      const RunControl::Action a = rc[j].decide(B.sc_host + (int64_t)j * KSCAL_DOUBLES, o, ran, save);
+      const size_t bytes = ctx[j]->ndof * sizeof(double);
+      if (save && (e = hipMemcpyAsync(xbest(j), ctx[j]->delta, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess)
+        return e;
+      if (a == RunControl::RETURN_BEST && rc[j].have_best &&
+          (e = hipMemcpyAsync(ctx[j]->delta, xbest(j), bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess)
+        return e;
+      if (a == RunControl::RESTART) {
+        reset_scalars(j);
+        one[j].restart(ctx[j]->R, ctx[j]->delta);
+      }
+      if (rc[j].fin) {
+        // the host stopped it: later batched launches must skip it
+        if ((e = hipMemcpyAsync(sc(j) + K_DONE, B.one_host, sizeof(double), hipMemcpyHostToDevice, st)) !=
+            hipSuccess)
+          return e;
+        table_stale = true;
+      }
+    }
+    return hipGetLastError();
+  }
+
+  hipError_t start() override {
+    for (size_t j = 0; j < ctx.size(); ++j) {
+      reset_scalars(j);
+      hipError_t e = hipMemsetAsync(ctx[j]->delta, 0, ctx[j]->ndof * sizeof(double), st);
+      if (e != hipSuccess) return e;
+      one[j].begin(ctx[j]->R);
+    }
+    hipError_t e = decide_all(0);
+    if (e != hipSuccess) return e;
+    return build_table();
+  }
+
+  hipError_t advance() override {
+    if (finished()) return hipSuccess;
+    if (table_stale) {
+      hipError_t e = build_table();
+      if (e != hipSuccess) return e;
+    }
+    const int ncyc = Idr<T, ND, S>::cycles_for(every);
+    for (int i = 0; i < ncyc; ++i) cycle();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return decide_all((int64_t)ncyc * (S + 1));
+  }
+
+  bool finished() const override {
+    for (const auto& r : rc)
+      if (!r.fin) return false;
+    return true;
+  }
+  const KrylovResult& result(int j) const override { return rc[j].res; }
+};
+
+template <typename T, int ND>
+std::unique_ptr<BatchRun> make_batch_impl(hipStream_t st, const std::vector<lgdm_ctx*>& c,
+                                          const std::vector<double>& tu, const std::vector<double>& te,
+                                          const lgdm_solver_opts& o, BatchSolveBuffers& B) {
+  switch (o.idr_s) {
+    case 1: return std::unique_ptr<BatchRun>(new BatchIdr<T, ND, 1>(st, c, tu, te, o, B));
+    case 2: return std::unique_ptr<BatchRun>(new BatchIdr<T, ND, 2>(st, c, tu, te, o, B));
+    case 8: return std::unique_ptr<BatchRun>(new BatchIdr<T, ND, 8>(st, c, tu, te, o, B));
+    default: return std::unique_ptr<BatchRun>(new BatchIdr<T, ND, 4>(st, c, tu, te, o, B));
+  }
+}
 
 template <typename T, int ND>
 std::unique_ptr<KrylovRun> make_run_impl(lgdm_ctx* c, const double* b, double* x,
@@ -1285,6 +1659,48 @@ std::unique_ptr<KrylovRun> make_krylov_run(lgdm_ctx* c, const double* b, double*
   }
 }
 
+std::unique_ptr<BatchRun> make_batch_run(hipStream_t st, const std::vector<lgdm_ctx*>& ctxs,
+                                         const std::vector<double>& tol_u, const std::vector<double>& tol_e,
+                                         const lgdm_solver_opts& o, BatchSolveBuffers& B) {
+  if (ctxs.empty() || (int)ctxs.size() > B.max_requests) return nullptr;
+  const bool mixed = ctxs[0]->precision == LGDM_MIXED;
+  for (lgdm_ctx* c : ctxs)
+    if (c->nd != ctxs[0]->nd || (c->precision == LGDM_MIXED) != mixed) return nullptr;
+  switch (ctxs[0]->nd) {
+    case 2: return mixed ? make_batch_impl<float, 2>(st, ctxs, tol_u, tol_e, o, B)
+                         : make_batch_impl<double, 2>(st, ctxs, tol_u, tol_e, o, B);
+    case 3: return mixed ? make_batch_impl<float, 3>(st, ctxs, tol_u, tol_e, o, B)
+                         : make_batch_impl<double, 3>(st, ctxs, tol_u, tol_e, o, B);
+    default: return mixed ? make_batch_impl<float, 4>(st, ctxs, tol_u, tol_e, o, B)
+                          : make_batch_impl<double, 4>(st, ctxs, tol_u, tol_e, o, B);
+  }
+}
+
+hipError_t batch_solve_alloc(BatchSolveBuffers& B, int max_requests) {
+  B.max_requests = max_requests;
+  hipError_t e = hipMalloc(&B.table_dev, max_requests * sizeof(KSlot));
+  if (e == hipSuccess) e = hipHostMalloc(&B.table_host, max_requests * sizeof(KSlot), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMalloc((void**)&B.sc_dev, (size_t)max_requests * KSCAL_DOUBLES * sizeof(double));
+  if (e == hipSuccess)
+    e = hipHostMalloc((void**)&B.sc_host, (size_t)max_requests * KSCAL_DOUBLES * sizeof(double),
+                      hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&B.one_host, sizeof(double), hipHostMallocDefault);
+  if (e == hipSuccess)
+    e = hipMalloc((void**)&B.part, (size_t)max_requests * BATCH_PART_PER_REQUEST * sizeof(double));
+  if (e == hipSuccess) *B.one_host = 1.0;
+  return e;
+}
+
+void batch_solve_free(BatchSolveBuffers& B) {
+  if (B.table_dev) (void)hipFree(B.table_dev);
+  if (B.table_host) (void)hipHostFree(B.table_host);
+  if (B.sc_dev) (void)hipFree(B.sc_dev);
+  if (B.sc_host) (void)hipHostFree(B.sc_host);
+  if (B.one_host) (void)hipHostFree(B.one_host);
+  if (B.part) (void)hipFree(B.part);
+  B = BatchSolveBuffers{};
+}
+
 hipError_t krylov_solve(lgdm_ctx* c, const double* b, double* xout, const lgdm_solver_opts& o,
                         double tol_u, double tol_e, KrylovResult& res) {
   std::unique_ptr<KrylovRun> run = make_krylov_run(c, b, xout, o, tol_u, tol_e);
@@ -1322,7 +1738,7 @@ template <typename T, int ND> hipError_t spmv_only_impl(lgdm_ctx* c, const doubl
   // dot products and |y|^2), the launch that dominates a default solve
   using I = Idr<T, ND, 4>;
   I S;
-  S.bind(c);
+  S.bind(c, c->stream, c->kscal, c->kpart);
   set_scalars_kernel<<<1, 64, 0, c->stream>>>(S.sc, 0.0, 0.0, c->mat.E / c->mat.h, BREAK_REL);
   spmv_kernel<T, ND, I::G, 3, 4><<<S.spmv_grid(), BS, 0, c->stream>>>(
       S.nn, c->row_ptr, c->nbr_ptr, c->nbr, S.vals, x, S.t, nullptr, S.sc, c->kpart);

@@ -166,6 +166,7 @@ struct lgdm_ctx {
   double* kscal_host = nullptr;    // pinned copy
   unsigned int* kcount = nullptr;  // last-block counters
   double* delta = nullptr;
+  bool last_solve_improved = true;  // the last linear solve returned a better-than-zero correction
 
   hipEvent_t ev[8] = {};
   bool events_ready = false;
@@ -205,6 +206,7 @@ struct KrylovResult {
   int restarts;
   double rel_u, rel_e;
   int64_t spmv;        // operator applications
+  bool improved;       // the returned iterate is better than the zero start
 };
 // one linear solve as a state machine (see krylov.hip)
 struct KrylovRun {
@@ -221,6 +223,32 @@ std::unique_ptr<KrylovRun> make_krylov_run(lgdm_ctx* c, const double* b, double*
 // per-field relative tolerances of the next Newton correction
 void newton_forcing(lgdm_ctx* c, const lgdm_solver_opts& o, double& tol_u, double& tol_e);
 lgdm_solver_opts fill_opts(const lgdm_solver_opts* o);  // defaults for zero fields
+// The linear solves of several requests of one serving batch (same element
+// type and precision) as one IDR(s) run: every kernel of a cycle is one
+// launch over all of them.  Buffers are owned by the batch.
+struct BatchSolveBuffers {
+  void* table_dev = nullptr;    // per-request descriptors
+  void* table_host = nullptr;   // pinned
+  double* sc_dev = nullptr;     // [max_requests][KSCAL_DOUBLES]
+  double* sc_host = nullptr;    // pinned
+  double* one_host = nullptr;   // pinned constant 1.0
+  double* part = nullptr;       // partial sums of a batched launch
+  int max_requests = 0;
+};
+hipError_t batch_solve_alloc(BatchSolveBuffers& B, int max_requests);
+void batch_solve_free(BatchSolveBuffers& B);
+struct BatchRun {
+  virtual ~BatchRun() = default;
+  virtual hipError_t start() = 0;     // initial residuals of every request
+  virtual hipError_t advance() = 0;   // enqueue check_every iterations of the running ones, read, decide
+  virtual bool finished() const = 0;
+  virtual const KrylovResult& result(int j) const = 0;
+};
+// requests: contexts with an assembled tangent and block-Jacobi; b = c->R,
+// x = c->delta; tol_u / tol_e per request.  Returns null (err set) on failure.
+std::unique_ptr<BatchRun> make_batch_run(hipStream_t st, const std::vector<lgdm_ctx*>& ctxs,
+                                         const std::vector<double>& tol_u, const std::vector<double>& tol_e,
+                                         const lgdm_solver_opts& o, BatchSolveBuffers& B);
 hipError_t krylov_setup(lgdm_ctx* c);  // block-Jacobi from the assembled matrix
 hipError_t krylov_solve(lgdm_ctx* c, const double* b, double* xout, const lgdm_solver_opts& o,
                         double tol_u, double tol_e, KrylovResult& res);

@@ -50,7 +50,9 @@ struct lgdm_batch {
   SlotDesc* desc_host = nullptr;  // pinned
   SlotDesc* desc_dev = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  BatchSolveBuffers bsolve;     // the batched IDR(s) solves of a tick
+  BatchSolveBuffers bsolve;     // the batched IDR(s) run's buffers
+  std::unique_ptr<BatchRun> run;  // requests whose linear solve is in progress (IDR(s))
+  int run_s = 0, run_nd = 0;      // the run's shadow-space dimension and unknowns per node
   std::string err;
 };
 
@@ -88,7 +90,9 @@ void release(lgdm_batch* b, Slot& s) {
   s = Slot();
 }
 
-void fail_slot(Slot& s, lgdm_status st) {
+void fail_slot(lgdm_batch* b, int i, lgdm_status st) {
+  Slot& s = b->slots[i];
+  if (s.solving && b->run) b->run->remove(i);
   s.state = LGDM_SLOT_FAILED;
   s.last_status = st;
   s.solving = false;
@@ -166,6 +170,7 @@ lgdm_status lgdm_batch_destroy(lgdm_batch* b) {
   if (b->desc_dev) (void)hipFree(b->desc_dev);
   if (b->ev0) (void)hipEventDestroy(b->ev0);
   if (b->ev1) (void)hipEventDestroy(b->ev1);
+  b->run.reset();
   batch_solve_free(b->bsolve);
   delete b;
   return LGDM_OK;
@@ -221,18 +226,33 @@ lgdm_status lgdm_batch_tick(lgdm_batch* b, const lgdm_solver_opts* o, lgdm_tick_
   if (!b) return LGDM_ERR_INVALID_ARG;
   const auto t0 = std::chrono::steady_clock::now();
   const lgdm_solver_opts op = fill_opts(o);
+  const bool idr = op.krylov_method != LGDM_KRYLOV_BICGSTAB;
   lgdm_tick_report R{};
   BHIP(b, hipSetDevice(b->device), "set device");
-  // 1. requests between increments start their next load step
+  // the batched IDR(s) run persists across ticks; it is rebuilt only when
+  // it is empty and the options or the element type changed
+  if (idr && b->dim != 0 && (!b->run || ((b->run_s != op.idr_s || b->run_nd != b->dim + 1) &&
+                                           b->run->active() == 0))) {
+    b->run.reset();
+    b->run = make_batch_run(b->stream, b->dim + 1, b->precision == LGDM_MIXED, op, b->bsolve);
+    b->run_s = op.idr_s;
+    b->run_nd = b->dim + 1;
+  }
+  if (b->run) b->run->set_opts(op);
+  // 1. requests between Newton iterations: those between increments start
+  //    their next load step
   std::vector<int> act;
+  int running = 0;
   for (int i = 0; i < (int)b->slots.size(); ++i) {
     Slot& s = b->slots[i];
     if (s.state != LGDM_SLOT_RUNNING) continue;
+    running++;
+    if (s.solving) continue;
     if (!s.in_increment) {
       const double lam = (double)(s.ctx->increment + 1) / (double)s.n_increments;
       lgdm_status st = lgdm_begin_increment(s.ctx, lam);
       if (st != LGDM_OK) {
-        fail_slot(s, st);
+        fail_slot(b, i, st);
         continue;
       }
       s.in_increment = true;
@@ -241,42 +261,41 @@ lgdm_status lgdm_batch_tick(lgdm_batch* b, const lgdm_solver_opts* o, lgdm_tick_
     act.push_back(i);
   }
   for (int i : act) BHIP(b, hipStreamSynchronize(b->slots[i].stream), "slot sync");
-  R.running = (int)act.size();
-  if (act.empty()) {
-    if (rep) *rep = R;
-    return LGDM_OK;
+  R.running = running;
+  // 2. one fused launch of each element kernel over those requests
+  if (!act.empty()) {
+    int64_t gpb = 0, nodeb = 0;
+    for (size_t j = 0; j < act.size(); ++j) {
+      lgdm_ctx* c = b->slots[act[j]].ctx;
+      SlotDesc& d = b->desc_host[j];
+      d.gp = gp_args(c);
+      d.node = node_args(c);
+      d.mp = make_params(c->mat, c->dim);
+      d.gp_block0 = gpb;
+      d.node_block0 = nodeb;
+      gpb += gp_kernel_blocks(c);
+      nodeb += node_kernel_blocks(c);
+      R.gauss_points += c->ngauss;
+    }
+    BHIP(b, hipMemcpyAsync(b->desc_dev, b->desc_host, act.size() * sizeof(SlotDesc), hipMemcpyHostToDevice,
+                           b->stream), "slot table");
+    BHIP(b, hipEventRecord(b->ev0, b->stream), "event");
+    BHIP(b, launch_fused_assembly(b->stream, b->dim, b->precision == LGDM_MIXED, b->desc_dev, (int)act.size(),
+                                  gpb, nodeb), "fused assembly");
+    BHIP(b, hipEventRecord(b->ev1, b->stream), "event");
+    for (int i : act) {
+      lgdm_ctx* c = b->slots[i].ctx;
+      BHIP(b, launch_norm_reduce_on(c, b->stream), "norms");
+      BHIP(b, hipMemcpyAsync(c->norms_host, c->norms_dev, NORM_SLOTS * sizeof(double), hipMemcpyDeviceToHost,
+                             b->stream), "norms");
+    }
+    BHIP(b, hipStreamSynchronize(b->stream), "fused assembly");
+    float ms = 0.f;
+    BHIP(b, hipEventElapsedTime(&ms, b->ev0, b->ev1), "event time");
+    R.t_assembly_ms = ms;
   }
-  // 2. one fused launch of each element kernel over every running request
-  int64_t gpb = 0, nodeb = 0;
-  for (size_t j = 0; j < act.size(); ++j) {
-    lgdm_ctx* c = b->slots[act[j]].ctx;
-    SlotDesc& d = b->desc_host[j];
-    d.gp = gp_args(c);
-    d.node = node_args(c);
-    d.mp = make_params(c->mat, c->dim);
-    d.gp_block0 = gpb;
-    d.node_block0 = nodeb;
-    gpb += gp_kernel_blocks(c);
-    nodeb += node_kernel_blocks(c);
-    R.gauss_points += c->ngauss;
-  }
-  BHIP(b, hipMemcpyAsync(b->desc_dev, b->desc_host, act.size() * sizeof(SlotDesc), hipMemcpyHostToDevice,
-                         b->stream), "slot table");
-  BHIP(b, hipEventRecord(b->ev0, b->stream), "event");
-  BHIP(b, launch_fused_assembly(b->stream, b->dim, b->precision == LGDM_MIXED, b->desc_dev, (int)act.size(),
-                                gpb, nodeb), "fused assembly");
-  BHIP(b, hipEventRecord(b->ev1, b->stream), "event");
-  for (int i : act) {
-    lgdm_ctx* c = b->slots[i].ctx;
-    BHIP(b, launch_norm_reduce_on(c, b->stream), "norms");
-    BHIP(b, hipMemcpyAsync(c->norms_host, c->norms_dev, NORM_SLOTS * sizeof(double), hipMemcpyDeviceToHost,
-                           b->stream), "norms");
-  }
-  BHIP(b, hipStreamSynchronize(b->stream), "fused assembly");
-  float ms = 0.f;
-  BHIP(b, hipEventElapsedTime(&ms, b->ev0, b->ev1), "event time");
-  R.t_assembly_ms = ms;
-  // 3. per-request decisions: commit, fail, or solve
+  // 3. per-request decisions: commit, fail, or start a solve
+  std::vector<int> solve;
   for (int i : act) {
     Slot& s = b->slots[i];
     lgdm_ctx* c = s.ctx;
@@ -284,7 +303,7 @@ lgdm_status lgdm_batch_tick(lgdm_batch* b, const lgdm_solver_opts* o, lgdm_tick_
     c->assembled = true;
     s.assemblies_total++;
     if (c->last_norms[5] != 0.0 || !std::isfinite(c->last_norms[0]) || !std::isfinite(c->last_norms[1])) {
-      fail_slot(s, LGDM_ERR_NAN);
+      fail_slot(b, i, LGDM_ERR_NAN);
       continue;
     }
     if (converged(c, op.tol_newton)) {
@@ -293,7 +312,7 @@ lgdm_status lgdm_batch_tick(lgdm_batch* b, const lgdm_solver_opts* o, lgdm_tick_
                              c->stream), "max damage");
       lgdm_status st = lgdm_commit_increment(c);   // synchronises the slot stream
       if (st != LGDM_OK) {
-        fail_slot(s, st);
+        fail_slot(b, i, st);
         continue;
       }
       s.max_damage = c->norms_host[12];
@@ -306,87 +325,89 @@ lgdm_status lgdm_batch_tick(lgdm_batch* b, const lgdm_solver_opts* o, lgdm_tick_
       continue;
     }
     if (s.newton >= op.max_newton) {
-      fail_slot(s, LGDM_ERR_NOT_CONVERGED);
+      fail_slot(b, i, LGDM_ERR_NOT_CONVERGED);
       continue;
     }
     BHIP(b, krylov_setup(c), "block-Jacobi setup");
     double tol_u = op.tol_krylov, tol_e = op.tol_krylov;
     newton_forcing(c, op, tol_u, tol_e);
-    if (op.krylov_method == LGDM_KRYLOV_BICGSTAB) {
-      s.run = make_krylov_run(c, c->R, c->delta, op, tol_u, tol_e);
-      BHIP(b, s.run->start(), "Krylov start");
-    }
     s.tol_u = tol_u;
     s.tol_e = tol_e;
     s.solving = true;
     R.solves++;
+    solve.push_back(i);
   }
   // 4. the solves
-  if (op.krylov_method == LGDM_KRYLOV_BICGSTAB) {
-    // one run per request on its own stream, interleaved by the host
+  std::vector<int> done;
+  if (idr && b->run) {
+    // IDR(s): new solves join the persistent batched run (every kernel one
+    // launch over all requests in it); rounds of check_every iterations run
+    // until some solve ends, at most MAX_ROUNDS, so that a request's Newton
+    // iterations follow its own solves rather than the slowest request's
+    constexpr int MAX_ROUNDS = 16;
+    for (int i : solve) {
+      Slot& s = b->slots[i];
+      BHIP(b, hipStreamSynchronize(s.stream), "block-Jacobi setup");
+      BHIP(b, b->run->add(i, s.ctx, s.tol_u, s.tol_e), "batched Krylov start");
+    }
+    std::vector<int> ids;
+    std::vector<KrylovResult> res;
+    for (int round = 0; round < MAX_ROUNDS && b->run->active() > 0; ++round) {
+      BHIP(b, b->run->advance(), "batched Krylov iterations");
+      b->run->take_finished(ids, res);
+      for (size_t k = 0; k < ids.size(); ++k) {
+        b->slots[ids[k]].kres = res[k];
+        done.push_back(ids[k]);
+      }
+      if (!done.empty()) break;
+    }
+  } else {
+    // BiCGSTAB: one run per request on its own stream, interleaved by the host
+    for (int i : solve) {
+      Slot& s = b->slots[i];
+      s.run = make_krylov_run(s.ctx, s.ctx->R, s.ctx->delta, op, s.tol_u, s.tol_e);
+      BHIP(b, s.run->start(), "Krylov start");
+    }
     bool pending = true;
     while (pending) {
       pending = false;
-      for (int i : act) {
+      for (int i : solve) {
         Slot& s = b->slots[i];
-        if (!s.solving || !s.run) continue;
         BHIP(b, s.run->check(), "Krylov check");
         if (s.run->finished()) continue;
         pending = true;
         if (!s.run->needs_check()) BHIP(b, s.run->launch(), "Krylov iterations");
       }
     }
-    for (int i : act) {
+    for (int i : solve) {
       Slot& s = b->slots[i];
-      if (!s.solving) continue;
+      BHIP(b, hipStreamSynchronize(s.stream), "Krylov");
       s.kres = s.run->result();
       s.run.reset();
-    }
-  } else {
-    // IDR(s): one batched run, every kernel one launch over all requests
-    std::vector<lgdm_ctx*> cs;
-    std::vector<double> tu, te;
-    std::vector<int> who;
-    for (int i : act) {
-      Slot& s = b->slots[i];
-      if (!s.solving) continue;
-      BHIP(b, hipStreamSynchronize(s.stream), "block-Jacobi setup");
-      cs.push_back(s.ctx);
-      tu.push_back(s.tol_u);
-      te.push_back(s.tol_e);
-      who.push_back(i);
-    }
-    if (!cs.empty()) {
-      std::unique_ptr<BatchRun> run = make_batch_run(b->stream, cs, tu, te, op, b->bsolve);
-      if (!run) return bfail(b, LGDM_ERR_INVALID_ARG, "batched solve: requests of mixed type");
-      BHIP(b, run->start(), "batched Krylov start");
-      while (!run->finished()) BHIP(b, run->advance(), "batched Krylov iterations");
-      // the last round may have enqueued copies of best iterates
-      BHIP(b, hipStreamSynchronize(b->stream), "batched Krylov");
-      for (size_t j = 0; j < who.size(); ++j) b->slots[who[j]].kres = run->result((int)j);
+      done.push_back(i);
     }
   }
-  // 5. Newton update of the solved requests
-  for (int i : act) {
+  // 5. Newton update of the requests whose solves ended
+  for (int i : done) {
     Slot& s = b->slots[i];
     if (!s.solving) continue;
     s.solving = false;
     R.krylov_iters += s.kres.iters;
     s.krylov_total += s.kres.iters;
     if (s.kres.status == LGDM_ERR_NAN) {
-      fail_slot(s, LGDM_ERR_NAN);
+      fail_slot(b, i, LGDM_ERR_NAN);
       continue;
     }
     if (s.kres.status != LGDM_OK && !s.kres.improved) {
       // a correction no better than none would repeat this iteration unchanged
-      fail_slot(s, LGDM_ERR_NOT_CONVERGED);
+      fail_slot(b, i, LGDM_ERR_NOT_CONVERGED);
       continue;
     }
     BHIP(b, launch_axpy(s.ctx, s.ctx->x, s.ctx->delta, 1.0, s.ctx->ndof), "update");
     s.newton++;
     s.newton_total++;
   }
-  for (int i : act)
+  for (int i : done)
     if (b->slots[i].stream) BHIP(b, hipStreamSynchronize(b->slots[i].stream), "slot sync");
   R.t_tick_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (rep) *rep = R;

@@ -1432,45 +1432,81 @@ template <typename T, int ND, int S>
 struct BatchIdr final : BatchRun {
   static constexpr int G = Solver<T, ND>::G;
   hipStream_t st;
-  std::vector<lgdm_ctx*> ctx;
+  lgdm_solver_opts o;
+  BatchSolveBuffers& B;
+  std::vector<lgdm_ctx*> ctx;          // by id; null when not in the run
   std::vector<RunControl> rc;
   std::vector<Idr<T, ND, S>> one;
   std::vector<double> se;
-  lgdm_solver_opts o;
-  BatchSolveBuffers& B;
+  std::vector<int> ended;              // ids whose solves ended, not yet taken
   KSlot* tab_host;
   KSlot* tab_dev;
-  int nrun = 0;                // requests in the device table
-  int64_t tot[3] = {0, 0, 0};  // workgroups per launch family
-  int every = 16;
+  int nrun = 0;                        // requests in the device table
+  int64_t tot[3] = {0, 0, 0};          // workgroups per launch family
   bool table_stale = true;
 
-  BatchIdr(hipStream_t s, const std::vector<lgdm_ctx*>& c, const std::vector<double>& tu,
-           const std::vector<double>& te, const lgdm_solver_opts& o_, BatchSolveBuffers& buf)
-      : st(s), ctx(c), rc(c.size()), one(c.size()), se(c.size()), o(o_), B(buf) {
+  BatchIdr(hipStream_t s, const lgdm_solver_opts& o_, BatchSolveBuffers& buf)
+      : st(s), o(o_), B(buf), ctx(buf.max_requests, nullptr), rc(buf.max_requests), one(buf.max_requests),
+        se(buf.max_requests, 0.0) {
     tab_host = static_cast<KSlot*>(B.table_host);
     tab_dev = static_cast<KSlot*>(B.table_dev);
-    every = o.check_every > 0 ? o.check_every : 16;
-    for (size_t j = 0; j < ctx.size(); ++j) {
-      one[j].bind(ctx[j], st, B.sc_dev + (int64_t)j * KSCAL_DOUBLES, ctx[j]->kpart);
-      rc[j].setup(tu[j], te[j], Idr<T, ND, S>::F32, 1);
-      se[j] = ctx[j]->mat.E / ctx[j]->mat.h;
-    }
   }
-  double* sc(size_t j) { return B.sc_dev + (int64_t)j * KSCAL_DOUBLES; }
-  double* xbest(size_t j) { return ctx[j]->kv + (int64_t)(KV_VECS - 1) * ctx[j]->ndof; }
+  double* sc(int j) { return B.sc_dev + (int64_t)j * KSCAL_DOUBLES; }
+  double* xbest(int j) { return ctx[j]->kv + (int64_t)(KV_VECS - 1) * ctx[j]->ndof; }
+  int every() const { return o.check_every > 0 ? o.check_every : 16; }
+  void set_opts(const lgdm_solver_opts& o_) override { o = o_; }
 
-  void reset_scalars(size_t j) {
+  void reset_scalars(int j) {
     set_scalars_kernel<<<1, 64, 0, st>>>(sc(j), rc[j].tol_u * rc[j].tol_u, rc[j].tol_e * rc[j].tol_e, se[j],
                                          BREAK_REL);
   }
 
-  // device table of the running requests
+  hipError_t add(int j, lgdm_ctx* c, double tu, double te) override {
+    if (j < 0 || j >= B.max_requests || ctx[j]) return hipErrorInvalidValue;
+    ctx[j] = c;
+    rc[j] = RunControl{};
+    rc[j].setup(tu, te, Idr<T, ND, S>::F32, 1);
+    se[j] = c->mat.E / c->mat.h;
+    one[j].bind(c, st, sc(j), c->kpart);
+    reset_scalars(j);
+    hipError_t e = hipMemsetAsync(c->delta, 0, c->ndof * sizeof(double), st);
+    if (e != hipSuccess) return e;
+    one[j].begin(c->R);
+    table_stale = true;
+    return hipGetLastError();
+  }
+
+  // stop a request's solve on the device and drop it from the run
+  hipError_t stop(int j) {
+    table_stale = true;
+    return hipMemcpyAsync(sc(j) + K_DONE, B.one_host, sizeof(double), hipMemcpyHostToDevice, st);
+  }
+  void remove(int j) override {
+    if (j < 0 || j >= B.max_requests || !ctx[j]) return;
+    (void)stop(j);
+    ctx[j] = nullptr;
+  }
+  int active() const override {
+    int n = 0;
+    for (auto* c : ctx) n += c != nullptr;
+    return n;
+  }
+  void take_finished(std::vector<int>& ids, std::vector<KrylovResult>& res) override {
+    ids.clear();
+    res.clear();
+    for (int j : ended) {
+      ids.push_back(j);
+      res.push_back(rc[j].res);
+    }
+    ended.clear();
+  }
+
+  // device table of the requests in the run
   hipError_t build_table() {
     nrun = 0;
     tot[0] = tot[1] = tot[2] = 0;
-    for (size_t j = 0; j < ctx.size(); ++j) {
-      if (rc[j].fin) continue;
+    for (int j = 0; j < B.max_requests; ++j) {
+      if (!ctx[j]) continue;
       const Idr<T, ND, S>& q = one[j];
       KSlot& k = tab_host[nrun++];
       k.nn = q.nn;
@@ -1521,12 +1557,12 @@ struct BatchIdr final : BatchRun {
 
   // read every request's scalars and act on them
   hipError_t decide_all(int64_t ran) {
-    hipError_t e = hipMemcpyAsync(B.sc_host, B.sc_dev, ctx.size() * KSCAL_DOUBLES * sizeof(double),
+    hipError_t e = hipMemcpyAsync(B.sc_host, B.sc_dev, (size_t)B.max_requests * KSCAL_DOUBLES * sizeof(double),
                                   hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return e;
-    for (size_t j = 0; j < ctx.size(); ++j) {
-      if (rc[j].fin) continue;
+    for (int j = 0; j < B.max_requests; ++j) {
+      if (!ctx[j]) continue;
       bool save = false;
       const RunControl::Action a = rc[j].decide(B.sc_host + (int64_t)j * KSCAL_DOUBLES, o, ran, save);
       const size_t bytes = ctx[j]->ndof * sizeof(double);
@@ -1540,58 +1576,43 @@ struct BatchIdr final : BatchRun {
         one[j].restart(ctx[j]->R, ctx[j]->delta);
       }
       if (rc[j].fin) {
-        // the host stopped it: later batched launches must skip it
-        if ((e = hipMemcpyAsync(sc(j) + K_DONE, B.one_host, sizeof(double), hipMemcpyHostToDevice, st)) !=
-            hipSuccess)
-          return e;
-        table_stale = true;
+        if ((e = stop(j)) != hipSuccess) return e;
+        ctx[j] = nullptr;
+        ended.push_back(j);
       }
     }
     return hipGetLastError();
   }
 
-  hipError_t start() override {
-    for (size_t j = 0; j < ctx.size(); ++j) {
-      reset_scalars(j);
-      hipError_t e = hipMemsetAsync(ctx[j]->delta, 0, ctx[j]->ndof * sizeof(double), st);
-      if (e != hipSuccess) return e;
-      one[j].begin(ctx[j]->R);
-    }
-    hipError_t e = decide_all(0);
-    if (e != hipSuccess) return e;
-    return build_table();
-  }
-
+  // requests added since the last round are checked in this round too: the
+  // scalars of a request whose start already converged say so with no iteration
   hipError_t advance() override {
-    if (finished()) return hipSuccess;
     if (table_stale) {
       hipError_t e = build_table();
       if (e != hipSuccess) return e;
     }
-    const int ncyc = Idr<T, ND, S>::cycles_for(every);
-    for (int i = 0; i < ncyc; ++i) cycle();
-    hipError_t e = hipGetLastError();
+    int64_t ran = 0;
+    if (nrun > 0) {
+      const int ncyc = Idr<T, ND, S>::cycles_for(every());
+      for (int i = 0; i < ncyc; ++i) cycle();
+      ran = (int64_t)ncyc * (S + 1);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    hipError_t e = decide_all(ran);
     if (e != hipSuccess) return e;
-    return decide_all((int64_t)ncyc * (S + 1));
+    // the copies enqueued by the decisions land before the caller reads the results
+    return hipStreamSynchronize(st);
   }
-
-  bool finished() const override {
-    for (const auto& r : rc)
-      if (!r.fin) return false;
-    return true;
-  }
-  const KrylovResult& result(int j) const override { return rc[j].res; }
 };
 
 template <typename T, int ND>
-std::unique_ptr<BatchRun> make_batch_impl(hipStream_t st, const std::vector<lgdm_ctx*>& c,
-                                          const std::vector<double>& tu, const std::vector<double>& te,
-                                          const lgdm_solver_opts& o, BatchSolveBuffers& B) {
+std::unique_ptr<BatchRun> make_batch_impl(hipStream_t st, const lgdm_solver_opts& o, BatchSolveBuffers& B) {
   switch (o.idr_s) {
-    case 1: return std::unique_ptr<BatchRun>(new BatchIdr<T, ND, 1>(st, c, tu, te, o, B));
-    case 2: return std::unique_ptr<BatchRun>(new BatchIdr<T, ND, 2>(st, c, tu, te, o, B));
-    case 8: return std::unique_ptr<BatchRun>(new BatchIdr<T, ND, 8>(st, c, tu, te, o, B));
-    default: return std::unique_ptr<BatchRun>(new BatchIdr<T, ND, 4>(st, c, tu, te, o, B));
+    case 1: return std::unique_ptr<BatchRun>(new BatchIdr<T, ND, 1>(st, o, B));
+    case 2: return std::unique_ptr<BatchRun>(new BatchIdr<T, ND, 2>(st, o, B));
+    case 8: return std::unique_ptr<BatchRun>(new BatchIdr<T, ND, 8>(st, o, B));
+    default: return std::unique_ptr<BatchRun>(new BatchIdr<T, ND, 4>(st, o, B));
   }
 }
 
@@ -1659,20 +1680,13 @@ std::unique_ptr<KrylovRun> make_krylov_run(lgdm_ctx* c, const double* b, double*
   }
 }
 
-std::unique_ptr<BatchRun> make_batch_run(hipStream_t st, const std::vector<lgdm_ctx*>& ctxs,
-                                         const std::vector<double>& tol_u, const std::vector<double>& tol_e,
-                                         const lgdm_solver_opts& o, BatchSolveBuffers& B) {
-  if (ctxs.empty() || (int)ctxs.size() > B.max_requests) return nullptr;
-  const bool mixed = ctxs[0]->precision == LGDM_MIXED;
-  for (lgdm_ctx* c : ctxs)
-    if (c->nd != ctxs[0]->nd || (c->precision == LGDM_MIXED) != mixed) return nullptr;
-  switch (ctxs[0]->nd) {
-    case 2: return mixed ? make_batch_impl<float, 2>(st, ctxs, tol_u, tol_e, o, B)
-                         : make_batch_impl<double, 2>(st, ctxs, tol_u, tol_e, o, B);
-    case 3: return mixed ? make_batch_impl<float, 3>(st, ctxs, tol_u, tol_e, o, B)
-                         : make_batch_impl<double, 3>(st, ctxs, tol_u, tol_e, o, B);
-    default: return mixed ? make_batch_impl<float, 4>(st, ctxs, tol_u, tol_e, o, B)
-                          : make_batch_impl<double, 4>(st, ctxs, tol_u, tol_e, o, B);
+std::unique_ptr<BatchRun> make_batch_run(hipStream_t st, int nd, bool mixed, const lgdm_solver_opts& o,
+                                         BatchSolveBuffers& B) {
+  if (o.krylov_method == LGDM_KRYLOV_BICGSTAB || B.max_requests <= 0) return nullptr;
+  switch (nd) {
+    case 2: return mixed ? make_batch_impl<float, 2>(st, o, B) : make_batch_impl<double, 2>(st, o, B);
+    case 3: return mixed ? make_batch_impl<float, 3>(st, o, B) : make_batch_impl<double, 3>(st, o, B);
+    default: return mixed ? make_batch_impl<float, 4>(st, o, B) : make_batch_impl<double, 4>(st, o, B);
   }
 }
 

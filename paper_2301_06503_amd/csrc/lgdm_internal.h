@@ -237,18 +237,25 @@ struct BatchSolveBuffers {
 };
 hipError_t batch_solve_alloc(BatchSolveBuffers& B, int max_requests);
 void batch_solve_free(BatchSolveBuffers& B);
+// A persistent batched run: requests join it with add() (tangent and
+// block-Jacobi assembled; b = c->R, x = c->delta) and leave it when their
+// solve ends (take_finished) or when removed; every advance() enqueues
+// check_every iterations of all of them, reads their scalars and decides.
+// Request ids are the batch's slot numbers (< B.max_requests).
 struct BatchRun {
   virtual ~BatchRun() = default;
-  virtual hipError_t start() = 0;     // initial residuals of every request
-  virtual hipError_t advance() = 0;   // enqueue check_every iterations of the running ones, read, decide
-  virtual bool finished() const = 0;
-  virtual const KrylovResult& result(int j) const = 0;
+  virtual hipError_t add(int id, lgdm_ctx* c, double tol_u, double tol_e) = 0;
+  virtual void remove(int id) = 0;
+  virtual hipError_t advance() = 0;
+  virtual int active() const = 0;
+  // ids whose solves ended since the last call, with their results
+  virtual void take_finished(std::vector<int>& ids, std::vector<KrylovResult>& res) = 0;
+  virtual void set_opts(const lgdm_solver_opts& o) = 0;
 };
-// requests: contexts with an assembled tangent and block-Jacobi; b = c->R,
-// x = c->delta; tol_u / tol_e per request.  Returns null (err set) on failure.
-std::unique_ptr<BatchRun> make_batch_run(hipStream_t st, const std::vector<lgdm_ctx*>& ctxs,
-                                         const std::vector<double>& tol_u, const std::vector<double>& tol_e,
-                                         const lgdm_solver_opts& o, BatchSolveBuffers& B);
+// a run for contexts of nd unknowns per node and the given precision; null
+// if the options do not select IDR(s)
+std::unique_ptr<BatchRun> make_batch_run(hipStream_t st, int nd, bool mixed, const lgdm_solver_opts& o,
+                                         BatchSolveBuffers& B);
 hipError_t krylov_setup(lgdm_ctx* c);  // block-Jacobi from the assembled matrix
 hipError_t krylov_solve(lgdm_ctx* c, const double* b, double* xout, const lgdm_solver_opts& o,
                         double tol_u, double tol_e, KrylovResult& res);

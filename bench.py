@@ -252,8 +252,9 @@ def main():
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--tol-krylov", type=float, default=1e-6,
-                    help="tightest relative tolerance of a Newton correction")
+    ap.add_argument("--tol-krylov", type=float, default=1e-3,
+                    help="relative tolerance of the Newton corrections far from convergence (the last "
+                         "ones solve only as far as the Newton test needs)")
     ap.add_argument("--krylov", default="idr", choices=["idr", "bicgstab"])
     ap.add_argument("--idr-s", type=int, default=4)
     ap.add_argument("--fixed-forcing", action="store_true",

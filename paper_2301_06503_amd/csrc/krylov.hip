@@ -53,9 +53,11 @@ constexpr double FLOOR_REL2 = 1e-30;
 // have comparable magnitudes, and a field whose right-hand side is far below
 // the other's cannot be resolved below the operator's rounding of the other
 constexpr double FIELD_FLOOR2 = 1e-6;
-// iterations without a new best residual after which a solve has stagnated:
-// at least this many, and at least as many as the solve has run (IDR(s)
-// residuals can plateau for hundreds of steps before they drop)
+// iterations without a new best residual after which a solve has stagnated
+// and returns its best iterate.  A solve that has not yet improved on its
+// zero start waits as long as it has run (IDR(s) residuals can plateau for
+// hundreds of steps before they drop; returning nothing would repeat the
+// Newton iteration unchanged).
 constexpr int STALL_ITERS = 500;
 // IDR(s) minimal-residual step: omega is enlarged until the cosine of the
 // angle between t and r it implies is at least this (van Gijzen & Sonneveld)
@@ -1328,7 +1330,8 @@ struct RunControl {
       return NONE;
     }
     stall += ran;
-    if (stall >= std::max<int64_t>(STALL_ITERS, res.iters) || res.iters >= o.max_krylov) {
+    const int64_t window = res.improved ? STALL_ITERS : std::max<int64_t>(STALL_ITERS, res.iters);
+    if (stall >= window || res.iters >= o.max_krylov) {
       res.status = LGDM_ERR_NOT_CONVERGED;
       fin = true;
       return RETURN_BEST;

@@ -49,7 +49,7 @@ class ServingLoop:
         self.requests = sorted(requests, key=lambda r: r.arrival_s)
         self.batch = binding.Batch(device=0, precision=precision, max_slots=max_slots,
                                    hbm_budget_bytes=hbm_budget_bytes)
-        self.opts = opts or binding.solver_opts(max_newton=40, tol_newton=1e-8, tol_krylov=1e-6,
+        self.opts = opts or binding.solver_opts(max_newton=40, tol_newton=1e-8, tol_krylov=1e-3,
                                                 max_krylov=20000, check_every=32)
         self.records: Dict[int, RequestRecord] = {}
         self.keep_results = keep_results

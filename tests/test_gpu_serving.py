@@ -149,3 +149,29 @@ def test_fused_assembly_matches_single(precision):
         np.testing.assert_array_equal(Db, ctx.query(binding.FIELD_DAMAGE_TRIAL))
         ctx.close()
     b.close()
+
+
+def test_alone_vs_mix_bitwise_large_requests():
+    """Requests large enough that the batched solve's per-request workgroup
+    counts hit their caps (grid-stride within the request) give the same
+    results alone and beside smaller requests."""
+    from paper_2301_06503_amd import binding
+    mk = lambda nx, inc, **kw: W.sen2d(nx=nx, ny=nx // 2, notch_len=nx // 4, n_increments=inc,
+                                       u_top=0.1 * inc / 200, material=W.base_material(**kw))
+    probs = [mk(210, 3), mk(40, 4, kappa0=6e-5), mk(150, 3, E=3e4)]
+    opts = binding.solver_opts(max_newton=40, tol_newton=1e-8, tol_krylov=1e-3, check_every=32)
+    alone = {}
+    for i, p in enumerate(probs):
+        b = binding.Batch(precision=1, max_slots=4)
+        alone[i] = _run(b, [p], [0], opts)[0]
+        b.close()
+    b = binding.Batch(precision=1, max_slots=4)
+    mix = _run(b, probs, [0, 0, 2], opts)
+    b.close()
+    for i in range(len(probs)):
+        xa, da, ia = alone[i]
+        xm, dm, im = mix[i]
+        print("request %d (%d dofs): %d Newton, identical %s" % (i, probs[i].ndof, ia["newton_total"],
+                                                                 np.array_equal(xa, xm)))
+        np.testing.assert_array_equal(xa, xm)
+        np.testing.assert_array_equal(da, dm)

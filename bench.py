@@ -256,7 +256,7 @@ def main():
                     help="relative tolerance of the Newton corrections far from convergence (the last "
                          "ones solve only as far as the Newton test needs)")
     ap.add_argument("--krylov", default="idr", choices=["idr", "bicgstab"])
-    ap.add_argument("--idr-s", type=int, default=4)
+    ap.add_argument("--idr-s", type=int, default=8)
     ap.add_argument("--fixed-forcing", action="store_true",
                     help="solve every Newton correction to --tol-krylov (default: adaptive forcing)")
     ap.add_argument("--max-krylov", type=int, default=20000)

@@ -110,7 +110,7 @@ typedef struct lgdm_solver_opts {
   int32_t check_every;     /* 16     Krylov iterations between host convergence reads */
   int32_t max_restarts;    /* 8      Krylov restarts after breakdown                */
   int32_t krylov_method;   /* LGDM_KRYLOV_IDRS                                      */
-  int32_t idr_s;           /* 4      IDR shadow-space dimension: 1, 2, 4 or 8 (other
+  int32_t idr_s;           /* 8      IDR shadow-space dimension: 1, 2, 4 or 8 (other
                                      values round up to the next of these, max 8) */
   int32_t forcing;         /* LGDM_FORCING_ADAPTIVE                                 */
   int32_t reserved;
@@ -122,7 +122,10 @@ typedef struct lgdm_solver_opts {
  *                         ||F_f|| / ||R_f||)) with m = 0.1 (FP64) or 0.01
  *                         (mixed): corrections far from convergence solve to
  *                         tol_krylov, the last ones only as far as the Newton
- *                         test needs.
+ *                         test needs.  From the 9th Newton iteration of an
+ *                         increment on, tol_krylov is replaced by
+ *                         min(tol_krylov, 1e-8): the inexact iterates of a
+ *                         strongly nonlinear increment can cycle.
  *  LGDM_FORCING_FIXED     every correction to tol_krylov.
  * lgdm_solve_linear always solves to tol_krylov.  Convergence of Newton is
  * judged on the FP64 residual either way. */

@@ -412,6 +412,7 @@ lgdm_status lgdm_begin_increment(lgdm_ctx* c, double lambda) {
   HIPCHECK(c, hipMemcpyAsync(c->x_save, c->x, c->ndof * sizeof(double), hipMemcpyDeviceToDevice, c->stream), "save x");
   HIPCHECK(c, launch_set_dirichlet(c, lambda), "set Dirichlet values");
   c->in_increment = true;
+  c->nw_iter = 0;
   return LGDM_OK;
 }
 

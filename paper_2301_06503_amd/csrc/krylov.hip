@@ -40,7 +40,7 @@ constexpr int MAX_GRID = KPART_BLOCKS;
 // device scalar slots
 enum {
   K_RHO = 0, K_RHO_OLD, K_ALPHA, K_OMEGA, K_BETA, K_RU, K_RE, K_BU, K_BE, K_DONE, K_STATUS,
-  K_ITER, K_TOL2, K_SE, K_RH2, K_B2, K_BRK, K_TOL2E, K_NSLOTS = 24
+  K_ITER, K_TOL2, K_SE, K_RH2, K_B2, K_BRK, K_TOL2E, K_SEED, K_NSLOTS = 24
 };
 // status values
 enum { KS_RUN = 0, KS_CONV = 1, KS_BREAK = 2, KS_NAN = 3 };
@@ -49,6 +49,9 @@ enum { KS_RUN = 0, KS_CONV = 1, KS_BREAK = 2, KS_NAN = 3 };
 constexpr double BREAK_REL = 1e-14;
 // residual at this fraction of |S b| is at the FP64 precision floor: stop
 constexpr double FLOOR_REL2 = 1e-30;
+// a recurrence residual grown beyond this multiple of |S b| (squared) has
+// left any useful range: a breakdown, restarted from the best iterate
+constexpr double GROWTH2 = 1e8;
 // a field is judged against max(|b_field|, FIELD_FLOOR |b|): the scaled fields
 // have comparable magnitudes, and a field whose right-hand side is far below
 // the other's cannot be resolved below the operator's rounding of the other
@@ -202,6 +205,7 @@ __device__ __forceinline__ void spmv_body(int64_t blk, int64_t nblk, int64_t n_n
   __shared__ double sm[NQ][BS];
   if (sc[K_DONE] != 0.0) return;
   const double se = sc[K_SE];
+  const int seed = (int)sc[K_SEED];
   const int lane = threadIdx.x % G;
   const int64_t grp = (blk * BS + threadIdx.x) / G;
   const int64_t ngrp = nblk * BS / G;
@@ -245,7 +249,7 @@ __device__ __forceinline__ void spmv_body(int64_t blk, int64_t nblk, int64_t n_n
       }
       if (MODE == 3) {
 #pragma unroll
-        for (int q = 0; q < NP; ++q) d[q] += shadow_entry(q, row) * yt;
+        for (int q = 0; q < NP; ++q) d[q] += shadow_entry(seed + q, row) * yt;
         d[NP] += yt * yt;
       }
     }
@@ -319,7 +323,7 @@ __global__ void __launch_bounds__(BS) scalar_kernel(int nblk, const double* __re
       sc[K_DONE] = 1.0;
       return;
     }
-    if (om == 0.0 || rho == 0.0 || fabs(rho) <= sc[K_BRK] * sqrt(sc[K_RH2] * r2)) {
+    if (om == 0.0 || rho == 0.0 || fabs(rho) <= sc[K_BRK] * sqrt(sc[K_RH2] * r2) || r2 > GROWTH2 * sc[K_B2]) {
       sc[K_STATUS] = KS_BREAK;
       sc[K_DONE] = 1.0;
       return;
@@ -554,13 +558,15 @@ __global__ void __launch_bounds__(256) pair_sum_kernel(int nblk, const double* _
 }
 
 // tol2u, tol2e: squared relative tolerances of the u and ebar rows
-__global__ void set_scalars_kernel(double* sc, double tol2u, double tol2e, double se, double brk) {
+// seed: index offset of the IDR shadow vectors (a restart draws new ones)
+__global__ void set_scalars_kernel(double* sc, double tol2u, double tol2e, double se, double brk, int seed) {
   if (threadIdx.x == 0) {
     for (int i = 0; i < K_NSLOTS; ++i) sc[i] = 0.0;
     sc[K_TOL2] = tol2u;
     sc[K_TOL2E] = tol2e;
     sc[K_SE] = se;
     sc[K_BRK] = brk;
+    sc[K_SEED] = (double)seed;
   }
 }
 
@@ -611,6 +617,11 @@ __device__ __forceinline__ bool idr_norms(double* sc, double ru, double re) {
     sc[K_DONE] = 1.0;
     return true;
   }
+  if (ru + re > GROWTH2 * sc[K_B2]) {
+    sc[K_STATUS] = KS_BREAK;
+    sc[K_DONE] = 1.0;
+    return true;
+  }
   return false;
 }
 
@@ -635,6 +646,7 @@ __device__ __forceinline__ void idr_init_body(int64_t blk, int64_t nblk, int64_t
                                               const double* __restrict__ sc, double* __restrict__ part) {
   __shared__ double sm[4 + S][BS];
   const double se = sc[K_SE];
+  const int seed = (int)sc[K_SEED];
   double d[4 + S];
 #pragma unroll
   for (int q = 0; q < 4 + S; ++q) d[q] = 0.0;
@@ -646,7 +658,7 @@ __device__ __forceinline__ void idr_init_body(int64_t blk, int64_t nblk, int64_t
     d[fe ? 1 : 0] += rd * rd;
     d[fe ? 3 : 2] += sb * sb;
 #pragma unroll
-    for (int q = 0; q < S; ++q) d[4 + q] += shadow_entry(q, i) * rd;
+    for (int q = 0; q < S; ++q) d[4 + q] += shadow_entry(seed + q, i) * rd;
   }
   write_partials<4 + S>(d, part, blk, sm);
 }
@@ -886,6 +898,7 @@ __device__ __forceinline__ void idr_om_body(int64_t blk, int64_t nblk, int64_t n
   __shared__ double sm[2 + S][BS];
   if (sc[K_DONE] != 0.0) return;
   const double om = sc[I_OM];
+  const int seed = (int)sc[K_SEED];
   double d[2 + S];
 #pragma unroll
   for (int q = 0; q < 2 + S; ++q) d[q] = 0.0;
@@ -895,7 +908,7 @@ __device__ __forceinline__ void idr_om_body(int64_t blk, int64_t nblk, int64_t n
     x[i] += om * v[i];
     d[(i % ND == ND - 1) ? 1 : 0] += rd * rd;
 #pragma unroll
-    for (int q = 0; q < S; ++q) d[2 + q] += shadow_entry(q, i) * rd;
+    for (int q = 0; q < S; ++q) d[2 + q] += shadow_entry(seed + q, i) * rd;
   }
   write_partials<2 + S>(d, part, blk, sm);
 }
@@ -1248,7 +1261,9 @@ struct Idr {
 // The host side of one solve, shared by single and batched runs: reads the
 // device scalars after some iterations and decides what happens next.
 struct RunControl {
-  enum Action { NONE, RESTART, RETURN_BEST };
+  // RESTART: restart from the current iterate; RESTART_BEST: from the best
+  // one (the current one is worse); RETURN_BEST: finish with the best one
+  enum Action { NONE, RESTART, RESTART_BEST, RETURN_BEST };
   KrylovResult res{};
   double tol_u = 0, tol_e = 0;
   int64_t done_iters = 0;      // iterations before the last restart
@@ -1267,6 +1282,9 @@ struct RunControl {
     res.status = LGDM_ERR_NOT_CONVERGED;
   }
   double score() const { return std::max(res.rel_u / tol_u, res.rel_e / tol_e); }
+  // shadow-vector offset of the current (re)start: every restart of IDR(s)
+  // draws shadow vectors it has not used before
+  int seed() const { return IDR_SMAX * (res.restarts + replacements); }
 
   // h: the scalars after `ran` more iterations were enqueued.  save_best is
   // set when the current iterate is the best so far and must be copied.
@@ -1312,9 +1330,10 @@ struct RunControl {
         res.improved = res.iters > 0 && std::isfinite(score());
         return NONE;
       }
+      const bool worse = have_best && !(score() <= best);
       res.restarts++;
       done_iters = res.iters;
-      return RESTART;
+      return worse ? RESTART_BEST : RESTART;
     }
     const double sc = score();
     if (std::isfinite(sc) && sc < best * (1.0 - 1e-3)) {
@@ -1374,7 +1393,8 @@ struct KrylovRunImpl final : KrylovRun {
   }
 
   hipError_t start() override {
-    set_scalars_kernel<<<1, 64, 0, c->stream>>>(S.sc, rc.tol_u * rc.tol_u, rc.tol_e * rc.tol_e, se, BREAK_REL);
+    set_scalars_kernel<<<1, 64, 0, c->stream>>>(S.sc, rc.tol_u * rc.tol_u, rc.tol_e * rc.tol_e, se, BREAK_REL,
+                                                0);
     hipError_t e = hipMemsetAsync(xout, 0, c->ndof * sizeof(double), c->stream);
     if (e != hipSuccess) return e;
     S.begin(b);
@@ -1405,11 +1425,13 @@ struct KrylovRunImpl final : KrylovRun {
       e = hipMemcpyAsync(xbest, xout, c->ndof * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
       if (e != hipSuccess) return e;
     }
-    if (a == RunControl::RETURN_BEST && rc.have_best)
-      return hipMemcpyAsync(xout, xbest, c->ndof * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
-    if (a == RunControl::RESTART) {
+    if ((a == RunControl::RETURN_BEST || a == RunControl::RESTART_BEST) && rc.have_best) {
+      e = hipMemcpyAsync(xout, xbest, c->ndof * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+      if (e != hipSuccess || a == RunControl::RETURN_BEST) return e;
+    }
+    if (a == RunControl::RESTART || a == RunControl::RESTART_BEST) {
       set_scalars_kernel<<<1, 64, 0, c->stream>>>(S.sc, rc.tol_u * rc.tol_u, rc.tol_e * rc.tol_e, se,
-                                                  BREAK_REL);
+                                                  BREAK_REL, rc.seed());
       S.restart(b, xout);
       pending_read = true;
       return read_scalars();
@@ -1461,7 +1483,7 @@ struct BatchIdr final : BatchRun {
 
   void reset_scalars(int j) {
     set_scalars_kernel<<<1, 64, 0, st>>>(sc(j), rc[j].tol_u * rc[j].tol_u, rc[j].tol_e * rc[j].tol_e, se[j],
-                                         BREAK_REL);
+                                         BREAK_REL, rc[j].seed());
   }
 
   hipError_t add(int j, lgdm_ctx* c, double tu, double te) override {
@@ -1571,10 +1593,10 @@ struct BatchIdr final : BatchRun {
       const size_t bytes = ctx[j]->ndof * sizeof(double);
       if (save && (e = hipMemcpyAsync(xbest(j), ctx[j]->delta, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess)
         return e;
-      if (a == RunControl::RETURN_BEST && rc[j].have_best &&
+      if ((a == RunControl::RETURN_BEST || a == RunControl::RESTART_BEST) && rc[j].have_best &&
           (e = hipMemcpyAsync(ctx[j]->delta, xbest(j), bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess)
         return e;
-      if (a == RunControl::RESTART) {
+      if (a == RunControl::RESTART || a == RunControl::RESTART_BEST) {
         reset_scalars(j);
         one[j].restart(ctx[j]->R, ctx[j]->delta);
       }
@@ -1658,7 +1680,7 @@ lgdm_solver_opts fill_opts(const lgdm_solver_opts* o) {
   if (r.max_restarts <= 0) r.max_restarts = 8;
   if (r.krylov_method != LGDM_KRYLOV_BICGSTAB) r.krylov_method = LGDM_KRYLOV_IDRS;
   if (r.forcing != LGDM_FORCING_FIXED) r.forcing = LGDM_FORCING_ADAPTIVE;
-  r.idr_s = r.idr_s <= 0 ? 4 : (r.idr_s <= 1 ? 1 : (r.idr_s <= 2 ? 2 : (r.idr_s <= 4 ? 4 : 8)));
+  r.idr_s = r.idr_s <= 0 ? 8 : (r.idr_s <= 1 ? 1 : (r.idr_s <= 2 ? 2 : (r.idr_s <= 4 ? 4 : 8)));
   return r;
 }
 
@@ -1733,9 +1755,10 @@ hipError_t krylov_solve(lgdm_ctx* c, const double* b, double* xout, const lgdm_s
 
 // Inexact Newton: the relative tolerances of one Newton correction, per
 // field.  A correction needs no smaller linear residual than a fraction of
-// what the field may keep at convergence: tol_f = max(tol_krylov,
-// min(0.5, c * tol_newton * |F_f| / |R_f|)), so the early corrections solve to
-// tol_krylov and the last one only as far as the Newton test needs.  With an
+// what the field may keep at convergence: tol_f = max(eta,
+// min(0.5, c * tol_newton * |F_f| / |R_f|)) with eta = tol_krylov, so the
+// early corrections solve to tol_krylov and the last one only as far as the
+// Newton test needs.  With an
 // FP32-stored operator the linear residual left in a correction comes back
 // amplified in the next FP64 residual (by up to the FP32 rounding of the
 // tangent times its condition number), so mixed contexts keep a tenfold
@@ -1743,21 +1766,27 @@ hipError_t krylov_solve(lgdm_ctx* c, const double* b, double* xout, const lgdm_s
 void newton_forcing(lgdm_ctx* c, const lgdm_solver_opts& o, double& tol_u, double& tol_e) {
   tol_u = tol_e = o.tol_krylov;
   if (o.forcing == LGDM_FORCING_FIXED) return;
-  const double margin = c->precision == LGDM_MIXED ? 0.01 : 0.1;
   const double ru = std::sqrt(c->last_norms[0]), re = std::sqrt(c->last_norms[1]);
   const double fu = std::sqrt(c->last_norms[2]), fe = std::sqrt(c->last_norms[3]);
-  if (ru > 0) tol_u = std::max(o.tol_krylov, std::min(0.5, margin * o.tol_newton * fu / ru));
-  if (re > 0) tol_e = std::max(o.tol_krylov, std::min(0.5, margin * o.tol_newton * fe / re));
+  // an increment still unconverged after ACCURATE_AFTER Newton iterations is
+  // strongly nonlinear: its inexact iterates can cycle, so it continues with
+  // accurate corrections (the exact-Newton limit)
+  constexpr int ACCURATE_AFTER = 8;
+  const double eta = c->nw_iter++ >= ACCURATE_AFTER ? std::min(o.tol_krylov, 1e-8) : o.tol_krylov;
+  const double margin = c->precision == LGDM_MIXED ? 0.01 : 0.1;
+  tol_u = tol_e = eta;
+  if (ru > 0) tol_u = std::max(eta, std::min(0.5, margin * o.tol_newton * fu / ru));
+  if (re > 0) tol_e = std::max(eta, std::min(0.5, margin * o.tol_newton * fe / re));
 }
 
 template <typename T, int ND> hipError_t spmv_only_impl(lgdm_ctx* c, const double* x) {
-  // the operator application of an IDR(4) step (SpMV with its four shadow
+  // the operator application of an IDR(8) step (SpMV with its eight shadow
   // dot products and |y|^2), the launch that dominates a default solve
-  using I = Idr<T, ND, 4>;
+  using I = Idr<T, ND, 8>;
   I S;
   S.bind(c, c->stream, c->kscal, c->kpart);
-  set_scalars_kernel<<<1, 64, 0, c->stream>>>(S.sc, 0.0, 0.0, c->mat.E / c->mat.h, BREAK_REL);
-  spmv_kernel<T, ND, I::G, 3, 4><<<S.spmv_grid(), BS, 0, c->stream>>>(
+  set_scalars_kernel<<<1, 64, 0, c->stream>>>(S.sc, 0.0, 0.0, c->mat.E / c->mat.h, BREAK_REL, 0);
+  spmv_kernel<T, ND, I::G, 3, 8><<<S.spmv_grid(), BS, 0, c->stream>>>(
       S.nn, c->row_ptr, c->nbr_ptr, c->nbr, S.vals, x, S.t, nullptr, S.sc, c->kpart);
   return hipGetLastError();
 }

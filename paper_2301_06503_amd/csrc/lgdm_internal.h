@@ -167,6 +167,7 @@ struct lgdm_ctx {
   unsigned int* kcount = nullptr;  // last-block counters
   double* delta = nullptr;
   bool last_solve_improved = true;  // the last linear solve returned a better-than-zero correction
+  int nw_iter = 0;                  // Newton corrections of the current increment
 
   hipEvent_t ev[8] = {};
   bool events_ready = false;

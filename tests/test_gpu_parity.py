@@ -202,7 +202,7 @@ def test_softening_branch_newton(precision):
     """A notched plate driven into the softening branch (request 3 of the
     seeded serving stream, 42 x 21 Q4, five increments to max D = 0.85):
     the Newton systems of the last increment are indefinite enough that
-    BiCGSTAB's single shadow vector breaks down repeatedly; with IDR(4) every
+    BiCGSTAB's single shadow vector breaks down repeatedly; with IDR(s) every
     solve converges and the damage matches the oracle's (direct solves)."""
     from paper_2301_06503_amd import binding
     prob = W.serving_stream(n_requests=6, rate_per_s=50.0, seed=1, nx_min=40, nx_max=80,

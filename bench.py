@@ -136,7 +136,8 @@ def run_precision(prob, precision, args, binding):
                                max_krylov=args.max_krylov, check_every=32,
                                krylov_method=binding.KRYLOV_BICGSTAB if args.krylov == "bicgstab"
                                else binding.KRYLOV_IDRS, idr_s=args.idr_s,
-                               forcing=binding.FORCING_FIXED if args.fixed_forcing else binding.FORCING_ADAPTIVE)
+                               forcing=binding.FORCING_FIXED if args.fixed_forcing else binding.FORCING_ADAPTIVE,
+                               precond=binding.PRECOND_AMG if args.precond == "amg" else binding.PRECOND_BLOCK_JACOBI)
     runner = PathRunner(ctx, prob, opts, binding)
     warm = new_acc()
     for i in range(args.warmup):
@@ -177,7 +178,8 @@ def run_precision(prob, precision, args, binding):
         "footprint_gb": ctx.footprint() / 1e9,
         "setup_ms": setup_s * 1e3,   # mesh upload, CSR pattern build (once per mesh), material, Dirichlet set
         "solver": {"krylov": args.krylov, "idr_s": args.idr_s if args.krylov == "idr" else None,
-                   "forcing": "fixed" if args.fixed_forcing else "adaptive", "tol_krylov": args.tol_krylov},
+                   "forcing": "fixed" if args.fixed_forcing else "adaptive", "tol_krylov": args.tol_krylov,
+                   "precond": args.precond},
     }
     ctx.close()
     del ctx
@@ -283,6 +285,8 @@ def main():
                          "ones solve only as far as the Newton test needs)")
     ap.add_argument("--krylov", default="idr", choices=["idr", "bicgstab"])
     ap.add_argument("--idr-s", type=int, default=8)
+    ap.add_argument("--precond", default="bj", choices=["bj", "amg"],
+                    help="block-Jacobi or aggregation multigrid (IDR only)")
     ap.add_argument("--fixed-forcing", action="store_true",
                     help="solve every Newton correction to --tol-krylov (default: adaptive forcing)")
     ap.add_argument("--max-krylov", type=int, default=20000)

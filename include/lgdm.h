@@ -101,6 +101,24 @@ typedef struct lgdm_material {
  *                        does. */
 enum { LGDM_KRYLOV_DEFAULT = 0, LGDM_KRYLOV_BICGSTAB = 1, LGDM_KRYLOV_IDRS = 2 };
 
+/* Right preconditioner of the linear solves of a single context; 0 selects
+ * LGDM_PRECOND_BLOCK_JACOBI.  Batch solves always use block-Jacobi.
+ *  LGDM_PRECOND_BLOCK_JACOBI  inverse of the (dim+1)x(dim+1) diagonal node
+ *                             blocks of the scaled tangent.
+ *  LGDM_PRECOND_AMG           one V(1,1)-cycle of aggregation multigrid
+ *                             (3D meshes with IDR(s) only, else
+ *                             LGDM_ERR_INVALID_ARG): node aggregates of the
+ *                             node graph (built once per mesh), on each
+ *                             aggregate the rigid-body motions and a constant
+ *                             micro-equivalent strain as the coarse basis (7
+ *                             unknowns per coarse node), Galerkin coarse
+ *                             operators P^T A P rebuilt for every tangent,
+ *                             damped block-Jacobi smoothing (weight 0.7) and a
+ *                             dense inverse on the coarsest level.  Block-Jacobi
+ *                             iteration counts grow with the mesh size; these
+ *                             stay nearly constant. */
+enum { LGDM_PRECOND_DEFAULT = 0, LGDM_PRECOND_BLOCK_JACOBI = 1, LGDM_PRECOND_AMG = 2 };
+
 /* Newton / Krylov options.  Zero-initialised fields take the defaults shown. */
 typedef struct lgdm_solver_opts {
   int32_t max_newton;      /* 30     Newton iterations per increment                */
@@ -113,7 +131,7 @@ typedef struct lgdm_solver_opts {
   int32_t idr_s;           /* 8      IDR shadow-space dimension: 1, 2, 4 or 8 (other
                                      values round up to the next of these, max 8) */
   int32_t forcing;         /* LGDM_FORCING_ADAPTIVE                                 */
-  int32_t reserved;
+  int32_t precond;         /* LGDM_PRECOND_BLOCK_JACOBI                             */
 } lgdm_solver_opts;
 
 /* Tolerance of the linear solves inside Newton (lgdm_newton_iteration,
@@ -154,6 +172,9 @@ typedef struct lgdm_increment_report {
   double krylov_rel_u;     /* last solve: ||(S(b - A x))_u|| / ||(S b)_u||          */
   double krylov_rel_e;     /* last solve: the same for the ebar rows                */
   int64_t krylov_spmv;     /* operator applications (SpMV) in the linear solves     */
+  int32_t precond_fallbacks; /* multigrid solves without progress, repeated with
+                                block-Jacobi                                        */
+  int32_t reserved;
 } lgdm_increment_report;
 
 /* View of the assembled tangent.  Device pointers owned by the context. */

@@ -28,6 +28,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "OOM", 3: "DEVICE", 4: "NOT_CONVER
 SLOT_FREE, SLOT_RUNNING, SLOT_FINISHED, SLOT_FAILED = 0, 1, 2, 3
 KRYLOV_DEFAULT, KRYLOV_BICGSTAB, KRYLOV_IDRS = 0, 1, 2
 FORCING_ADAPTIVE, FORCING_FIXED = 0, 1
+PRECOND_DEFAULT, PRECOND_BLOCK_JACOBI, PRECOND_AMG = 0, 1, 2
 
 # every entry point the header declares
 EXPORTS = [
@@ -55,7 +56,7 @@ class SolverOpts(ctypes.Structure):
                 ("tol_newton", ctypes.c_double), ("tol_krylov", ctypes.c_double),
                 ("check_every", ctypes.c_int32), ("max_restarts", ctypes.c_int32),
                 ("krylov_method", ctypes.c_int32), ("idr_s", ctypes.c_int32),
-                ("forcing", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("forcing", ctypes.c_int32), ("precond", ctypes.c_int32)]
 
 
 class IncrementReport(ctypes.Structure):
@@ -67,7 +68,7 @@ class IncrementReport(ctypes.Structure):
         ("n_assemblies", ctypes.c_int32), ("restarts", ctypes.c_int32),
         ("krylov_status", ctypes.c_int32), ("inexact_solves", ctypes.c_int32),
         ("krylov_rel_u", ctypes.c_double), ("krylov_rel_e", ctypes.c_double),
-        ("krylov_spmv", ctypes.c_int64)]
+        ("krylov_spmv", ctypes.c_int64), ("precond_fallbacks", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

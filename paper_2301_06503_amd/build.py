@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblgdm.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["element.hip", "pattern.hip", "krylov.hip", "capi.cpp", "batch.cpp"]
+SOURCES = ["element.hip", "pattern.hip", "krylov.hip", "amg.hip", "capi.cpp", "batch.cpp"]
 ARCH = os.environ.get("LGDM_OFFLOAD_ARCH", "gfx950")
 
 
@@ -43,7 +43,7 @@ def compile_one(src):
 
 def build(verbose=True):
     os.makedirs(OBJ, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(5, len(SOURCES))) as ex:
+    with ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
         objs = list(ex.map(compile_one, SOURCES))
     tmp = OUT + ".tmp"
     cmd = [_hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs

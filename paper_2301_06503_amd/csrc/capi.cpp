@@ -62,6 +62,7 @@ lgdm_status hip_fail(lgdm_ctx* c, hipError_t e, const char* where) {
   } while (0)
 
 void free_mesh(lgdm_ctx* c) {
+  amg_release(c);
   // keep pinned host buffers; release every device allocation
   std::vector<std::pair<void*, size_t>> all = c->allocs;
   for (auto& a : all) dfree(c, a.first);
@@ -124,8 +125,32 @@ bool residual_converged(const lgdm_ctx* c, double tol) {
 lgdm_status linear_solve(lgdm_ctx* c, const double* b_dev, double* x_dev, const lgdm_solver_opts& o,
                          double tol_u, double tol_e, lgdm_increment_report* rep) {
   HIPCHECK(c, krylov_setup(c), "block-Jacobi setup");
+  if (o.precond == LGDM_PRECOND_AMG) {
+    if (o.krylov_method != LGDM_KRYLOV_IDRS)
+      return fail(c, LGDM_ERR_INVALID_ARG, "the multigrid preconditioner needs IDR(s)");
+    std::string msg;
+    const hipError_t e = amg_setup(c, msg);
+    if (e != hipSuccess)
+      return msg.empty() ? hip_fail(c, e, "multigrid setup")
+                         : fail(c, e == hipErrorInvalidValue ? LGDM_ERR_INVALID_ARG : LGDM_ERR_DEVICE,
+                                "multigrid setup: " + msg);
+  }
   KrylovResult kr{};
   HIPCHECK(c, krylov_solve(c, b_dev, x_dev, o, tol_u, tol_e, kr), "Krylov solve");
+  if (o.precond == LGDM_PRECOND_AMG && kr.status != LGDM_OK && !kr.improved) {
+    // the smoother can amplify where block-Jacobi sees a far-spread spectrum
+    // (strongly indefinite tangents): a multigrid solve that made no
+    // progress is repeated with block-Jacobi alone
+    lgdm_solver_opts bj = o;
+    bj.precond = LGDM_PRECOND_BLOCK_JACOBI;
+    const int64_t it0 = kr.iters, sp0 = kr.spmv;
+    const int rs0 = kr.restarts;
+    HIPCHECK(c, krylov_solve(c, b_dev, x_dev, bj, tol_u, tol_e, kr), "Krylov solve");
+    kr.iters += it0;
+    kr.spmv += sp0;
+    kr.restarts += rs0;
+    if (rep) rep->precond_fallbacks += 1;
+  }
   c->last_solve_improved = kr.status == LGDM_OK || kr.improved;
   if (rep) {
     rep->krylov_iters += kr.iters;

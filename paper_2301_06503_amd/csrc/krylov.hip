@@ -42,6 +42,7 @@ enum {
   K_RHO = 0, K_RHO_OLD, K_ALPHA, K_OMEGA, K_BETA, K_RU, K_RE, K_BU, K_BE, K_DONE, K_STATUS,
   K_ITER, K_TOL2, K_SE, K_RH2, K_B2, K_BRK, K_TOL2E, K_SEED, K_NSLOTS = 24
 };
+static_assert(K_DONE == KSLOT_DONE, "done slot shared with the multigrid kernels");
 // status values
 enum { KS_RUN = 0, KS_CONV = 1, KS_BREAK = 2, KS_NAN = 3 };
 // a recurrence scalar below this fraction of the norms it is made of is a
@@ -788,7 +789,7 @@ __device__ __forceinline__ void idr_g_scalar_body(int64_t nblk, const double* __
 
 // G_K -= sum_{i<K} a_i G_i, U_K likewise; r -= beta G_K; x += beta U_K;
 // the last step (K = s - 1) also forms v = M^-1 r for the minimal-residual
-// step.  Partials |r_u|^2, |r_e|^2.
+// step when M is block-Jacobi (minv not null).  Partials |r_u|^2, |r_e|^2.
 template <typename T, int ND, int S, int K>
 __device__ __forceinline__ void idr_upd_body(int64_t blk, int64_t nblk, int64_t n_nodes,
                                              const T* __restrict__ minv, double* __restrict__ Gv,
@@ -834,7 +835,7 @@ __device__ __forceinline__ void idr_upd_body(int64_t blk, int64_t nblk, int64_t 
     }
     rn.store(r + o);
     xn.store(x + o);
-    if (LAST) {
+    if (LAST && minv != nullptr) {
       Quad<T, ND> m[ND];
 #pragma unroll
       for (int i = 0; i < ND; ++i) m[i].load(minv + a * ND * ND + i * ND);
@@ -850,6 +851,45 @@ __device__ __forceinline__ void idr_upd_body(int64_t blk, int64_t nblk, int64_t 
     }
   }
   write_partials<2>(d, part, blk, sm);
+}
+
+// Step K with a preconditioner applied by separate launches (multigrid):
+// v = r - sum_j c_j G_{K+j} before it, U_K = sum_j c_j U_{K+j} + omega z
+// after it (z = M^-1 v); the first cycle after a (re)start has no G, U terms.
+template <int S, int K>
+__global__ void __launch_bounds__(BS) idr_formv_kernel(int64_t n, const double* __restrict__ r,
+                                                       const double* __restrict__ Gv, double* __restrict__ v,
+                                                       const double* __restrict__ sc) {
+  if (sc[K_DONE] != 0.0) return;
+  const bool fresh = sc[I_FRESH] != 0.0;
+  double cc[S - K];
+#pragma unroll
+  for (int j = 0; j < S - K; ++j) cc[j] = sc[I_C + j];
+  for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+    double x = r[i];
+    if (!fresh)
+#pragma unroll
+      for (int j = 0; j < S - K; ++j) x -= cc[j] * Gv[(int64_t)(K + j) * n + i];
+    v[i] = x;
+  }
+}
+
+template <int S, int K>
+__global__ void __launch_bounds__(BS) idr_formu_kernel(int64_t n, const double* __restrict__ z,
+                                                       double* __restrict__ Uv, const double* __restrict__ sc) {
+  if (sc[K_DONE] != 0.0) return;
+  const bool fresh = sc[I_FRESH] != 0.0;
+  const double om = sc[I_OM];
+  double cc[S - K];
+#pragma unroll
+  for (int j = 0; j < S - K; ++j) cc[j] = sc[I_C + j];
+  for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+    double u = om * z[i];
+    if (!fresh)
+#pragma unroll
+      for (int j = 0; j < S - K; ++j) u += cc[j] * Uv[(int64_t)(K + j) * n + i];
+    Uv[(int64_t)K * n + i] = u;
+  }
 }
 
 __device__ __forceinline__ void idr_r_scalar_body(int64_t nblk, const double* __restrict__ part,
@@ -1107,6 +1147,7 @@ struct Solver {
   // (two passes, four nodes per wave) beat 32 by a few per cent
   static constexpr bool F32 = std::is_same<T, float>::value;
   static constexpr int G = ND == 4 ? 16 : (ND == 3 ? 16 : 4);
+  bool mg = false;  // BiCGSTAB is block-Jacobi preconditioned only
   lgdm_ctx* c;
   hipStream_t st;
   const T* vals;
@@ -1195,6 +1236,7 @@ struct Idr {
   double* kp = nullptr;
   double *r = nullptr, *v = nullptr, *t = nullptr, *Gv = nullptr, *Uv = nullptr;
   int64_t n = 0, nn = 0;
+  bool mg = false;  // multigrid preconditioner (the context's hierarchy) instead of block-Jacobi
 
   void bind(lgdm_ctx* ctx, hipStream_t stream, double* scal, double* part) {
     c = ctx;
@@ -1226,15 +1268,26 @@ struct Idr {
   // the s steps of a cycle, each with its compile-time index K
   template <int K> void steps(double* x, int64_t gs, double pnorm2) {
     if constexpr (K < S) {
-      auto kd = idr_dir_kernel<T, ND, S, K>;
-      kd<<<grid_of(kd, nn), BS, 0, st>>>(nn, minv, r, Gv, Uv, n, sc);
+      if (mg) {
+        // v = r - sum c G (in v); z = M^-1 v (in t); U_K from z.  v and t
+        // are free until the minimal-residual step at the end of the cycle.
+        auto kv = idr_formv_kernel<S, K>;
+        kv<<<grid_of(kv, n), BS, 0, st>>>(n, r, Gv, v, sc);
+        (void)amg_apply(c, v, t, sc, st);
+        auto kf = idr_formu_kernel<S, K>;
+        kf<<<grid_of(kf, n), BS, 0, st>>>(n, t, Uv, sc);
+      } else {
+        auto kd = idr_dir_kernel<T, ND, S, K>;
+        kd<<<grid_of(kd, nn), BS, 0, st>>>(nn, minv, r, Gv, Uv, n, sc);
+      }
       spmv_kernel<T, ND, G, 3, S><<<gs, BS, 0, st>>>(nn, c->row_ptr, c->nbr_ptr, c->nbr, vals,
                                                      Uv + (int64_t)K * n, Gv + (int64_t)K * n, nullptr, sc, kp);
       idr_g_scalar<S><<<1, BS, 0, st>>>((int)gs, kp, sc, K, pnorm2);
       auto ku = idr_upd_kernel<T, ND, S, K>;
       const int64_t gu = grid_of(ku, nn);
-      ku<<<gu, BS, 0, st>>>(nn, minv, Gv, Uv, r, x, v, n, sc, kp);
+      ku<<<gu, BS, 0, st>>>(nn, mg ? nullptr : minv, Gv, Uv, r, x, v, n, sc, kp);
       idr_r_scalar<<<1, BS, 0, st>>>((int)gu, kp, sc);
+      if (K == S - 1 && mg) (void)amg_apply(c, r, v, sc, st);  // v = M^-1 r
       steps<K + 1>(x, gs, pnorm2);
     }
   }
@@ -1382,6 +1435,7 @@ struct KrylovRunImpl final : KrylovRun {
                 double te)
       : c(ctx), b(b_), xout(x_), o(o_) {
     S.bind(c, c->stream, c->kscal, c->kpart);
+    S.mg = o.precond == LGDM_PRECOND_AMG && c->amg != nullptr;
     xbest = c->kv + (int64_t)(KV_VECS - 1) * c->ndof;
     rc.setup(tu, te, Method::F32, Method::SPMV_PER_ITER);
     se = c->mat.E / c->mat.h;
@@ -1680,6 +1734,7 @@ lgdm_solver_opts fill_opts(const lgdm_solver_opts* o) {
   if (r.max_restarts <= 0) r.max_restarts = 8;
   if (r.krylov_method != LGDM_KRYLOV_BICGSTAB) r.krylov_method = LGDM_KRYLOV_IDRS;
   if (r.forcing != LGDM_FORCING_FIXED) r.forcing = LGDM_FORCING_ADAPTIVE;
+  if (r.precond != LGDM_PRECOND_AMG) r.precond = LGDM_PRECOND_BLOCK_JACOBI;
   r.idr_s = r.idr_s <= 0 ? 8 : (r.idr_s <= 1 ? 1 : (r.idr_s <= 2 ? 2 : (r.idr_s <= 4 ? 4 : 8)));
   return r;
 }

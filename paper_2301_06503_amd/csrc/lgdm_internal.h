@@ -94,6 +94,9 @@ constexpr int KV_VECS = 3 + 2 * IDR_SMAX + 1;
 constexpr int KSCAL_DOUBLES = 128;     // device scalar slots of a solve
 constexpr int KPART_PER_BLOCK = 16;    // partial sums per workgroup (at most 4 + IDR_SMAX)
 constexpr int KPART_BLOCKS = 2048;     // workgroups of a Krylov vector kernel, at most
+constexpr int KSLOT_DONE = 9;          // device scalar slot of a solve's done flag
+
+struct Amg;  // aggregation-multigrid hierarchy of a context (amg.hip)
 
 }  // namespace lgdm
 
@@ -166,6 +169,7 @@ struct lgdm_ctx {
   double* kscal_host = nullptr;    // pinned copy
   unsigned int* kcount = nullptr;  // last-block counters
   double* delta = nullptr;
+  lgdm::Amg* amg = nullptr;         // multigrid hierarchy (built at the first multigrid solve)
   bool last_solve_improved = true;  // the last linear solve returned a better-than-zero correction
   int nw_iter = 0;                  // Newton corrections of the current increment
 
@@ -262,6 +266,22 @@ hipError_t krylov_solve(lgdm_ctx* c, const double* b, double* xout, const lgdm_s
                         double tol_u, double tol_e, KrylovResult& res);
 hipError_t launch_spmv_only(lgdm_ctx* c, const double* x, double* scratch);  // y = S K x
 hipError_t launch_axpy(lgdm_ctx* c, double* y, const double* x, double a, int64_t n);
+
+// Aggregation multigrid (amg.hip).  amg_setup builds the hierarchy's
+// structure on the first call for a mesh (host aggregation of the node graph)
+// and, on every call, the coarse operators of the current tangent (after
+// krylov_setup).  amg_apply enqueues out = one V-cycle applied to in; it does
+// nothing once sc[KSLOT_DONE] is set (sc may be null).  amg_release frees the
+// host side (device memory belongs to the context's allocations).
+hipError_t amg_setup(lgdm_ctx* c, std::string& msg);
+hipError_t amg_apply(lgdm_ctx* c, const double* in, double* out, const double* sc, hipStream_t st);
+void amg_release(lgdm_ctx* c);
+struct AmgInfo {
+  int levels;
+  int64_t nodes[16];
+  int64_t pairs[16];
+};
+void amg_info(const lgdm_ctx* c, AmgInfo& info);
 hipError_t launch_field_norms(lgdm_ctx* c, const double* v, double* out_dev);  // |v_u|^2, |v_e|^2
 
 }  // namespace lgdm

@@ -54,6 +54,8 @@ def tiny_problems():
                                  n_increments=30, material=m_pe),
         "beam3d_10x4x3": W.beam3d(nx=10, ny=4, nz=3, lx=40.0, ly=16.0, lz=12.0, u_load=-0.02,
                                   n_increments=20),
+        "beam3d_24x8x6": W.beam3d(nx=24, ny=8, nz=6, lx=96.0, ly=32.0, lz=24.0, u_load=-0.04,
+                                  n_increments=20),
     }
     d = W.beam3d(nx=6, ny=4, nz=3, lx=24.0, ly=16.0, lz=12.0, u_load=-0.02, n_increments=20)
     d.coords = W.perturbed_coords(d, seed=3, amp=0.2)

@@ -95,23 +95,29 @@ def test_mixed_vs_fp64_gpu(name, n_inc):
     assert derr <= 1e-5
 
 
-@pytest.mark.parametrize("precision", [0, MIXED])
-def test_c3p_path_vs_stored_oracle(precision):
+@pytest.mark.parametrize("precision,precond", [(0, 0), (MIXED, 0), (0, 2), (MIXED, 2)])
+def test_c3p_path_vs_stored_oracle(precision, precond):
     """The 64 x 16 x 8 beam (parity subsample of the 256 x 64 x 32 workload),
     first four increments into damage, against the FP64 oracle's path stored
-    by tests/golden/make_golden.py.  Damage error stated; bounded by 1e-8
-    (FP64) and 1e-7 (mixed precision)."""
+    by tests/golden/make_golden.py, with block-Jacobi (0) and multigrid (2)
+    preconditioning.  Damage error stated; bounded by 1e-8 (FP64) and 1e-7
+    (mixed precision)."""
     import os
     from paper_2301_06503_amd import binding
     g = np.load(os.path.join(os.path.dirname(__file__), "golden", "c3p_oracle_path.npz"))
     prob = W.config("c3p")
-    print("case: c3p precision", precision, flush=True)
+    print("case: c3p precision", precision, "precond", precond, flush=True)
     ctx = context(prob, precision)
-    opts = binding.solver_opts(max_newton=40, tol_newton=1e-10, tol_krylov=1e-3, max_krylov=20000)
+    opts = binding.solver_opts(max_newton=40, tol_newton=1e-10, tol_krylov=1e-3, max_krylov=20000,
+                               precond=precond)
     errs = []
     for n in range(1, len(g["D"]) + 1):
         rep = ctx.solve_increment(n / prob.n_increments, opts)
         errs.append(float(np.abs(ctx.query(2) - g["D"][n - 1]).max()))
+        print("increment", n, "newton", rep["newton_iters"], "krylov iters", rep["krylov_iters"],
+              "fallbacks", rep["precond_fallbacks"], "res_u/ref_u %.1e res_e/ref_e %.1e" %
+              (rep["res_u"] / rep["ref_u"], rep["res_e"] / rep["ref_e"]),
+              "reaction %.9g (oracle %.9g)" % (rep["reaction"], g["reaction"][n - 1]), flush=True)
         assert rep["reaction"] == pytest.approx(float(g["reaction"][n - 1]), rel=1e-6)
     print("damage error per increment vs stored oracle:", ["%.2e" % e for e in errs],
           "max D %.3f" % g["D"][-1].max())

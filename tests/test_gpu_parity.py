@@ -102,29 +102,34 @@ def test_assembly_bitwise_repeatable(name):
     ctx.close()
 
 
-KRYLOV_CASES = [(n, 1, 0) for n in ("bar1d_37", "sen2d_13x7_ps", "beam3d_10x4x3", "c1")] + \
-    [(n, 2, 4) for n in ("bar1d_37", "sen2d_13x7_ps", "beam3d_10x4x3", "c1")] + \
-    [("beam3d_10x4x3", 2, s) for s in (1, 2, 8)]
+KRYLOV_CASES = [(n, 1, 0, 0) for n in ("bar1d_37", "sen2d_13x7_ps", "beam3d_10x4x3", "c1")] + \
+    [(n, 2, 4, 0) for n in ("bar1d_37", "sen2d_13x7_ps", "beam3d_10x4x3", "c1")] + \
+    [("beam3d_10x4x3", 2, s, 0) for s in (1, 2, 8)] + \
+    [(n, 2, 8, 2) for n in ("beam3d_10x4x3", "beam3d_6x4x3_distorted", "beam3d_24x8x6")]
 
 
-@pytest.mark.parametrize("name,method,s", KRYLOV_CASES)
-def test_krylov_matches_direct_solve(name, method, s):
-    """BiCGSTAB (method 1) and IDR(s) (method 2) solve the Newton system of a
+@pytest.mark.parametrize("name,method,s,precond", KRYLOV_CASES)
+def test_krylov_matches_direct_solve(name, method, s, precond):
+    """BiCGSTAB (method 1) and IDR(s) (method 2), block-Jacobi (precond 0) or
+    multigrid (precond 2) preconditioned, solve the Newton system of a
     damaged state to a per-field true residual of 1e-10 and agree with a
     direct sparse LU of the oracle's tangent."""
-    _print_case("%s method %d s %d" % (name, method, s))
+    _print_case("%s method %d s %d precond %d" % (name, method, s, precond))
     import scipy.sparse.linalg as spla
     from paper_2301_06503_amd import binding
     prob = TINY[name] if name in TINY else W.config(name)
-    # a mildly perturbed state; the tiny meshes are partly damaged, the full
-    # 2D plate is kept below the threshold (an elastic Newton system)
-    spread, escale = (0.5, 0.05) if name == "c1" else (1.5, 1.0)
+    # a mildly perturbed state; the tiny meshes are partly damaged, the
+    # larger ones are kept below the threshold (an elastic Newton system: a
+    # random damage field there is so ill-conditioned that the forward error
+    # of a 1e-10 residual exceeds the bound below)
+    mild = name in ("c1", "beam3d_24x8x6")
+    spread, escale = (0.5, 0.05) if mild else (1.5, 1.0)
     x, kn = W.injected_state(prob, seed=2, noise=0.02, kappa_spread=spread, ebar_scale=escale)
     ctx = context(prob)
     ctx.set_state(x, kn)
     _, R = ctx.assemble()
     delta, rep = ctx.solve_linear(R, binding.solver_opts(tol_krylov=1e-13, max_krylov=50000,
-                                                         krylov_method=method, idr_s=s))
+                                                         krylov_method=method, idr_s=s, precond=precond))
     st = Oracle(prob).eval_state(x, kn)
     ref = spla.splu(st["K"].tocsc()).solve(st["R"])
     d = delta.cpu().numpy()
@@ -138,6 +143,14 @@ def test_krylov_matches_direct_solve(name, method, s):
           "true rel res", ru, re)
     assert ru <= 1e-10 and re <= 1e-10, (ru, re)
     assert max(ferr.values()) <= 1e-6, ferr
+    # Dirichlet rows are identity with a zero right-hand side: the correction
+    # there is exactly zero (the preconditioners keep those entries zero)
+    assert np.all(d[Oracle(prob).bc_dofs] == 0.0)
+    if precond == 2 and mild:
+        # the CPU model of the same cycle needs 58 IDR(8) steps on the
+        # 24 x 8 x 6 beam (block-Jacobi: 341); the count stays nearly flat
+        # under refinement
+        assert rep["krylov_iters"] <= 150, rep["krylov_iters"]
     ctx.close()
 
 

@@ -137,13 +137,18 @@ def run_precision(prob, precision, args, binding):
                                krylov_method=binding.KRYLOV_BICGSTAB if args.krylov == "bicgstab"
                                else binding.KRYLOV_IDRS, idr_s=args.idr_s,
                                forcing=binding.FORCING_FIXED if args.fixed_forcing else binding.FORCING_ADAPTIVE,
-                               precond=binding.PRECOND_AMG if args.precond == "amg" else binding.PRECOND_BLOCK_JACOBI)
+                               precond={"default": binding.PRECOND_DEFAULT, "bj": binding.PRECOND_BLOCK_JACOBI,
+                                        "amg": binding.PRECOND_AMG}[args.precond])
     runner = PathRunner(ctx, prob, opts, binding)
     warm = new_acc()
     for i in range(args.warmup):
         runner.step(warm)
         log("warmup step %d done (increment %d, spmv %d)" % (i + 1, runner.inc, warm["spmv"]))
     acc = new_acc()
+    # live timing of the dominant solver kernel over the timed steps: the
+    # IDR SpMV (the only pass over the matrix per Krylov step, with either
+    # preconditioner)
+    ctx.probe_start(binding.PROBE_IDR_SPMV)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -152,12 +157,17 @@ def run_precision(prob, precision, args, binding):
             % (i + 1, runner.inc, acc["newton"], acc["spmv"]))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    probe_ms, probe_n = ctx.probe_stop()
+    amg_levels = ctx.amg_levels()
     view, _ = ctx.assemble(-1.0, want_R=False)
     kt = ctx.kernel_times(args.kernel_reps)
     nnz = view.nnz
     npairs = nnz // (prob.ndpn ** 2)
     s_val = 4 if precision == binding.MIXED else 8
     asm_b, spmv_b = algorithmic_bytes(prob, nnz, npairs, s_val)
+    probe_b = spmv_b
+    probe_name = "spmv_kernel<%s, %d, 16, 3, 8> (IDR SpMV)" % (
+        "float" if precision == binding.MIXED else "double", prob.ndpn)
     ng = ctx.ngauss
     res = {
         "gp_per_s": ng * acc["n_asm"] / wall,
@@ -175,6 +185,11 @@ def run_precision(prob, precision, args, binding):
         "assembly_bytes": asm_b, "spmv_bytes": spmv_b,
         "assembly_gbs": asm_b / ((kt[0] + kt[1]) * 1e-3) / 1e9,
         "spmv_gbs": spmv_b / (kt[2] * 1e-3) / 1e9,
+        "probe": {"kernel": probe_name, "key": "spmv", "avg_ms": probe_ms,
+                  "launches_timed": probe_n, "algorithmic_bytes": probe_b,
+                  "gbs": probe_b / (probe_ms * 1e-3) / 1e9 if probe_ms > 0 else None,
+                  "note": "HIP events around each launch on the context's stream during the timed steps"},
+        "multigrid_levels": amg_levels,
         "footprint_gb": ctx.footprint() / 1e9,
         "setup_ms": setup_s * 1e3,   # mesh upload, CSR pattern build (once per mesh), material, Dirichlet set
         "solver": {"krylov": args.krylov, "idr_s": args.idr_s if args.krylov == "idr" else None,
@@ -285,8 +300,8 @@ def main():
                          "ones solve only as far as the Newton test needs)")
     ap.add_argument("--krylov", default="idr", choices=["idr", "bicgstab"])
     ap.add_argument("--idr-s", type=int, default=8)
-    ap.add_argument("--precond", default="bj", choices=["bj", "amg"],
-                    help="block-Jacobi or aggregation multigrid (IDR only)")
+    ap.add_argument("--precond", default="default", choices=["default", "bj", "amg"],
+                    help="block-Jacobi or aggregation multigrid (IDR only); the default is multigrid on 3D meshes")
     ap.add_argument("--fixed-forcing", action="store_true",
                     help="solve every Newton correction to --tol-krylov (default: adaptive forcing)")
     ap.add_argument("--max-krylov", type=int, default=20000)
@@ -308,21 +323,22 @@ def main():
     fp64_res = None
     if prec == binding.MIXED and not args.no_fp64_compare:
         fp64_res = run_precision(prob, binding.FP64, args, binding)
-    # dominant kernel of a step: SpMV (every operator application) vs assembly
+    # dominant kernel of a step: the probed solver kernel (one launch per
+    # Krylov step) vs the assembly kernels (one launch each per Newton step)
     kt = main_res["kernel_ms"]
-    spmv_share = main_res["spmv_launches"] * kt["spmv"]
+    pr = main_res["probe"]
+    solver_share = main_res["krylov_iters"] * pr["avg_ms"]
     asm_share = main_res["assemblies"] * (kt["gauss_point"] + kt["node_assembly"])
-    if spmv_share >= asm_share:
-        achieved = main_res["spmv_gbs"]
-        kern = "spmv"
+    if solver_share >= asm_share and pr["gbs"]:
+        achieved, kern, key_kern, nbytes = pr["gbs"], pr["kernel"], pr["key"], pr["algorithmic_bytes"]
     else:
-        achieved = main_res["assembly_gbs"]
-        kern = "assembly"
-    key = "%s_%s_%s" % (args.config, args.precision, kern)
+        achieved, kern, key_kern, nbytes = (main_res["assembly_gbs"], "gauss_point+node_assembly", "assembly",
+                                            main_res["assembly_bytes"])
+    key = "%s_%s_%s" % (args.config, args.precision, key_kern)
     roofline = {"bound": "hbm", "kernel": kern, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": committed_traffic(key, None),
-                "algorithmic_bytes": main_res["spmv_bytes"] if kern == "spmv" else main_res["assembly_bytes"]}
+                "traffic": committed_traffic(key, None), "algorithmic_bytes": nbytes,
+                "launch_ms": pr["avg_ms"] if key_kern != "assembly" else None}
     roof_asm = {"bound": "hbm", "kernel": "gauss_point+node_assembly",
                 "achieved": round(main_res["assembly_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(main_res["assembly_gbs"] / HBM_PEAK_GBS, 4)}

@@ -101,22 +101,26 @@ typedef struct lgdm_material {
  *                        does. */
 enum { LGDM_KRYLOV_DEFAULT = 0, LGDM_KRYLOV_BICGSTAB = 1, LGDM_KRYLOV_IDRS = 2 };
 
-/* Right preconditioner of the linear solves of a single context; 0 selects
- * LGDM_PRECOND_BLOCK_JACOBI.  Batch solves always use block-Jacobi.
+/* Right preconditioner of the linear solves of a single context.  0
+ * (LGDM_PRECOND_DEFAULT) selects LGDM_PRECOND_AMG for IDR(s) solves on 3D
+ * meshes that have a coarse level (more than 13 nodes), block-Jacobi
+ * otherwise.  Batch solves always use block-Jacobi.
  *  LGDM_PRECOND_BLOCK_JACOBI  inverse of the (dim+1)x(dim+1) diagonal node
  *                             blocks of the scaled tangent.
- *  LGDM_PRECOND_AMG           one V(1,1)-cycle of aggregation multigrid
- *                             (3D meshes with IDR(s) only, else
- *                             LGDM_ERR_INVALID_ARG): node aggregates of the
- *                             node graph (built once per mesh), on each
- *                             aggregate the rigid-body motions and a constant
- *                             micro-equivalent strain as the coarse basis (7
- *                             unknowns per coarse node), Galerkin coarse
- *                             operators P^T A P rebuilt for every tangent,
- *                             damped block-Jacobi smoothing (weight 0.7) and a
- *                             dense inverse on the coarsest level.  Block-Jacobi
- *                             iteration counts grow with the mesh size; these
- *                             stay nearly constant. */
+ *  LGDM_PRECOND_AMG           one cycle of aggregation multigrid (3D meshes
+ *                             with IDR(s) only, else LGDM_ERR_INVALID_ARG):
+ *                             node aggregates of the node graph (built once
+ *                             per mesh), on each aggregate the rigid-body
+ *                             motions and a constant micro-equivalent strain
+ *                             as the coarse basis (7 unknowns per coarse
+ *                             node), Galerkin coarse operators P^T A P rebuilt
+ *                             for every tangent.  Finest level: damped
+ *                             block-Jacobi (weight 0.7) plus the coarse
+ *                             correction, side by side; coarser levels:
+ *                             V(1,1) with the same smoother; a dense inverse
+ *                             on the coarsest level.  Block-Jacobi iteration
+ *                             counts grow with the mesh size; these stay
+ *                             nearly constant. */
 enum { LGDM_PRECOND_DEFAULT = 0, LGDM_PRECOND_BLOCK_JACOBI = 1, LGDM_PRECOND_AMG = 2 };
 
 /* Newton / Krylov options.  Zero-initialised fields take the defaults shown. */
@@ -131,7 +135,7 @@ typedef struct lgdm_solver_opts {
   int32_t idr_s;           /* 8      IDR shadow-space dimension: 1, 2, 4 or 8 (other
                                      values round up to the next of these, max 8) */
   int32_t forcing;         /* LGDM_FORCING_ADAPTIVE                                 */
-  int32_t precond;         /* LGDM_PRECOND_BLOCK_JACOBI                             */
+  int32_t precond;         /* LGDM_PRECOND_DEFAULT                                  */
 } lgdm_solver_opts;
 
 /* Tolerance of the linear solves inside Newton (lgdm_newton_iteration,
@@ -306,8 +310,39 @@ lgdm_status lgdm_debug_element_blocks(lgdm_ctx* ctx, int64_t e0, int64_t e1, dou
  * Leaves the assembled matrix and state unchanged. */
 lgdm_status lgdm_kernel_times(lgdm_ctx* ctx, int32_t reps, double* avg_ms);
 
+/* Measurement aid: live timing of one kernel inside the linear solves.
+ * lgdm_probe_start records a pair of HIP events around every launch of that
+ * kernel on the context's stream (at most 64 launches in flight are
+ * recorded; later ones are skipped until earlier pairs complete);
+ * lgdm_probe_stop waits for them and returns the average duration (ms) and
+ * the number of launches timed.  Kinds: LGDM_PROBE_IDR_SPMV, the operator
+ * application of an IDR(s) step with its shadow-vector dot products;
+ * LGDM_PROBE_MG_FINEST, the finest-level kernel of the multigrid cycle
+ * (block-Jacobi plus the prolongated coarse correction).  Starting a probe
+ * replaces a running one; lgdm_probe_stop without one is LGDM_ERR_STATE. */
+enum { LGDM_PROBE_IDR_SPMV = 0, LGDM_PROBE_MG_FINEST = 1 };
+lgdm_status lgdm_probe_start(lgdm_ctx* ctx, int32_t kind);
+lgdm_status lgdm_probe_stop(lgdm_ctx* ctx, double* avg_ms, int64_t* count);
+
 /* Device bytes held by the context (mesh, pattern, state, matrix, solver). */
 lgdm_status lgdm_footprint(lgdm_ctx* ctx, int64_t* bytes);
+
+/* The node aggregation rule of the multigrid preconditioner (host only, no
+ * device call).  Graph: CSR over n nodes in host memory, ptr [n + 1] and adj
+ * [ptr[n]] with ascending neighbour ids that include the node itself.  In
+ * node order, a node whose neighbours are all unaggregated forms a new
+ * aggregate with them; then each node left over joins the aggregate of its
+ * first (lowest-id) aggregated neighbour, or forms one alone.  Writes agg
+ * [n] (aggregate of each node, numbered in order of creation) and *n_agg.
+ * INVALID_ARG for NULL pointers or n < 0, or a neighbour id outside [0, n). */
+lgdm_status lgdm_amg_aggregate(int64_t n, const int32_t* ptr, const int32_t* adj, int32_t* agg,
+                               int64_t* n_agg);
+
+/* Node counts of the context's multigrid levels (finest first) once a
+ * multigrid solve has built them: writes up to max_levels counts to nodes
+ * and the number of levels to *n_levels (0 before the first multigrid
+ * solve). */
+lgdm_status lgdm_amg_levels(lgdm_ctx* ctx, int32_t max_levels, int64_t* nodes, int32_t* n_levels);
 
 /* ------------------------------------------------------------------------
  * Continuous batching of many simulation requests on one device.

@@ -29,6 +29,7 @@ SLOT_FREE, SLOT_RUNNING, SLOT_FINISHED, SLOT_FAILED = 0, 1, 2, 3
 KRYLOV_DEFAULT, KRYLOV_BICGSTAB, KRYLOV_IDRS = 0, 1, 2
 FORCING_ADAPTIVE, FORCING_FIXED = 0, 1
 PRECOND_DEFAULT, PRECOND_BLOCK_JACOBI, PRECOND_AMG = 0, 1, 2
+PROBE_IDR_SPMV, PROBE_MG_FINEST = 0, 1
 
 # every entry point the header declares
 EXPORTS = [
@@ -37,7 +38,8 @@ EXPORTS = [
     "lgdm_solve_linear", "lgdm_solve_increment", "lgdm_begin_increment",
     "lgdm_newton_iteration", "lgdm_commit_increment", "lgdm_abort_increment", "lgdm_get_csr",
     "lgdm_get_connectivity", "lgdm_get_sizes", "lgdm_query_state", "lgdm_set_state",
-    "lgdm_debug_element_blocks", "lgdm_kernel_times", "lgdm_footprint",
+    "lgdm_debug_element_blocks", "lgdm_kernel_times", "lgdm_footprint", "lgdm_amg_aggregate",
+    "lgdm_amg_levels", "lgdm_probe_start", "lgdm_probe_stop",
     "lgdm_batch_create", "lgdm_batch_destroy", "lgdm_batch_last_error", "lgdm_request_footprint",
     "lgdm_batch_admit", "lgdm_batch_tick", "lgdm_batch_slot_info", "lgdm_batch_query",
     "lgdm_batch_retire", "lgdm_batch_usage",
@@ -147,6 +149,10 @@ def load_library(path: str = LIB_PATH):
         "lgdm_debug_element_blocks": [P, I64, I64, P, P],
         "lgdm_footprint": [P, ctypes.POINTER(I64)],
         "lgdm_kernel_times": [P, I32, P],
+        "lgdm_amg_aggregate": [I64, P, P, P, ctypes.POINTER(I64)],
+        "lgdm_amg_levels": [P, I32, P, ctypes.POINTER(I32)],
+        "lgdm_probe_start": [P, I32],
+        "lgdm_probe_stop": [P, ctypes.POINTER(D), ctypes.POINTER(I64)],
         "lgdm_batch_create": [ctypes.POINTER(P), I32, P, I32, I32, I64],
         "lgdm_batch_destroy": [P],
         "lgdm_request_footprint": [I32, I64, I64, I32, ctypes.POINTER(I64)],
@@ -413,6 +419,24 @@ class Context:
         self._check(self.lib.lgdm_footprint(self.h, ctypes.byref(b)))
         return b.value
 
+    def probe_start(self, kind):
+        """Start live timing of one kernel kind inside the solves."""
+        self._check(self.lib.lgdm_probe_start(self.h, int(kind)))
+
+    def probe_stop(self):
+        """(average ms, launches timed) since probe_start."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        self._check(self.lib.lgdm_probe_stop(self.h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def amg_levels(self):
+        """Node counts of the multigrid levels (finest first); empty before
+        the first multigrid solve."""
+        nodes = np.zeros(16, dtype=np.int64)
+        n = ctypes.c_int32()
+        self._check(self.lib.lgdm_amg_levels(self.h, 16, nodes.ctypes.data, ctypes.byref(n)))
+        return [int(v) for v in nodes[:n.value]]
+
 
 class Batch:
     """Continuous batching of requests on one device (lgdm_batch_* of the C ABI)."""
@@ -499,3 +523,18 @@ class Batch:
         u, b, o = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
         self._check(self.lib.lgdm_batch_usage(self.h, ctypes.byref(u), ctypes.byref(b), ctypes.byref(o)))
         return u.value, b.value, o.value
+
+
+def amg_aggregate(ptr, adj):
+    """The multigrid node aggregation rule on a host CSR graph (no device):
+    returns (agg [n] int32, number of aggregates)."""
+    lib = load_library()
+    ptr = np.ascontiguousarray(ptr, dtype=np.int32)
+    adj = np.ascontiguousarray(adj, dtype=np.int32)
+    n = len(ptr) - 1
+    agg = np.empty(max(n, 0), dtype=np.int32)
+    na = ctypes.c_int64()
+    st = lib.lgdm_amg_aggregate(n, ptr.ctypes.data, adj.ctypes.data, agg.ctypes.data, ctypes.byref(na))
+    if st != LGDM_OK:
+        raise LgdmError(st, "lgdm_amg_aggregate")
+    return agg, na.value

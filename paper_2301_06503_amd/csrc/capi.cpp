@@ -42,6 +42,72 @@ void dfree(lgdm_ctx* c, void* p) {
   else (void)hipFree(p);
 }
 
+namespace {
+
+// move finished event pairs into the sum (block: wait for all)
+void probe_harvest(KernelProbe& p, bool block) {
+  size_t i = 0;
+  for (; i < p.pending.size(); ++i) {
+    auto& pr = p.pending[i];
+    if (block) {
+      if (hipEventSynchronize(pr.second) != hipSuccess) break;
+    } else if (hipEventQuery(pr.second) != hipSuccess) {
+      (void)hipGetLastError();
+      break;
+    }
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+      p.sum_ms += ms;
+      p.count += 1;
+    }
+    p.pool.push_back(pr.first);
+    p.pool.push_back(pr.second);
+  }
+  p.pending.erase(p.pending.begin(), p.pending.begin() + i);
+}
+
+void probe_release(lgdm_ctx* c) {
+  if (!c->probe) return;
+  probe_harvest(*c->probe, true);
+  for (auto& pr : c->probe->pending) {
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  for (auto e : c->probe->pool) (void)hipEventDestroy(e);
+  delete c->probe;
+  c->probe = nullptr;
+}
+
+}  // namespace
+
+void probe_before(lgdm_ctx* c, int kind, hipStream_t st) {
+  KernelProbe* p = c->probe;
+  if (!p || p->kind != kind) return;
+  probe_harvest(*p, false);
+  if (p->pool.size() < 2) return;  // all pairs in flight: this launch is not sampled
+  p->open1 = p->pool.back();
+  p->pool.pop_back();
+  p->open0 = p->pool.back();
+  p->pool.pop_back();
+  if (hipEventRecord(p->open0, st) != hipSuccess) {
+    p->pool.push_back(p->open0);
+    p->pool.push_back(p->open1);
+    p->open0 = p->open1 = nullptr;
+  }
+}
+
+void probe_after(lgdm_ctx* c, int kind, hipStream_t st) {
+  KernelProbe* p = c->probe;
+  if (!p || p->kind != kind || !p->open0) return;
+  if (hipEventRecord(p->open1, st) == hipSuccess) {
+    p->pending.emplace_back(p->open0, p->open1);
+  } else {
+    p->pool.push_back(p->open0);
+    p->pool.push_back(p->open1);
+  }
+  p->open0 = p->open1 = nullptr;
+}
+
 }  // namespace lgdm
 
 namespace {
@@ -63,6 +129,7 @@ lgdm_status hip_fail(lgdm_ctx* c, hipError_t e, const char* where) {
 
 void free_mesh(lgdm_ctx* c) {
   amg_release(c);
+  c->amg_unavailable = false;
   // keep pinned host buffers; release every device allocation
   std::vector<std::pair<void*, size_t>> all = c->allocs;
   for (auto& a : all) dfree(c, a.first);
@@ -122,18 +189,28 @@ bool residual_converged(const lgdm_ctx* c, double tol) {
   return ru <= tol * std::max(fu, tiny) && re <= tol * std::max(fe, tiny);
 }
 
-lgdm_status linear_solve(lgdm_ctx* c, const double* b_dev, double* x_dev, const lgdm_solver_opts& o,
+lgdm_status linear_solve(lgdm_ctx* c, const double* b_dev, double* x_dev, const lgdm_solver_opts& opts,
                          double tol_u, double tol_e, lgdm_increment_report* rep) {
   HIPCHECK(c, krylov_setup(c), "block-Jacobi setup");
+  lgdm_solver_opts o = opts;
+  if (o.precond == LGDM_PRECOND_DEFAULT)
+    o.precond = c->dim == 3 && o.krylov_method == LGDM_KRYLOV_IDRS && !c->amg_unavailable ? LGDM_PRECOND_AMG
+                                                                                           : LGDM_PRECOND_BLOCK_JACOBI;
   if (o.precond == LGDM_PRECOND_AMG) {
     if (o.krylov_method != LGDM_KRYLOV_IDRS)
       return fail(c, LGDM_ERR_INVALID_ARG, "the multigrid preconditioner needs IDR(s)");
     std::string msg;
     const hipError_t e = amg_setup(c, msg);
-    if (e != hipSuccess)
+    if (e == hipErrorInvalidValue && opts.precond == LGDM_PRECOND_DEFAULT) {
+      // no usable hierarchy for this mesh (too small, or coarsening
+      // stalled): the default is block-Jacobi for it from now on
+      c->amg_unavailable = true;
+      o.precond = LGDM_PRECOND_BLOCK_JACOBI;
+    } else if (e != hipSuccess) {
       return msg.empty() ? hip_fail(c, e, "multigrid setup")
                          : fail(c, e == hipErrorInvalidValue ? LGDM_ERR_INVALID_ARG : LGDM_ERR_DEVICE,
                                 "multigrid setup: " + msg);
+    }
   }
   KrylovResult kr{};
   HIPCHECK(c, krylov_solve(c, b_dev, x_dev, o, tol_u, tol_e, kr), "Krylov solve");
@@ -216,6 +293,7 @@ lgdm_status lgdm_destroy(lgdm_ctx* c) {
   if (!c) return LGDM_ERR_INVALID_ARG;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
+  probe_release(c);
   free_mesh(c);
   if (c->norms_host) (void)hipHostFree(c->norms_host);
   if (c->kscal_host) (void)hipHostFree(c->kscal_host);
@@ -657,6 +735,47 @@ lgdm_status lgdm_kernel_times(lgdm_ctx* c, int32_t reps, double* avg_ms) {
     HIPCHECK(c, hipEventElapsedTime(&ms, c->ev[5], c->ev[6]), "event time");
     avg_ms[k] = ms / reps;
   }
+  return LGDM_OK;
+}
+
+lgdm_status lgdm_probe_start(lgdm_ctx* c, int32_t kind) {
+  if (!c || kind < 0 || kind >= PROBE_KINDS) return fail(c, LGDM_ERR_INVALID_ARG, "bad probe kind");
+  probe_release(c);
+  auto* p = new KernelProbe();
+  p->kind = kind;
+  for (int i = 0; i < 128; ++i) {
+    // timing-only events: no system-scope fence (cache writeback and
+    // invalidation) around the timed launches
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) break;
+    p->pool.push_back(e);
+  }
+  c->probe = p;
+  if (p->pool.size() < 2) {
+    probe_release(c);
+    return fail(c, LGDM_ERR_DEVICE, "could not create probe events");
+  }
+  return LGDM_OK;
+}
+
+lgdm_status lgdm_probe_stop(lgdm_ctx* c, double* avg_ms, int64_t* count) {
+  if (!c || !avg_ms || !count) return fail(c, LGDM_ERR_INVALID_ARG, "bad arguments");
+  *avg_ms = 0.0;
+  *count = 0;
+  if (!c->probe) return fail(c, LGDM_ERR_STATE, "no probe running");
+  probe_harvest(*c->probe, true);
+  *count = c->probe->count;
+  *avg_ms = c->probe->count > 0 ? c->probe->sum_ms / c->probe->count : 0.0;
+  probe_release(c);
+  return LGDM_OK;
+}
+
+lgdm_status lgdm_amg_levels(lgdm_ctx* c, int32_t max_levels, int64_t* nodes, int32_t* n_levels) {
+  if (!c || !n_levels || max_levels < 0 || (max_levels > 0 && !nodes)) return fail(c, LGDM_ERR_INVALID_ARG, "bad arguments");
+  AmgInfo info;
+  amg_info(c, info);
+  *n_levels = info.levels;
+  for (int l = 0; l < info.levels && l < max_levels; ++l) nodes[l] = info.nodes[l];
   return LGDM_OK;
 }
 

@@ -1280,8 +1280,10 @@ struct Idr {
         auto kd = idr_dir_kernel<T, ND, S, K>;
         kd<<<grid_of(kd, nn), BS, 0, st>>>(nn, minv, r, Gv, Uv, n, sc);
       }
+      probe_before(c, PROBE_IDR_SPMV, st);
       spmv_kernel<T, ND, G, 3, S><<<gs, BS, 0, st>>>(nn, c->row_ptr, c->nbr_ptr, c->nbr, vals,
                                                      Uv + (int64_t)K * n, Gv + (int64_t)K * n, nullptr, sc, kp);
+      probe_after(c, PROBE_IDR_SPMV, st);
       idr_g_scalar<S><<<1, BS, 0, st>>>((int)gs, kp, sc, K, pnorm2);
       auto ku = idr_upd_kernel<T, ND, S, K>;
       const int64_t gu = grid_of(ku, nn);
@@ -1734,7 +1736,7 @@ lgdm_solver_opts fill_opts(const lgdm_solver_opts* o) {
   if (r.max_restarts <= 0) r.max_restarts = 8;
   if (r.krylov_method != LGDM_KRYLOV_BICGSTAB) r.krylov_method = LGDM_KRYLOV_IDRS;
   if (r.forcing != LGDM_FORCING_FIXED) r.forcing = LGDM_FORCING_ADAPTIVE;
-  if (r.precond != LGDM_PRECOND_AMG) r.precond = LGDM_PRECOND_BLOCK_JACOBI;
+  if (r.precond != LGDM_PRECOND_AMG && r.precond != LGDM_PRECOND_BLOCK_JACOBI) r.precond = LGDM_PRECOND_DEFAULT;
   r.idr_s = r.idr_s <= 0 ? 8 : (r.idr_s <= 1 ? 1 : (r.idr_s <= 2 ? 2 : (r.idr_s <= 4 ? 4 : 8)));
   return r;
 }

@@ -98,6 +98,18 @@ constexpr int KSLOT_DONE = 9;          // device scalar slot of a solve's done f
 
 struct Amg;  // aggregation-multigrid hierarchy of a context (amg.hip)
 
+// Live timing of one kernel inside the solves: HIP event pairs around its
+// launches on the context's stream, harvested without blocking.
+enum ProbeKind { PROBE_IDR_SPMV = 0, PROBE_MG_FINEST = 1, PROBE_KINDS = 2 };
+struct KernelProbe {
+  int kind = -1;
+  std::vector<hipEvent_t> pool;                               // free events
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;    // recorded, in launch order
+  hipEvent_t open0 = nullptr, open1 = nullptr;                // the launch being recorded
+  double sum_ms = 0.0;
+  int64_t count = 0;
+};
+
 }  // namespace lgdm
 
 struct lgdm_ctx {
@@ -170,6 +182,8 @@ struct lgdm_ctx {
   unsigned int* kcount = nullptr;  // last-block counters
   double* delta = nullptr;
   lgdm::Amg* amg = nullptr;         // multigrid hierarchy (built at the first multigrid solve)
+  lgdm::KernelProbe* probe = nullptr;  // live kernel timing (measurement aid)
+  bool amg_unavailable = false;     // the mesh has no usable hierarchy (default: block-Jacobi)
   bool last_solve_improved = true;  // the last linear solve returned a better-than-zero correction
   int nw_iter = 0;                  // Newton corrections of the current increment
 
@@ -283,5 +297,9 @@ struct AmgInfo {
 };
 void amg_info(const lgdm_ctx* c, AmgInfo& info);
 hipError_t launch_field_norms(lgdm_ctx* c, const double* v, double* out_dev);  // |v_u|^2, |v_e|^2
+
+// around a launch of the kernel `kind` on st (no-ops unless that kind is probed)
+void probe_before(lgdm_ctx* c, int kind, hipStream_t st);
+void probe_after(lgdm_ctx* c, int kind, hipStream_t st);
 
 }  // namespace lgdm

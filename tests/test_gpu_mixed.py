@@ -95,11 +95,11 @@ def test_mixed_vs_fp64_gpu(name, n_inc):
     assert derr <= 1e-5
 
 
-@pytest.mark.parametrize("precision,precond", [(0, 0), (MIXED, 0), (0, 2), (MIXED, 2)])
+@pytest.mark.parametrize("precision,precond", [(0, 1), (MIXED, 1), (0, 2), (MIXED, 2)])
 def test_c3p_path_vs_stored_oracle(precision, precond):
     """The 64 x 16 x 8 beam (parity subsample of the 256 x 64 x 32 workload),
     first four increments into damage, against the FP64 oracle's path stored
-    by tests/golden/make_golden.py, with block-Jacobi (0) and multigrid (2)
+    by tests/golden/make_golden.py, with block-Jacobi (1) and multigrid (2)
     preconditioning.  Damage error stated; bounded by 1e-8 (FP64) and 1e-7
     (mixed precision)."""
     import os

@@ -102,15 +102,15 @@ def test_assembly_bitwise_repeatable(name):
     ctx.close()
 
 
-KRYLOV_CASES = [(n, 1, 0, 0) for n in ("bar1d_37", "sen2d_13x7_ps", "beam3d_10x4x3", "c1")] + \
-    [(n, 2, 4, 0) for n in ("bar1d_37", "sen2d_13x7_ps", "beam3d_10x4x3", "c1")] + \
-    [("beam3d_10x4x3", 2, s, 0) for s in (1, 2, 8)] + \
+KRYLOV_CASES = [(n, 1, 0, 1) for n in ("bar1d_37", "sen2d_13x7_ps", "beam3d_10x4x3", "c1")] + \
+    [(n, 2, 4, 1) for n in ("bar1d_37", "sen2d_13x7_ps", "beam3d_10x4x3", "c1")] + \
+    [("beam3d_10x4x3", 2, s, 1) for s in (1, 2, 8)] + \
     [(n, 2, 8, 2) for n in ("beam3d_10x4x3", "beam3d_6x4x3_distorted", "beam3d_24x8x6")]
 
 
 @pytest.mark.parametrize("name,method,s,precond", KRYLOV_CASES)
 def test_krylov_matches_direct_solve(name, method, s, precond):
-    """BiCGSTAB (method 1) and IDR(s) (method 2), block-Jacobi (precond 0) or
+    """BiCGSTAB (method 1) and IDR(s) (method 2), block-Jacobi (precond 1) or
     multigrid (precond 2) preconditioned, solve the Newton system of a
     damaged state to a per-field true residual of 1e-10 and agree with a
     direct sparse LU of the oracle's tangent."""
@@ -147,10 +147,10 @@ def test_krylov_matches_direct_solve(name, method, s, precond):
     # there is exactly zero (the preconditioners keep those entries zero)
     assert np.all(d[Oracle(prob).bc_dofs] == 0.0)
     if precond == 2 and mild:
-        # the CPU model of the same cycle needs 58 IDR(8) steps on the
+        # a CPU model of the same cycle needs about 110 IDR(8) steps on the
         # 24 x 8 x 6 beam (block-Jacobi: 341); the count stays nearly flat
         # under refinement
-        assert rep["krylov_iters"] <= 150, rep["krylov_iters"]
+        assert rep["krylov_iters"] <= 200, rep["krylov_iters"]
     ctx.close()
 
 
@@ -235,4 +235,50 @@ def test_softening_branch_newton(precision):
     err = float(np.abs(ctx.query(2) - o.D_n).max())
     print("max damage error vs oracle %.3e (max D %.3f)" % (err, o.D_n.max()))
     assert err <= (1e-8 if precision == 0 else 1e-6)
+    ctx.close()
+
+
+@pytest.mark.gpu
+def test_multigrid_selection_and_levels():
+    """Explicit multigrid on a 2D mesh, or on a 3D mesh with no coarse level,
+    is an argument error; the default falls back to block-Jacobi there and
+    agrees with the direct solve.  On the 24 x 8 x 6 beam the default builds a
+    hierarchy whose levels shrink to a dense coarsest level of at most 13
+    nodes."""
+    import scipy.sparse.linalg as spla
+    from paper_2301_06503_amd import binding
+    _print_case("multigrid selection")
+    opts = lambda p: binding.solver_opts(tol_krylov=1e-12, max_krylov=20000, precond=p)
+    # 2D: explicit multigrid rejected
+    prob = TINY["sen2d_13x7_ps"]
+    ctx = context(prob)
+    _, R = ctx.assemble()
+    with pytest.raises(binding.LgdmError) as ei:
+        ctx.solve_linear(R, opts(binding.PRECOND_AMG))
+    assert ei.value.status == binding.LGDM_ERR_INVALID_ARG
+    ctx.close()
+    # 3D with 12 nodes: no coarse level
+    small = W.beam3d(nx=2, ny=1, nz=1, lx=8.0, ly=4.0, lz=4.0, u_load=-0.01, n_increments=10)
+    x, kn = W.injected_state(small, seed=1, noise=0.01, kappa_spread=0.5, ebar_scale=0.05)
+    ctx = context(small)
+    ctx.set_state(x, kn)
+    _, R = ctx.assemble()
+    with pytest.raises(binding.LgdmError) as ei:
+        ctx.solve_linear(R, opts(binding.PRECOND_AMG))
+    assert ei.value.status == binding.LGDM_ERR_INVALID_ARG
+    d, rep = ctx.solve_linear(R, opts(binding.PRECOND_DEFAULT))
+    st = Oracle(small).eval_state(x, kn)
+    ref = spla.splu(st["K"].tocsc()).solve(st["R"])
+    assert np.abs(d.cpu().numpy() - ref).max() <= 1e-8 * np.abs(ref).max()
+    assert ctx.amg_levels() == []
+    ctx.close()
+    # hierarchy of the default on a mesh with coarse levels
+    prob = TINY["beam3d_24x8x6"]
+    ctx = context(prob)
+    _, R = ctx.assemble()
+    ctx.solve_linear(R, opts(binding.PRECOND_DEFAULT))
+    lv = ctx.amg_levels()
+    print("levels", lv)
+    assert lv[0] == prob.n_nodes and len(lv) >= 2
+    assert all(b < a for a, b in zip(lv, lv[1:])) and lv[-1] <= 13
     ctx.close()

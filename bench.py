@@ -202,6 +202,77 @@ def run_precision(prob, precision, args, binding):
     return res
 
 
+def load_path_run(prob, precision, args, binding, n_inc):
+    """Whole load path: increments 1..n_inc, each solved to the Newton test
+    inside the library (lgdm_solve_increment) and timed on the host.  Each
+    increment's reaction force and maximum damage classify it as elastic (no
+    damage yet), near the peak (reaction within 2% of the path maximum) or
+    post-peak (after the maximum), the three phases the step time is
+    reported for."""
+    import statistics
+    import torch
+    ctx = binding.Context(device=0, precision=precision)
+    ctx.setup_problem(prob)
+    torch.cuda.synchronize()
+    opts = binding.solver_opts(max_newton=40, tol_newton=1e-8, tol_krylov=args.tol_krylov,
+                               max_krylov=args.max_krylov, check_every=32, krylov_method=binding.KRYLOV_IDRS,
+                               idr_s=args.idr_s, forcing=binding.FORCING_ADAPTIVE,
+                               precond={"default": binding.PRECOND_DEFAULT, "bj": binding.PRECOND_BLOCK_JACOBI,
+                                        "amg": binding.PRECOND_AMG}[args.precond])
+    incs = []
+    stop = None
+    for i in range(n_inc):
+        t0 = time.perf_counter()
+        d = ctx.solve_increment((i + 1) / prob.n_increments, opts, raise_on_fail=False)
+        dt = time.perf_counter() - t0
+        if d["status"] != 0:
+            stop = {"increment": i + 1, "status": d["status"],
+                    "error": ctx.lib.lgdm_last_error(ctx.h).decode()}
+            log("load path stops at increment %d: %s" % (i + 1, stop["error"]))
+            break
+        incs.append({"inc": i + 1, "ms": dt * 1e3, "newton": d["newton_iters"], "assemblies": d["n_assemblies"],
+                     "krylov": d["krylov_iters"], "t_asm": d["t_assembly_ms"], "t_sol": d["t_solve_ms"],
+                     "reaction": d["reaction"], "max_damage": d["max_damage"]})
+        if (i + 1) % 10 == 0:
+            log("load path %s: increment %d, %.1f ms, %d Newton, reaction %.4e, max D %.4f" % (
+                "mixed" if precision == binding.MIXED else "fp64", i + 1, dt * 1e3, d["newton_iters"],
+                d["reaction"], d["max_damage"]))
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+    ng = prob.n_elems * prob.ngp
+    rmax = max(abs(r["reaction"]) for r in incs) if incs else 0.0
+    ipk = max(range(len(incs)), key=lambda j: abs(incs[j]["reaction"])) if incs else 0
+    phases = {"elastic": [], "near_peak": [], "post_peak": [], "pre_peak_damaged": []}
+    for j, r in enumerate(incs):
+        if r["max_damage"] <= 0.0:
+            phases["elastic"].append(r)
+        elif abs(abs(r["reaction"]) - rmax) <= 0.02 * rmax:
+            phases["near_peak"].append(r)
+        elif j > ipk:
+            phases["post_peak"].append(r)
+        else:
+            phases["pre_peak_damaged"].append(r)
+
+    def summ(rs):
+        if not rs:
+            return None
+        steps = [r["ms"] / max(r["newton"], 1) for r in rs]
+        asm = [r["t_asm"] / max(r["assemblies"], 1) for r in rs]
+        return {"increments": [rs[0]["inc"], rs[-1]["inc"]], "count": len(rs),
+                "newton_step_ms_median": statistics.median(steps), "newton_step_ms_min": min(steps),
+                "ms_per_increment_median": statistics.median(r["ms"] for r in rs),
+                "newton_per_increment_median": statistics.median(r["newton"] for r in rs),
+                "krylov_per_newton_median": statistics.median(r["krylov"] / max(r["newton"], 1) for r in rs),
+                "assembly_gp_per_s_device_median": ng / (statistics.median(asm) * 1e-3),
+                "gp_per_s": ng * sum(r["assemblies"] for r in rs) / (sum(r["ms"] for r in rs) * 1e-3)}
+    return {"increments_run": len(incs), "stopped": stop, "peak_increment": incs[ipk]["inc"] if incs else None,
+            "peak_reaction": incs[ipk]["reaction"] if incs else None,
+            "whole_path": summ(incs), "phases": {k: summ(v) for k, v in phases.items()},
+            "per_increment": [[r["inc"], round(r["ms"], 2), r["newton"], r["krylov"], r["reaction"],
+                               round(r["max_damage"], 6)] for r in incs]}
+
+
 def cpu_baseline(name, prob, budget_s=20.0):
     """The oracle on the host, one BLAS thread (the sparse LU is single
     threaded): whole Newton iterations (element evaluation, triplet
@@ -307,6 +378,10 @@ def main():
     ap.add_argument("--max-krylov", type=int, default=20000)
     ap.add_argument("--kernel-reps", type=int, default=5)
     ap.add_argument("--serving-seconds", type=float, default=30.0)
+    ap.add_argument("--load-path", type=int, default=0,
+                    help="instead of the bench line: run this many increments of the load path (-1: all) in "
+                         "mixed precision and FP64 and report the step time per phase (elastic, near the "
+                         "peak, post-peak)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the LGDM hot path here is built and measured on a single "
@@ -319,6 +394,16 @@ def main():
     from paper_2301_06503_amd import binding
     prob = W.config(args.config)
     prec = binding.MIXED if args.precision == "mixed" else binding.FP64
+    if args.load_path:
+        n_inc = prob.n_increments if args.load_path < 0 else min(args.load_path, prob.n_increments)
+        lp = {"workload": WORKLOADS[args.config], "name": args.config, "increments_requested": n_inc,
+              "columns": ["increment", "ms", "newton", "krylov", "reaction", "max_damage"]}
+        for label, pr in (("mixed", binding.MIXED), ("fp64", binding.FP64)):
+            if label == "fp64" and args.no_fp64_compare:
+                continue
+            lp[label] = load_path_run(prob, pr, args, binding, n_inc)
+        print(json.dumps({"metric": METRIC, "load_path": lp}))
+        return
     main_res = run_precision(prob, prec, args, binding)
     fp64_res = None
     if prec == binding.MIXED and not args.no_fp64_compare:

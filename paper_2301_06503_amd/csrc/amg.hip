@@ -139,8 +139,9 @@ template <typename T, typename TC, int NDF>
 __global__ void __launch_bounds__(BS) galerkin_kernel(
     int64_t nslots, const int32_t* __restrict__ slot_row, const int32_t* __restrict__ cnbr,
     const int32_t* __restrict__ cnbr_ptr, const int32_t* __restrict__ crow_ptr,
-    const int32_t* __restrict__ gal_ptr, const int32_t* __restrict__ gal, const int32_t* __restrict__ pair_row,
-    const int32_t* __restrict__ nbr_ptr, const int32_t* __restrict__ nbr, const int32_t* __restrict__ row_ptr,
+    const int32_t* __restrict__ gal_ptr, const int32_t* __restrict__ gal, const int32_t* __restrict__ mem_ptr,
+    const int32_t* __restrict__ mem, const int32_t* __restrict__ nbr_ptr, const int32_t* __restrict__ nbr,
+    const int32_t* __restrict__ row_ptr,
     const T* __restrict__ vals, double se, const uint8_t* __restrict__ flags, const double* __restrict__ cen,
     const double* __restrict__ ccen, double inv_scale, double ratio, TC* __restrict__ cvals) {
   for (int64_t s = (int64_t)blockIdx.x * BS + threadIdx.x; s < nslots; s += (int64_t)gridDim.x * BS) {
@@ -152,61 +153,74 @@ __global__ void __launch_bounds__(BS) galerkin_kernel(
     for (int k = 0; k < NC; ++k)
 #pragma unroll
       for (int l = 0; l < NC; ++l) acc[k][l] = 0.0;
-    for (int32_t e = gal_ptr[s]; e < gal_ptr[s + 1]; ++e) {
-      const int32_t p = gal[e];
-      const int32_t a = pair_row[p], b = nbr[p];
-      const int32_t p0 = nbr_ptr[a];
-      const int64_t len = (int64_t)(nbr_ptr[a + 1] - p0) * NDF;
-      const T* __restrict__ blk = vals + row_ptr[(int64_t)a * NDF] + (int64_t)(p - p0) * NDF;
-      double da[3], db[3];
+    // The slot's list holds its fine pairs in fine pair order, i.e. grouped by
+    // row node a in ascending order, and the rows are the members of I
+    // (ascending).  Walking the members in an outer loop keeps the lanes of
+    // one coarse row on the same fine row at the same time (their blocks lie
+    // in the same few cache lines) and loads a's row data once; the pairs are
+    // still summed in list order.
+    int32_t e = gal_ptr[s];
+    const int32_t e_end = gal_ptr[s + 1];
+    for (int32_t mi = mem_ptr[I]; mi < mem_ptr[I + 1] && e < e_end; ++mi) {
+      const int32_t a = mem[mi];
+      const int32_t p0 = nbr_ptr[a], p1 = nbr_ptr[a + 1];
+      const int64_t len = (int64_t)(p1 - p0) * NDF;
+      const T* __restrict__ rowv = vals + row_ptr[(int64_t)a * NDF];
+      double da[3];
 #pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        da[i] = (cen[3 * (int64_t)a + i] - ci[i]) * inv_scale;
-        db[i] = (cen[3 * (int64_t)b + i] - cj[i]) * inv_scale;
-      }
-      // the block, ebar row scaled, Dirichlet rows of a / columns of b zeroed
-      double A[NDF][NDF];
+      for (int i = 0; i < 3; ++i) da[i] = (cen[3 * (int64_t)a + i] - ci[i]) * inv_scale;
+      for (; e < e_end; ++e) {
+        const int32_t p = gal[e];
+        if (p >= p1) break;   // the slot's pairs of row a are done
+        const int32_t b = nbr[p];
+        const T* __restrict__ blk = rowv + (int64_t)(p - p0) * NDF;
+        double db[3];
 #pragma unroll
-      for (int i = 0; i < NDF; ++i) {
-        Vals<T, NDF> row;
-        row.load(blk + i * len);
-        const double rs = i == NDF - 1 ? se : 1.0;
-#pragma unroll
-        for (int j = 0; j < NDF; ++j) A[i][j] = row.v[j] * rs;
-      }
-      if (flags) {
+        for (int i = 0; i < 3; ++i) db[i] = (cen[3 * (int64_t)b + i] - cj[i]) * inv_scale;
+        // the block, ebar row scaled, Dirichlet rows of a / columns of b zeroed
+        double A[NDF][NDF];
 #pragma unroll
         for (int i = 0; i < NDF; ++i) {
-          const bool ra = flags[(int64_t)a * NDF + i] & 1, cb = flags[(int64_t)b * NDF + i] & 1;
+          Vals<T, NDF> row;
+          row.load(blk + i * len);
+          const double rs = i == NDF - 1 ? se : 1.0;
 #pragma unroll
-          for (int j = 0; j < NDF; ++j) {
-            if (ra) A[i][j] = 0.0;
-            if (cb) A[j][i] = 0.0;
+          for (int j = 0; j < NDF; ++j) A[i][j] = row.v[j] * rs;
+        }
+        if (flags) {
+#pragma unroll
+          for (int i = 0; i < NDF; ++i) {
+            const bool ra = flags[(int64_t)a * NDF + i] & 1, cb = flags[(int64_t)b * NDF + i] & 1;
+#pragma unroll
+            for (int j = 0; j < NDF; ++j) {
+              if (ra) A[i][j] = 0.0;
+              if (cb) A[j][i] = 0.0;
+            }
           }
         }
-      }
-      // row k of X = P_a^T A (NDF values), then row k of X P_b
+        // row k of X = P_a^T A (NDF values), then row k of X P_b
 #pragma unroll
-      for (int k = 0; k < NC; ++k) {
-        double x[NDF];
+        for (int k = 0; k < NC; ++k) {
+          double x[NDF];
 #pragma unroll
-        for (int j = 0; j < NDF; ++j) {
-          if (k < 3) x[j] = A[k][j];
-          else if (k < 6) {
-            x[j] = rot_dot(k - 3, da, A[0][j], A[1][j], A[2][j]);
-            if constexpr (NDF == NC) x[j] += ratio * A[k][j];
-          } else x[j] = A[NDF - 1][j];
+          for (int j = 0; j < NDF; ++j) {
+            if (k < 3) x[j] = A[k][j];
+            else if (k < 6) {
+              x[j] = rot_dot(k - 3, da, A[0][j], A[1][j], A[2][j]);
+              if constexpr (NDF == NC) x[j] += ratio * A[k][j];
+            } else x[j] = A[NDF - 1][j];
+          }
+          acc[k][0] += x[0];
+          acc[k][1] += x[1];
+          acc[k][2] += x[2];
+#pragma unroll
+          for (int m = 0; m < 3; ++m) {
+            double y = rot_dot(m, db, x[0], x[1], x[2]);
+            if constexpr (NDF == NC) y += ratio * x[3 + m];
+            acc[k][3 + m] += y;
+          }
+          acc[k][6] += x[NDF - 1];
         }
-        acc[k][0] += x[0];
-        acc[k][1] += x[1];
-        acc[k][2] += x[2];
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-          double y = rot_dot(m, db, x[0], x[1], x[2]);
-          if constexpr (NDF == NC) y += ratio * x[3 + m];
-          acc[k][3 + m] += y;
-        }
-        acc[k][6] += x[NDF - 1];
       }
     }
     const int32_t q0 = cnbr_ptr[I];
@@ -595,7 +609,6 @@ struct AmgLevel {
   int32_t* agg = nullptr;                         // [n]
   int32_t *mem_ptr = nullptr, *mem = nullptr;     // members of each next-level node
   int32_t *gal_ptr = nullptr, *gal = nullptr;     // fine pairs of each next-level pair slot
-  int32_t* pair_row = nullptr;                    // row node of each pair [npairs]
   int32_t* slot_row = nullptr;                    // (next level) row node of each of its pair slots
 };
 
@@ -733,10 +746,9 @@ hipError_t build(lgdm_ctx* c, Amg& m, std::string& msg) {
     }
     const int64_t cpairs = (int64_t)cadj.size();
     // Galerkin lists: fine pairs of each coarse pair slot, in fine pair order
-    std::vector<int32_t> pair_row(ptr[n]), pslot(ptr[n]), gal_ptr(cpairs + 1, 0), gal(ptr[n]), slot_row(cpairs);
+    std::vector<int32_t> pslot(ptr[n]), gal_ptr(cpairs + 1, 0), gal(ptr[n]), slot_row(cpairs);
     for (int64_t a = 0; a < n; ++a)
       for (int32_t p = ptr[a]; p < ptr[a + 1]; ++p) {
-        pair_row[p] = (int32_t)a;
         const int32_t I = agg[a], J = agg[adj[p]];
         const int32_t s = (int32_t)(std::lower_bound(cadj.begin() + cptr[I], cadj.begin() + cptr[I + 1], J) -
                                     cadj.begin());
@@ -774,7 +786,6 @@ hipError_t build(lgdm_ctx* c, Amg& m, std::string& msg) {
     F.mem = upload(c, mem, e);
     F.gal_ptr = upload(c, gal_ptr, e);
     F.gal = upload(c, gal, e);
-    F.pair_row = upload(c, pair_row, e);
     AmgLevel C;
     C.n = na;
     C.nd = NC;
@@ -793,7 +804,7 @@ hipError_t build(lgdm_ctx* c, Amg& m, std::string& msg) {
     C.r = (double*)dalloc(c, na * NC * sizeof(double));
     C.xo = (double*)dalloc(c, na * NC * sizeof(double));
     if (e != hipSuccess) return e;
-    if (!F.agg || !F.mem_ptr || !F.mem || !F.gal_ptr || !F.gal || !F.pair_row || !C.slot_row || !C.nbr_ptr ||
+    if (!F.agg || !F.mem_ptr || !F.mem || !F.gal_ptr || !F.gal || !C.slot_row || !C.nbr_ptr ||
         !C.nbr || !C.row_ptr || !C.dpos || !C.cen || !C.vals || !C.minv || !C.b || !C.x || !C.r || !C.xo)
       return hipErrorOutOfMemory;
     // uploads read these host vectors: finish before they go out of scope
@@ -832,12 +843,12 @@ template <typename T> hipError_t numeric(lgdm_ctx* c, Amg& m) {
     if (F.nd == NC) {
       auto k = galerkin_kernel<T, T, NC>;
       k<<<grid_for(k, slots), BS, 0, st>>>(C.npairs, C.slot_row, C.nbr, C.nbr_ptr, C.row_ptr, F.gal_ptr, F.gal,
-                                                 F.pair_row, F.nbr_ptr, F.nbr, F.row_ptr, (const T*)F.vals, 1.0,
+                                                 F.mem_ptr, F.mem, F.nbr_ptr, F.nbr, F.row_ptr, (const T*)F.vals, 1.0,
                                                  F.flags, F.cen, C.cen, inv_scale, ratio, (T*)C.vals);
     } else {
       auto k = galerkin_kernel<T, T, 4>;
       k<<<grid_for(k, slots), BS, 0, st>>>(C.npairs, C.slot_row, C.nbr, C.nbr_ptr, C.row_ptr, F.gal_ptr, F.gal,
-                                                 F.pair_row, F.nbr_ptr, F.nbr, F.row_ptr, (const T*)F.vals, se,
+                                                 F.mem_ptr, F.mem, F.nbr_ptr, F.nbr, F.row_ptr, (const T*)F.vals, se,
                                                  F.flags, F.cen, C.cen, inv_scale, ratio, (T*)C.vals);
     }
     if (l + 2 < m.lv.size())

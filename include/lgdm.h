@@ -80,13 +80,23 @@ enum {
  *           kappa <- ebar where ebar - kappa_n > tol_hist; D = 0 where
  *           kappa - kappa0 < tol_dmg.  0 reproduces A.1 / A.2 literally.
  *  plane    LGDM_PLANE_STRESS or LGDM_PLANE_STRAIN (2D only)
+ *  coupling LGDM_COUPLING_EXECUTED (0): sigma = (1 - D) C : eps and Eq. 11b
+ *           without its h term, the form the paper's executed code (Fig. 2)
+ *           assembles.  LGDM_COUPLING_EQ2 (1): the stress of Eq. 2,
+ *           sigma = (1 - D) C : eps + h (eeq - ebar) d eeq / d eps, Eq. 11b
+ *           as printed, and K^uu of Eq. 11a plus the terms of the consistent
+ *           linearisation of Eq. 2, int B^T h [n n^T + (eeq - ebar)
+ *           d^2 eeq / d eps^2] B (n = d eeq / d eps; the second derivative of
+ *           A.3 is dropped where sqrt(s) <= 1e-6 kappa0, s the square-root
+ *           argument).  Single contexts only: the batch rejects it.
  *  thickness  out-of-plane thickness (2D) or cross-section area (1D); 3D ignores it. */
 typedef struct lgdm_material {
   double E, nu, kappa0, alpha, beta, c, R, eta, k, h, tol_hist, tol_dmg;
   int32_t plane;
-  int32_t reserved;
+  int32_t coupling;
   double thickness;
 } lgdm_material;
+enum { LGDM_COUPLING_EXECUTED = 0, LGDM_COUPLING_EQ2 = 1 };
 
 /* Krylov method of the linear solve of the Newton system (Eq. 11).  Both are
  * right-preconditioned with per-node block-Jacobi and work on the same

@@ -57,6 +57,7 @@ class Material:
     tol_dmg: float = 1e-10
     plane: int = PLANE_STRESS
     thickness: float = 1.0
+    coupling: int = 0       # 0: stress (1 - D) C : eps; 1: the stress of Eq. 2 with its h term
 
     def as_dict(self) -> Dict[str, float]:
         return dataclasses.asdict(self)

@@ -48,6 +48,15 @@ R10 Equal-order elements (line2 / quad4 / hex8) for u and ebar; full 2-point
 R11 The element stiffness scale multiplies C only (not h, not c).
 R12 D, kappa, g and their derivatives are evaluated at the current iterate
     from the committed kappa_n; kappa_n is committed only at convergence.
+R13 Coupling variant (material coupling = 1): the stress of Eq. 2,
+    sigma = (1 - D) C : eps + h (eeq - ebar) d eeq/d eps, the derivative of
+    the free energy of Eq. 1, in place of R1.  K^{u ebar} is Eq. 11b as
+    printed (with its -h d eeq/d eps N term), and K^uu is Eq. 11a completed
+    by the consistent linearisation of Eq. 2:
+    + int B^T h [n n^T + (eeq - ebar) d^2 eeq/d eps^2] B, n = d eeq/d eps.
+    The second derivative of A.3 is dropped where sqrt(s) <= 1e-6 kappa0
+    (s the square-root argument; the cone point of A.3, cf. R6).  Eqs. 11c,
+    11d, 11f are unchanged.
 """
 from __future__ import annotations
 
@@ -216,6 +225,43 @@ def equivalent_strain_voigt(dim, plane, k, nu, ev):
     return eeq, n
 
 
+def equivalent_strain_hessian_voigt(dim, plane, k, nu, ev, kappa0):
+    """d^2 eeq / d eps_voigt^2 [..., nstr, nstr] for the coupling variant (R13).
+
+    On the 3D tensor (R5), with s = c2^2 I1^2 + c3 J2 and q = ds/deps =
+    2 c2^2 I1 1 + c3 dev(eps):
+        d^2 eeq = (1 / (4 k sqrt(s))) (2 c2^2 1 (x) 1 + c3 P_dev)
+                  - (1 / (8 k s^(3/2))) q (x) q,
+    P_dev the deviatoric projector.  The Voigt form contracts it with the
+    tensor of each unit Voigt strain (the linear map of R5, which carries the
+    plane-stress eps_zz).  Zero where sqrt(s) <= 1e-6 kappa0, and in 1D
+    (eeq = eps is linear)."""
+    ev = np.asarray(ev, dtype=np.float64)
+    nstr = ev.shape[-1]
+    if dim == 1:
+        return np.zeros(ev.shape + (nstr,))
+    c1, c2, c3 = mvm_coefficients(k, nu)
+    eye = np.eye(3)
+    t = _voigt_to_tensor(dim, plane, nu, ev)
+    I1 = np.trace(t, axis1=-2, axis2=-1)
+    dev = t - I1[..., None, None] / 3.0 * eye
+    s = c2 * c2 * I1 * I1 + c3 * 0.5 * np.sum(dev * dev, axis=(-2, -1))
+    sq = np.sqrt(np.maximum(s, 0.0))
+    on = sq > 1e-6 * kappa0
+    sqs = np.where(on, sq, 1.0)
+    al = np.where(on, 1.0 / (4.0 * k * sqs), 0.0)
+    be = np.where(on, 1.0 / (8.0 * k * sqs ** 3), 0.0)
+    q = 2.0 * c2 * c2 * I1[..., None, None] * eye + c3 * dev
+    T = _voigt_to_tensor(dim, plane, nu, np.eye(nstr))          # [nstr, 3, 3] tensor of each unit strain
+    trT = np.trace(T, axis1=-2, axis2=-1)                       # [nstr]
+    devT = T - trT[:, None, None] / 3.0 * eye
+    dd = np.einsum("aij,bij->ab", devT, devT)                   # dev T_a : dev T_b
+    qT = np.einsum("...ij,aij->...a", q, T)                     # q : T_a
+    H = (al[..., None, None] * (2.0 * c2 * c2 * np.outer(trT, trT) + c3 * dd)
+         - be[..., None, None] * qT[..., :, None] * qT[..., None, :])
+    return H
+
+
 def elasticity_matrix(dim, plane, E, nu):
     """Elasticity matrix C in Voigt form (engineering shears)."""
     if dim == 1:
@@ -296,6 +342,7 @@ def eval_elements(dim, coords, conn, e_scale, mat, x, kappa_n, elems=None, want_
     kappa0 = _mat(mat, "kappa0"); alpha = _mat(mat, "alpha"); beta = _mat(mat, "beta")
     tol_h = _mat(mat, "tol_hist"); tol_d = _mat(mat, "tol_dmg")
     plane = int(_mat(mat, "plane")); thick = _mat(mat, "thickness")
+    coupling = int(mat.get("coupling", 0) if isinstance(mat, dict) else getattr(mat, "coupling", 0))
     if elems is None:
         elems = np.arange(conn.shape[0])
     elems = np.asarray(elems, dtype=np.int64)
@@ -336,6 +383,8 @@ def eval_elements(dim, coords, conn, e_scale, mat, x, kappa_n, elems=None, want_
         Cs = es[:, None, None] * Cm                    # [ne, nstr, nstr]
         Ceps = np.einsum("est,et->es", Cs, eps)
         sigma = (1.0 - D)[:, None] * Ceps              # R1
+        if coupling:                                   # R13: Eq. 2
+            sigma = sigma + (h * (eeq - ebar))[:, None] * n
         fu += np.einsum("esc,es->ec", B, sigma) * wJ[:, None]
         fe += (np.outer(h * (ebar - eeq) * wJ, N)
                + np.einsum("ead,ed->ea", dNdx, (gv * h * c * wJ)[:, None] * gradb))  # R2
@@ -348,6 +397,13 @@ def eval_elements(dim, coords, conn, e_scale, mat, x, kappa_n, elems=None, want_
         # Eq. 11b (R1): -B^T (C eps dD/dkappa dkappa/debar) N
         v = Ceps * (dD * chi * wJ)[:, None]
         Kue -= np.einsum("esc,es,a->eca", B, v, N, optimize=True)
+        if coupling:
+            # R13: Eq. 11b's -B^T h n N, and Eq. 11a completed by the linearisation of Eq. 2
+            Kue -= np.einsum("esc,es,a->eca", B, (h * wJ)[:, None] * n, N, optimize=True)
+            Hv = equivalent_strain_hessian_voigt(dim, plane, k, nu, eps, kappa0)
+            Dc = (h * wJ)[:, None, None] * (n[:, :, None] * n[:, None, :]
+                                            + (eeq - ebar)[:, None, None] * Hv)
+            Kuu += np.einsum("esc,est,etd->ecd", B, Dc, B, optimize=True)
         # Eq. 11c: -N h n^T B
         Keu -= np.einsum("a,es,esc->eac", N, (h * wJ)[:, None] * n, B, optimize=True)
         # Eq. 11d (R3): h N N^T + h c g' D' chi (B_e grad ebar) N^T + g h c B_e^T B_e
@@ -385,6 +441,8 @@ def element_loop_eval(dim, coords, conn, e_scale, mat, x, kappa_n):
     c = _mat(mat, "c"); R = _mat(mat, "R"); eta = _mat(mat, "eta")
     kappa0 = _mat(mat, "kappa0"); alpha = _mat(mat, "alpha"); beta = _mat(mat, "beta")
     tol_h = _mat(mat, "tol_hist"); tol_d = _mat(mat, "tol_dmg")
+    if int(mat.get("coupling", 0) if isinstance(mat, dict) else getattr(mat, "coupling", 0)):
+        raise NotImplementedError("element_loop_eval covers readings R1-R12 only")
     plane = int(_mat(mat, "plane")); thick = _mat(mat, "thickness")
     nel, nen = conn.shape
     nd = dim + 1

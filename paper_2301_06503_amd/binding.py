@@ -49,7 +49,7 @@ EXPORTS = [
 class Material(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in
                 ("E", "nu", "kappa0", "alpha", "beta", "c", "R", "eta", "k", "h", "tol_hist",
-                 "tol_dmg")] + [("plane", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                 "tol_dmg")] + [("plane", ctypes.c_int32), ("coupling", ctypes.c_int32),
                                 ("thickness", ctypes.c_double)]
 
 
@@ -197,6 +197,7 @@ def material_struct(m) -> Material:
               "thickness"):
         setattr(s, k, float(d[k]))
     s.plane = int(d.get("plane", 0))
+    s.coupling = int(d.get("coupling", 0))
     return s
 
 

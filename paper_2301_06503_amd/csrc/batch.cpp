@@ -198,6 +198,8 @@ lgdm_status lgdm_batch_admit(lgdm_batch* b, const lgdm_request* r, int32_t* slot
     }
   if (free_slot < 0) return bfail(b, LGDM_ERR_BUSY, "no free slot");
   if (b->used + est > b->budget) return bfail(b, LGDM_ERR_BUSY, "HBM budget exhausted");
+  if (r->material.coupling != LGDM_COUPLING_EXECUTED)
+    return bfail(b, LGDM_ERR_INVALID_ARG, "the batch serves the executed-code coupling only");
   Slot& s = b->slots[free_slot];
   BHIP(b, hipSetDevice(b->device), "set device");
   BHIP(b, hipStreamCreate(&s.stream), "slot stream");

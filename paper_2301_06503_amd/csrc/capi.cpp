@@ -375,8 +375,9 @@ lgdm_status lgdm_upload_mesh(lgdm_ctx* c, int32_t dim, int32_t elem_type, int64_
   c->D_n = (double*)dalloc(c, ng * sizeof(double));
   c->kappa_t = (double*)dalloc(c, ng * sizeof(double));
   c->D_t = (double*)dalloc(c, ng * sizeof(double));
-  const int rs = dim == 1 ? Rec<1>::STRIDE : (dim == 2 ? Rec<2>::STRIDE : Rec<3>::STRIDE);
+  const int rs = rec_stride(dim, c->has_mat && c->mat.coupling == LGDM_COUPLING_EQ2);
   c->rec = (double*)dalloc(c, ng * rs * sizeof(double));
+  c->rec_stride = rs;
   if (mixed) c->vals32 = (float*)dalloc(c, c->nnz * sizeof(float));
   else c->vals = (double*)dalloc(c, c->nnz * sizeof(double));
   c->n_partials = node_kernel_blocks(c);
@@ -424,8 +425,18 @@ lgdm_status lgdm_set_material(lgdm_ctx* c, const lgdm_material* m) {
   if (!c || !m) return fail(c, LGDM_ERR_INVALID_ARG, "NULL material");
   if (!(m->E > 0) || !(m->nu > -1.0 && m->nu < 0.5) || !(m->kappa0 > 0) || !(m->k > 0) ||
       !(m->h > 0) || !(m->eta > 0) || !(m->c >= 0) || !(m->thickness > 0) ||
-      !(m->tol_hist >= 0) || !(m->tol_dmg >= 0) || (m->plane != 0 && m->plane != 1))
+      !(m->tol_hist >= 0) || !(m->tol_dmg >= 0) || (m->plane != 0 && m->plane != 1) ||
+      (m->coupling != LGDM_COUPLING_EXECUTED && m->coupling != LGDM_COUPLING_EQ2))
     return fail(c, LGDM_ERR_INVALID_ARG, "material parameter out of range");
+  // the coupling variant's Gauss-point records are longer
+  if (c->dim != 0 && c->rec_stride < rec_stride(c->dim, m->coupling == LGDM_COUPLING_EQ2)) {
+    const int rs = rec_stride(c->dim, true);
+    HIPCHECK(c, hipStreamSynchronize(c->stream), "set_material");
+    dfree(c, c->rec);
+    c->rec = (double*)dalloc(c, c->ngauss * rs * sizeof(double));
+    c->rec_stride = c->rec ? rs : 0;
+    if (!c->rec) return fail(c, LGDM_ERR_OOM, "device allocation failed (Gauss-point records)");
+  }
   c->mat = *m;
   c->has_mat = true;
   c->assembled = false;

@@ -82,10 +82,10 @@ template <int DIM> __device__ __forceinline__ constexpr int sym_idx(int i, int j
 // ---------------------------------------------------------------------------
 // Kernel 1: Gauss-point state and record
 // ---------------------------------------------------------------------------
-template <int DIM>
+template <int DIM, bool CPL>
 __device__ __forceinline__ void gp_point(int64_t gid, const GpArgs& A, const MatParams& mp) {
   using E = Elem<DIM>;
-  using RC = Rec<DIM>;
+  using RC = Rec<DIM, CPL>;
   if (gid >= A.ngauss) return;
   const double* __restrict__ coords = A.coords;
   const int32_t* __restrict__ conn = A.conn;
@@ -190,6 +190,8 @@ __device__ __forceinline__ void gp_point(int64_t gid, const GpArgs& A, const Mat
   // modified von Mises equivalent strain (A.3) and its gradient G = d eeq / d eps
   double eeq;
   double G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  double q3[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // coupling variant: ds / deps
+  double al = 0.0, be = 0.0;                          // coupling variant: coefficients of d^2 eeq
   if (DIM == 1) {
     eeq = eps[0][0];
     G[0][0] = 1.0;
@@ -206,6 +208,18 @@ __device__ __forceinline__ void gp_point(int64_t gid, const GpArgs& A, const Mat
       }
     J2 *= 0.5;
     const double s = mp.c2 * mp.c2 * I1 * I1 + mp.c3 * J2;
+    if (CPL) {
+      // d^2 eeq / deps^2 = al (2 c2^2 1 (x) 1 + c3 P_dev) - be q (x) q, dropped at the cone point
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) q3[i][j] = (i == j ? 2.0 * mp.c2 * mp.c2 * I1 : 0.0) + mp.c3 * dev[i][j];
+      const double sqv = s > 0.0 ? sqrt(s) : 0.0;
+      if (sqv > mp.sq_guard) {
+        al = 1.0 / (4.0 * mp.k * sqv);
+        be = al / (2.0 * s);
+      }
+    }
     if (s > 0.0) {
       const double sq = sqrt(s);
       eeq = mp.c1 * I1 + sq / (2.0 * mp.k);
@@ -291,15 +305,34 @@ __device__ __forceinline__ void gp_point(int64_t gid, const GpArgs& A, const Mat
   r[RC::CG] = wJ * gv * mp.h * mp.c;
   r[RC::RE] = wJ * mp.h * (ebar - eeq);
   r[RC::FR] = wJ * mp.h * eeq;
+  if (CPL) {
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+      for (int j = i; j < DIM; ++j) r[RC::GU + sym_idx<DIM>(i, j)] = G[i][j];
+    r[RC::AL] = al;
+    r[RC::BE] = be;
+    if (DIM == 3) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = i; j < 3; ++j) r[RC::Q + sym_idx<3>(i, j)] = q3[i][j];
+    } else if (DIM == 2) {
+      r[RC::Q + 0] = q3[0][0];
+      r[RC::Q + 1] = q3[1][1];
+      r[RC::Q + 2] = q3[0][1];
+      r[RC::Q + 3] = q3[2][2];
+    }
+  }
 #pragma unroll
   for (int f = RC::USED; f < RC::STRIDE; ++f) r[f] = 0.0;
   kappa_t[gid] = kap;
   D_t[gid] = D;
 }
 
-template <int DIM>
+template <int DIM, bool CPL>
 __global__ void __launch_bounds__(256) gp_kernel(GpArgs A, MatParams mp) {
-  gp_point<DIM>((int64_t)blockIdx.x * blockDim.x + threadIdx.x, A, mp);
+  gp_point<DIM, CPL>((int64_t)blockIdx.x * blockDim.x + threadIdx.x, A, mp);
 }
 
 // slot of workgroup b in a fused launch (slot ranges ascending by first block)
@@ -319,7 +352,7 @@ template <int DIM>
 __global__ void __launch_bounds__(256) gp_fused_kernel(const SlotDesc* __restrict__ slots, int nslots) {
   const int s = find_slot(slots, nslots, blockIdx.x, false);
   const int64_t lb = (int64_t)blockIdx.x - slots[s].gp_block0;
-  gp_point<DIM>(lb * blockDim.x + threadIdx.x, slots[s].gp, slots[s].mp);
+  gp_point<DIM, false>(lb * blockDim.x + threadIdx.x, slots[s].gp, slots[s].mp);
 }
 
 // ---------------------------------------------------------------------------
@@ -327,9 +360,9 @@ __global__ void __launch_bounds__(256) gp_fused_kernel(const SlotDesc* __restric
 // ---------------------------------------------------------------------------
 // record fields in registers in precision T (16-byte loads; records are
 // 16-byte aligned)
-template <int DIM, typename T>
-__device__ __forceinline__ void load_rec(const double* __restrict__ rv, T (&rr)[(Rec<DIM>::USED + 1) & ~1]) {
-  constexpr int RU = (Rec<DIM>::USED + 1) & ~1;
+template <int DIM, bool CPL, typename T>
+__device__ __forceinline__ void load_rec(const double* __restrict__ rv, T (&rr)[(Rec<DIM, CPL>::USED + 1) & ~1]) {
+  constexpr int RU = (Rec<DIM, CPL>::USED + 1) & ~1;
 #pragma unroll
   for (int i = 0; i < RU; i += 2) {
     const double2 t = *reinterpret_cast<const double2*>(rv + i);
@@ -351,16 +384,91 @@ __device__ __forceinline__ void grad_n(const T* r, const T dNxi[DIM], T out[DIM]
   }
 }
 
+// Coupling variant (the stress of Eq. 2): adds h (eeq - ebar) G grad N_a to
+// the internal force, -h (G grad N_a) N_b to K^{u ebar} (Eq. 11b as
+// printed) and h [(G grad N_a)(G grad N_b)^T + (eeq - ebar) d^2 eeq] to K^uu,
+// the linearisation of Eq. 2 (G = d eeq / d eps).  The strain variation of
+// u_i at node a is sym(e_i (x) grad N_a), plus f (grad N_a)_i e_z (x) e_z in
+// plane stress (f = ezz_fac), so with t_a = (1 + f) grad N_a:
+//   tr = t_a,i,   d_a : d_b = (delta_ik ga.gb + ga_k gb_i) / 2 + f^2 ga_i gb_k,
+//   q : d_a = (q ga)_i + f q_zz ga_i,
+//   d_a : d^2 eeq : d_b = al (2 c2^2 tr_a tr_b + c3 (d_a : d_b - tr_a tr_b / 3))
+//                         - be (q : d_a)(q : d_b).
+template <int DIM, typename T>
+__device__ __forceinline__ void coupling_terms(const double* r, const double ga[DIM], const double gb[DIM],
+                                               double Nb, const MatParams& mp, bool want_k, bool want_f,
+                                               T blk[DIM + 1][DIM + 1], double fa[DIM + 2]) {
+  using RC = Rec<DIM, true>;
+  double Gga[DIM], Ggb[DIM];
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) {
+    double sa = 0.0, sb = 0.0;
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) {
+      sa += r[RC::GU + sym_idx<DIM>(i, j)] * ga[j];
+      sb += r[RC::GU + sym_idx<DIM>(i, j)] * gb[j];
+    }
+    Gga[i] = sa;
+    Ggb[i] = sb;
+  }
+  const double ec = -r[RC::RE];   // wJ h (eeq - ebar)
+  if (want_f) {
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) fa[i] += ec * Gga[i];
+  }
+  if (!want_k) return;
+  const double cee = r[RC::CEE];  // wJ h
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) blk[i][DIM] -= (T)(cee * Gga[i] * Nb);
+  double qa[DIM], qb[DIM];
+  const double f = DIM == 2 ? mp.ezz_fac : 0.0;
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) {
+    double sa = 0.0, sb = 0.0;
+    if (DIM == 3) {
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) {
+        sa += r[RC::Q + sym_idx<3>(i, j)] * ga[j];
+        sb += r[RC::Q + sym_idx<3>(i, j)] * gb[j];
+      }
+    } else if (DIM == 2) {
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) {
+        sa += r[RC::Q + sym_idx<2>(i, j)] * ga[j];
+        sb += r[RC::Q + sym_idx<2>(i, j)] * gb[j];
+      }
+      sa += f * r[RC::Q + 3] * ga[i];
+      sb += f * r[RC::Q + 3] * gb[i];
+    }
+    qa[i] = sa;
+    qb[i] = sb;
+  }
+  const double al = r[RC::AL], be = r[RC::BE];
+  const double c22 = 2.0 * mp.c2 * mp.c2, c3 = mp.c3, t1 = (1.0 + f) * (1.0 + f);
+  double dab = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) dab += ga[d] * gb[d];
+#pragma unroll
+  for (int i = 0; i < DIM; ++i)
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      const double trtr = t1 * ga[i] * gb[k];
+      const double dd = 0.5 * ((i == k ? dab : 0.0) + ga[k] * gb[i]) + f * f * ga[i] * gb[k];
+      const double hess = al * (c22 * trtr + c3 * (dd - trtr / 3.0)) - be * qa[i] * qb[k];
+      blk[i][k] += (T)(cee * Gga[i] * Ggb[k] + ec * hess);
+    }
+}
+
 // tangent block d f_a / d x_b and (want_f) the internal force on node a of
 // one element at Gauss point g: one read of the record serves both;
 // gradients in FP64, block arithmetic in the working precision T
-template <int DIM, typename T>
+template <int DIM, typename T, bool CPL>
 __device__ __forceinline__ void block_and_force(const double* __restrict__ rv, int g, int la, int lb,
                                                 const MatParams& mp, bool want_k, bool want_f,
                                                 T blk[DIM + 1][DIM + 1], double fa[DIM + 2]) {
-  using RC = Rec<DIM>;
+  using RC = Rec<DIM, CPL>;
   double r[(RC::USED + 1) & ~1];
-  load_rec<DIM, double>(rv, r);
+  load_rec<DIM, CPL, double>(rv, r);
   double Na, Nb, dNa[DIM], dNb[DIM], ga[DIM], gbv[DIM];
   shape_fast<DIM, double>(la, g, Na, dNa);
   shape_fast<DIM, double>(lb, g, Nb, dNb);
@@ -383,7 +491,10 @@ __device__ __forceinline__ void block_and_force(const double* __restrict__ rv, i
     fa[DIM] += r[RC::RE] * Na + r[RC::CG] * ga_geb;
     fa[DIM + 1] += r[RC::FR] * Na;
   }
-  if (!want_k) return;
+  if (!want_k) {
+    if constexpr (CPL) coupling_terms<DIM, T>(r, ga, gbv, Nb, mp, false, want_f, blk, fa);
+    return;
+  }
   const T cuu = (T)r[RC::CUU];
   T ta[DIM], tb[DIM];
 #pragma unroll
@@ -416,6 +527,7 @@ __device__ __forceinline__ void block_and_force(const double* __restrict__ rv, i
     blk[DIM][j] -= tNa * gg;
   }
   blk[DIM][DIM] += (T)r[RC::CEE] * tNa * (T)Nb + (T)r[RC::CGP] * (T)ga_geb * (T)Nb + (T)r[RC::CG] * dab;
+  if constexpr (CPL) coupling_terms<DIM, T>(r, ga, gbv, Nb, mp, want_k, want_f, blk, fa);
 }
 
 // ---------------------------------------------------------------------------
@@ -428,12 +540,12 @@ constexpr int NODE_BLOCK = 256;
 // errors of ~1e-7 of the largest entry in every entry (rigid-body and
 // bending modes of the assembled tangent are no longer annihilated to that
 // level), which on slender meshes is the size of the smallest eigenvalues.
-template <int DIM, typename T> struct NodeLds {
+template <int DIM, typename T, bool CPL> struct NodeLds {
   using E = Elem<DIM>;
   static constexpr int NEN = E::NEN, NGP = E::NGP, ND = E::ND, NB = ND * ND;
   static constexpr int L = NEN * NEN;                 // lanes per node
   static constexpr int NPB = NODE_BLOCK / L;          // nodes per workgroup
-  static constexpr int RS = Rec<DIM>::STRIDE;
+  static constexpr int RS = Rec<DIM, CPL>::STRIDE;
   static constexpr int GS = RS + 2;                   // per Gauss point (even: 16-byte aligned)
   static constexpr int KS = NGP * GS + 2;             // per element: spreads a node's elements over LDS banks
   static constexpr int REC_D = NPB * NEN * KS;        // phase 1: records, doubles
@@ -444,7 +556,7 @@ template <int DIM, typename T> struct NodeLds {
   static constexpr int SMEM_D = REC_D > P2_D ? REC_D : P2_D;
 };
 
-template <int DIM, typename T, bool WANT_K>
+template <int DIM, typename T, bool WANT_K, bool CPL>
 __device__ __forceinline__ void node_block(int64_t blk, const NodeArgs& A, const MatParams& mp) {
   const int64_t n_nodes = A.n_nodes;
   const int32_t* __restrict__ n2e_ptr = A.n2e_ptr;
@@ -459,8 +571,8 @@ __device__ __forceinline__ void node_block(int64_t blk, const NodeArgs& A, const
   double* __restrict__ R = A.R;
   double* __restrict__ partials = A.partials;
   using E = Elem<DIM>;
-  using RC = Rec<DIM>;
-  using LD = NodeLds<DIM, T>;
+  using RC = Rec<DIM, CPL>;
+  using LD = NodeLds<DIM, T, CPL>;
   constexpr int NEN = E::NEN, ND = E::ND, NB = ND * ND, NGP = E::NGP;
   constexpr int L = LD::L, NPB = LD::NPB, RS = LD::RS, GS = LD::GS, KS = LD::KS;
   constexpr int FPL = RS / NEN;                // record doubles each lane stages per Gauss point
@@ -535,7 +647,8 @@ __device__ __forceinline__ void node_block(int64_t blk, const NodeArgs& A, const
     if (act) {
       const bool wf = (b == 0);
 #pragma unroll 1
-      for (int g = 0; g < NGP; ++g) block_and_force<DIM, double>(srec + g * GS, g, la, b, mp, WANT_K, wf, blk, f);
+      for (int g = 0; g < NGP; ++g)
+        block_and_force<DIM, double, CPL>(srec + g * GS, g, la, b, mp, WANT_K, wf, blk, f);
     }
     __syncthreads();
     // phase 2: blocks to LDS, position -> local node table
@@ -629,16 +742,16 @@ __device__ __forceinline__ void node_block(int64_t blk, const NodeArgs& A, const
   }
 }
 
-template <int DIM, typename T, bool WANT_K>
+template <int DIM, typename T, bool WANT_K, bool CPL>
 __global__ void __launch_bounds__(NODE_BLOCK) node_kernel(NodeArgs A, MatParams mp) {
-  node_block<DIM, T, WANT_K>(blockIdx.x, A, mp);
+  node_block<DIM, T, WANT_K, CPL>(blockIdx.x, A, mp);
 }
 
 template <int DIM, typename T, bool WANT_K>
 __global__ void __launch_bounds__(NODE_BLOCK) node_fused_kernel(const SlotDesc* __restrict__ slots,
                                                                 int nslots) {
   const int s = find_slot(slots, nslots, blockIdx.x, true);
-  node_block<DIM, T, WANT_K>((int64_t)blockIdx.x - slots[s].node_block0, slots[s].node, slots[s].mp);
+  node_block<DIM, T, WANT_K, false>((int64_t)blockIdx.x - slots[s].node_block0, slots[s].node, slots[s].mp);
 }
 
 // fixed-order two-stage sums: stage one sums contiguous chunks of the
@@ -687,12 +800,12 @@ __global__ void damage_kernel(int64_t n, const double* __restrict__ kappa, MatPa
 }
 
 // element blocks for parity checks: one thread per (element, a, b)
-template <int DIM>
+template <int DIM, bool CPL>
 __global__ void element_blocks_kernel(int64_t e0, int64_t e1, const double* __restrict__ rec,
                                       MatParams mp, double* __restrict__ Ke,
                                       double* __restrict__ fe) {
   using E = Elem<DIM>;
-  using RC = Rec<DIM>;
+  using RC = Rec<DIM, CPL>;
   constexpr int NEN = E::NEN, ND = E::ND, NL = NEN * ND;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t ne = e1 - e0;
@@ -709,8 +822,8 @@ __global__ void element_blocks_kernel(int64_t e0, int64_t e1, const double* __re
 #pragma unroll
   for (int i = 0; i < DIM + 2; ++i) f[i] = 0.0;
   for (int g = 0; g < E::NGP; ++g)
-    block_and_force<DIM, double>(rec + (e * E::NGP + g) * RC::STRIDE, g, la, lb, mp, Ke != nullptr,
-                                 lb == 0, blk, f);
+    block_and_force<DIM, double, CPL>(rec + (e * E::NGP + g) * RC::STRIDE, g, la, lb, mp, Ke != nullptr,
+                                      lb == 0, blk, f);
   if (Ke) {
     double* out = Ke + el * NL * NL;
 #pragma unroll
@@ -773,6 +886,8 @@ MatParams make_params(const lgdm_material& m, int dim) {
   p.c3 = 12.0 * m.k / ((1.0 + m.nu) * (1.0 + m.nu));
   p.thick = dim < 3 ? m.thickness : 1.0;
   p.g_den = 1.0 - std::exp(-m.eta);
+  p.coupling = m.coupling;
+  p.sq_guard = 1e-6 * m.kappa0;
   return p;
 }
 
@@ -798,10 +913,19 @@ hipError_t launch_gp_kernel(lgdm_ctx* c, const MatParams& mp) {
   const int64_t grid = gp_kernel_blocks(c);
   if (grid == 0) return hipSuccess;
   const GpArgs A = gp_args(c);
+  const bool cpl = mp.coupling != 0;
   switch (c->dim) {
-    case 1: gp_kernel<1><<<grid, 256, 0, c->stream>>>(A, mp); break;
-    case 2: gp_kernel<2><<<grid, 256, 0, c->stream>>>(A, mp); break;
-    default: gp_kernel<3><<<grid, 256, 0, c->stream>>>(A, mp);
+    case 1:
+      if (cpl) gp_kernel<1, true><<<grid, 256, 0, c->stream>>>(A, mp);
+      else gp_kernel<1, false><<<grid, 256, 0, c->stream>>>(A, mp);
+      break;
+    case 2:
+      if (cpl) gp_kernel<2, true><<<grid, 256, 0, c->stream>>>(A, mp);
+      else gp_kernel<2, false><<<grid, 256, 0, c->stream>>>(A, mp);
+      break;
+    default:
+      if (cpl) gp_kernel<3, true><<<grid, 256, 0, c->stream>>>(A, mp);
+      else gp_kernel<3, false><<<grid, 256, 0, c->stream>>>(A, mp);
   }
   return hipGetLastError();
 }
@@ -811,8 +935,13 @@ static void node_launch(lgdm_ctx* c, const MatParams& mp, bool want_k) {
   const int64_t grid = node_kernel_blocks(c);
   if (grid == 0) return;
   const NodeArgs A = node_args(c);
-  if (want_k) node_kernel<DIM, T, true><<<grid, NODE_BLOCK, 0, c->stream>>>(A, mp);
-  else node_kernel<DIM, T, false><<<grid, NODE_BLOCK, 0, c->stream>>>(A, mp);
+  if (mp.coupling) {
+    if (want_k) node_kernel<DIM, T, true, true><<<grid, NODE_BLOCK, 0, c->stream>>>(A, mp);
+    else node_kernel<DIM, T, false, true><<<grid, NODE_BLOCK, 0, c->stream>>>(A, mp);
+  } else {
+    if (want_k) node_kernel<DIM, T, true, false><<<grid, NODE_BLOCK, 0, c->stream>>>(A, mp);
+    else node_kernel<DIM, T, false, false><<<grid, NODE_BLOCK, 0, c->stream>>>(A, mp);
+  }
 }
 
 hipError_t launch_node_kernel(lgdm_ctx* c, const MatParams& mp, bool want_k) {
@@ -890,9 +1019,17 @@ hipError_t launch_element_blocks(lgdm_ctx* c, const MatParams& mp, int64_t e0, i
   const int64_t grid = (n + 255) / 256;
   if (grid == 0) return hipSuccess;
   switch (c->dim) {
-    case 1: element_blocks_kernel<1><<<grid, 256, 0, c->stream>>>(e0, e1, c->rec, mp, Ke, fe); break;
-    case 2: element_blocks_kernel<2><<<grid, 256, 0, c->stream>>>(e0, e1, c->rec, mp, Ke, fe); break;
-    default: element_blocks_kernel<3><<<grid, 256, 0, c->stream>>>(e0, e1, c->rec, mp, Ke, fe);
+    case 1:
+      if (mp.coupling) element_blocks_kernel<1, true><<<grid, 256, 0, c->stream>>>(e0, e1, c->rec, mp, Ke, fe);
+      else element_blocks_kernel<1, false><<<grid, 256, 0, c->stream>>>(e0, e1, c->rec, mp, Ke, fe);
+      break;
+    case 2:
+      if (mp.coupling) element_blocks_kernel<2, true><<<grid, 256, 0, c->stream>>>(e0, e1, c->rec, mp, Ke, fe);
+      else element_blocks_kernel<2, false><<<grid, 256, 0, c->stream>>>(e0, e1, c->rec, mp, Ke, fe);
+      break;
+    default:
+      if (mp.coupling) element_blocks_kernel<3, true><<<grid, 256, 0, c->stream>>>(e0, e1, c->rec, mp, Ke, fe);
+      else element_blocks_kernel<3, false><<<grid, 256, 0, c->stream>>>(e0, e1, c->rec, mp, Ke, fe);
   }
   return hipGetLastError();
 }

@@ -22,13 +22,18 @@ struct MatParams {
   double ezz_fac;        // plane stress: eps_zz = ezz_fac (eps_xx + eps_yy); else 0
   double thick;          // thickness (2D) / area (1D); 1 in 3D
   double g_den;          // 1 - exp(-eta)
+  double sq_guard;       // coupling variant: no second derivative of A.3 where sqrt(s) <= this
+  int coupling;          // LGDM_COUPLING_EXECUTED or LGDM_COUPLING_EQ2
 };
 
 // Record layout of one Gauss point written by the Gauss-point kernel and
 // read by the node-row assembly kernel.  Tensor components are stored as
 // symmetric tensor entries (not engineering shears): 2D (xx, yy, xy),
-// 3D (xx, yy, zz, xy, yz, xz).
-template <int DIM> struct Rec {
+// 3D (xx, yy, zz, xy, yz, xz).  The coupling variant (CPL: the stress of
+// Eq. 2) appends d eeq / d eps unscaled, the two coefficients of the second
+// derivative of A.3 and q = ds / deps of its square-root argument s (3D
+// tensor entries; in 2D xx, yy, xy, zz).
+template <int DIM, bool CPL = false> struct Rec {
   static constexpr int NS = DIM == 1 ? 1 : (DIM == 2 ? 3 : 6);
   static constexpr int JINV = 0;                 // J^-1 [DIM*DIM], (J^-1)_{j d}
   static constexpr int CUU = DIM * DIM;          // wJ (1 - D) s_e
@@ -41,10 +46,22 @@ template <int DIM> struct Rec {
   static constexpr int CG = CGP + 1;             // wJ g h c
   static constexpr int RE = CG + 1;              // wJ h (ebar - eeq)
   static constexpr int FR = RE + 1;              // wJ h eeq
-  static constexpr int USED = FR + 1;
-  static constexpr int STRIDE = DIM == 1 ? 12 : (DIM == 2 ? 20 : 32);
+  static constexpr int NQ = DIM == 1 ? 0 : (DIM == 2 ? 4 : 6);
+  static constexpr int GU = FR + 1;              // CPL: d eeq / d eps [NS] (plane stress: chained through eps_zz)
+  static constexpr int AL = GU + NS;             // CPL: 1 / (4 k sqrt(s)), 0 where sqrt(s) <= guard
+  static constexpr int BE = AL + 1;              // CPL: 1 / (8 k s^(3/2)), likewise
+  static constexpr int Q = BE + 1;               // CPL: q = 2 c2^2 I1 1 + c3 dev(eps) [NQ]
+  static constexpr int USED = CPL ? Q + NQ : FR + 1;
+  static constexpr int STRIDE = CPL ? (DIM == 1 ? 16 : (DIM == 2 ? 28 : 48))
+                                    : (DIM == 1 ? 12 : (DIM == 2 ? 20 : 32));
   static_assert(USED <= STRIDE, "record stride");
 };
+
+// doubles per Gauss-point record of a context
+inline int rec_stride(int dim, bool cpl) {
+  if (cpl) return dim == 1 ? Rec<1, true>::STRIDE : (dim == 2 ? Rec<2, true>::STRIDE : Rec<3, true>::STRIDE);
+  return dim == 1 ? Rec<1>::STRIDE : (dim == 2 ? Rec<2>::STRIDE : Rec<3>::STRIDE);
+}
 
 // arguments of the Gauss-point kernel for one problem
 struct GpArgs {
@@ -161,6 +178,7 @@ struct lgdm_ctx {
 
   // assembly outputs (H3-H5)
   double* rec = nullptr;
+  int rec_stride = 0;     // doubles per Gauss-point record in `rec`
   double* vals = nullptr;
   float* vals32 = nullptr;
   double* R = nullptr;

@@ -19,8 +19,10 @@ are measured with HIP events on the library's stream.
 Prints one JSON line.
 """
 import argparse
+import dataclasses
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -63,7 +65,10 @@ class PathRunner:
         while True:
             before = (rep.t_assembly_ms, rep.t_solve_ms, rep.t_update_ms, rep.n_assemblies,
                       rep.krylov_iters, rep.krylov_spmv)
+            t_it = time.perf_counter()
             conv, r = self.ctx.newton_iteration(self.opts, rep)
+            if not conv:
+                acc["step_ms"].append((time.perf_counter() - t_it) * 1e3)
             if self.verbose:
                 log("  inc %d it %d |R_u|/|F_u|=%.3e |R_e|/|F_e|=%.3e krylov=%d spmv=%d restarts=%d "
                     "asm=%.3fms solve=%.1fms" % (
@@ -91,7 +96,7 @@ class PathRunner:
 
 def new_acc():
     return dict(t_asm=0.0, t_sol=0.0, t_upd=0.0, n_asm=0, krylov=0, spmv=0, newton=0, increments=0,
-                last_rel_u=None, last_rel_e=None)
+                last_rel_u=None, last_rel_e=None, step_ms=[])
 
 
 def algorithmic_bytes(prob, nnz, npairs, s_val):
@@ -173,6 +178,9 @@ def run_precision(prob, precision, args, binding):
         "gp_per_s": ng * acc["n_asm"] / wall,
         "ms_per_increment": wall * 1e3 / args.steps,
         "newton_step_ms": wall * 1e3 / max(acc["newton"], 1),
+        "newton_step_ms_median": statistics.median(acc["step_ms"]) if acc["step_ms"] else None,
+        "newton_step_ms_min": min(acc["step_ms"]) if acc["step_ms"] else None,
+        "newton_step_ms_each": [round(v, 2) for v in acc["step_ms"]],
         "newton_iterations": acc["newton"], "assemblies": acc["n_asm"],
         "increments_in_timed_region": acc["increments"], "increments_committed": runner.inc,
         "assembly_gp_per_s_device": ng * acc["n_asm"] / (acc["t_asm"] / 1e3) if acc["t_asm"] > 0 else None,
@@ -378,6 +386,9 @@ def main():
     ap.add_argument("--max-krylov", type=int, default=20000)
     ap.add_argument("--kernel-reps", type=int, default=5)
     ap.add_argument("--serving-seconds", type=float, default=30.0)
+    ap.add_argument("--coupling", type=int, default=0, choices=[0, 1],
+                    help="1: the stress of Eq. 2 with its h term and the consistent tangent (material coupling "
+                         "variant); 0: the executed-code form (default)")
     ap.add_argument("--load-path", type=int, default=0,
                     help="instead of the bench line: run this many increments of the load path (-1: all) in "
                          "mixed precision and FP64 and report the step time per phase (elastic, near the "
@@ -393,6 +404,8 @@ def main():
     import lgdm_workloads as W
     from paper_2301_06503_amd import binding
     prob = W.config(args.config)
+    if args.coupling:
+        prob.material = dataclasses.replace(prob.material, coupling=args.coupling)
     prec = binding.MIXED if args.precision == "mixed" else binding.FP64
     if args.load_path:
         n_inc = prob.n_increments if args.load_path < 0 else min(args.load_path, prob.n_increments)
@@ -449,6 +462,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.config], "name": args.config,
                    "precision": args.precision, "ndof": prob.ndof, "gauss_points": prob.n_elems * prob.ngp,
+                   "coupling": "eq2" if args.coupling else "executed",
                    "tol_newton": 1e-8, "step": "one load increment: Newton iterations to "
                    "||R||/||F|| < 1e-8 per field, then the history commit",
                    "newton_step_ms": main_res["newton_step_ms"],

@@ -124,3 +124,13 @@ def test_batch_rejects_coupling_variant():
     with pytest.raises(binding.LgdmError):
         b.admit(prob)
     b.close()
+
+
+def test_coupling_value_checked():
+    from paper_2301_06503_amd import binding
+    prob = TINY["bar1d_37"]
+    ctx = context(prob)
+    bad = dataclasses.replace(prob.material, coupling=2)
+    with pytest.raises(binding.LgdmError):
+        ctx.set_material(bad)
+    ctx.close()

@@ -241,7 +241,7 @@ def load_path_run(prob, precision, args, binding, n_inc):
         incs.append({"inc": i + 1, "ms": dt * 1e3, "newton": d["newton_iters"], "assemblies": d["n_assemblies"],
                      "krylov": d["krylov_iters"], "t_asm": d["t_assembly_ms"], "t_sol": d["t_solve_ms"],
                      "reaction": d["reaction"], "max_damage": d["max_damage"]})
-        if (i + 1) % 10 == 0:
+        if (i + 1) % 10 == 0 or dt > 5.0:
             log("load path %s: increment %d, %.1f ms, %d Newton, reaction %.4e, max D %.4f" % (
                 "mixed" if precision == binding.MIXED else "fp64", i + 1, dt * 1e3, d["newton_iters"],
                 d["reaction"], d["max_damage"]))

@@ -229,22 +229,40 @@ def load_path_run(prob, precision, args, binding, n_inc):
                                         "amg": binding.PRECOND_AMG}[args.precond])
     incs = []
     stop = None
+    keys = ("newton_iters", "n_assemblies", "krylov_iters", "t_assembly_ms", "t_solve_ms")
+
+    def advance(lam0, lam1, depth):
+        """Solve the load step lam0 -> lam1; a step that fails (the state is
+        restored by the library) is split into two halves, at most
+        `cutback` times.  Returns (status, summed report, sub-steps)."""
+        d = ctx.solve_increment(lam1, opts, raise_on_fail=False)
+        if d["status"] == 0 or depth >= args.cutback:
+            return d["status"], d, 1
+        mid = 0.5 * (lam0 + lam1)
+        st1, d1, n1 = advance(lam0, mid, depth + 1)
+        if st1 != 0:
+            return st1, d1, n1
+        st2, d2, n2 = advance(mid, lam1, depth + 1)
+        for k in keys:
+            d2[k] = d2[k] + d1[k]
+        return st2, d2, n1 + n2
+
     for i in range(n_inc):
         t0 = time.perf_counter()
-        d = ctx.solve_increment((i + 1) / prob.n_increments, opts, raise_on_fail=False)
+        status, d, nsub = advance(i / prob.n_increments, (i + 1) / prob.n_increments, 0)
         dt = time.perf_counter() - t0
-        if d["status"] != 0:
-            stop = {"increment": i + 1, "status": d["status"],
+        if status != 0:
+            stop = {"increment": i + 1, "status": status, "cutbacks": args.cutback,
                     "error": ctx.lib.lgdm_last_error(ctx.h).decode()}
             log("load path stops at increment %d: %s" % (i + 1, stop["error"]))
             break
         incs.append({"inc": i + 1, "ms": dt * 1e3, "newton": d["newton_iters"], "assemblies": d["n_assemblies"],
                      "krylov": d["krylov_iters"], "t_asm": d["t_assembly_ms"], "t_sol": d["t_solve_ms"],
-                     "reaction": d["reaction"], "max_damage": d["max_damage"]})
-        if (i + 1) % 10 == 0 or dt > 5.0:
-            log("load path %s: increment %d, %.1f ms, %d Newton, reaction %.4e, max D %.4f" % (
+                     "reaction": d["reaction"], "max_damage": d["max_damage"], "substeps": nsub})
+        if (i + 1) % 10 == 0 or dt > 5.0 or nsub > 1:
+            log("load path %s: increment %d, %.1f ms, %d Newton, reaction %.4e, max D %.4f, %d sub-steps" % (
                 "mixed" if precision == binding.MIXED else "fp64", i + 1, dt * 1e3, d["newton_iters"],
-                d["reaction"], d["max_damage"]))
+                d["reaction"], d["max_damage"], nsub))
     ctx.close()
     del ctx
     torch.cuda.empty_cache()
@@ -278,7 +296,7 @@ def load_path_run(prob, precision, args, binding, n_inc):
             "peak_reaction": incs[ipk]["reaction"] if incs else None,
             "whole_path": summ(incs), "phases": {k: summ(v) for k, v in phases.items()},
             "per_increment": [[r["inc"], round(r["ms"], 2), r["newton"], r["krylov"], r["reaction"],
-                               round(r["max_damage"], 6)] for r in incs]}
+                               round(r["max_damage"], 6), r["substeps"]] for r in incs]}
 
 
 def cpu_baseline(name, prob, budget_s=20.0):
@@ -389,6 +407,8 @@ def main():
     ap.add_argument("--coupling", type=int, default=0, choices=[0, 1],
                     help="1: the stress of Eq. 2 with its h term and the consistent tangent (material coupling "
                          "variant); 0: the executed-code form (default)")
+    ap.add_argument("--cutback", type=int, default=0,
+                    help="load-path mode: split a load step that fails into halves, at most this many times")
     ap.add_argument("--load-path", type=int, default=0,
                     help="instead of the bench line: run this many increments of the load path (-1: all) in "
                          "mixed precision and FP64 and report the step time per phase (elastic, near the "
@@ -410,7 +430,8 @@ def main():
     if args.load_path:
         n_inc = prob.n_increments if args.load_path < 0 else min(args.load_path, prob.n_increments)
         lp = {"workload": WORKLOADS[args.config], "name": args.config, "increments_requested": n_inc,
-              "columns": ["increment", "ms", "newton", "krylov", "reaction", "max_damage"]}
+              "columns": ["increment", "ms", "newton", "krylov", "reaction", "max_damage", "substeps"],
+              "cutback": args.cutback}
         for label, pr in (("mixed", binding.MIXED), ("fp64", binding.FP64)):
             if label == "fp64" and args.no_fp64_compare:
                 continue

@@ -547,7 +547,14 @@ template <int DIM, typename T, bool CPL> struct NodeLds {
   static constexpr int NPB = NODE_BLOCK / L;          // nodes per workgroup
   static constexpr int RS = Rec<DIM, CPL>::STRIDE;
   static constexpr int GS = RS + 2;                   // per Gauss point (even: 16-byte aligned)
-  static constexpr int KS = NGP * GS + 2;             // per element: spreads a node's elements over LDS banks
+  // rounds of Gauss points staged through LDS: the coupling variant's hex8
+  // records (48 doubles) are staged in two rounds of four points, 52 KB
+  // instead of 103 KB, two workgroups per CU instead of one (9.3 -> 6.1 ms
+  // on the 256x64x32 beam); the default records stay in one round (two
+  // rounds under a 3-wave register bound spill and run 4.7 ms against 3.4)
+  static constexpr int NSTAGE = (CPL && NGP > 4) ? 2 : 1;
+  static constexpr int GPS = NGP / NSTAGE;            // Gauss points per round
+  static constexpr int KS = GPS * GS + 2;             // per element: spreads a node's elements over LDS banks
   static constexpr int REC_D = NPB * NEN * KS;        // phase 1: records, doubles
   static constexpr int BLK_B = NB * NODE_BLOCK * (int)sizeof(double);
   static constexpr int F_B = (DIM + 2) * NODE_BLOCK * 8;
@@ -625,17 +632,6 @@ __device__ __forceinline__ void node_block(int64_t blk, const NodeArgs& A, const
       la = ent & 7;
       p = pos[(e * NEN + la) * NEN + b];
     }
-    // phase 1: stage every Gauss point of the node's elements in one round
-    // (lane (k, b) copies doubles [b*FPL, (b+1)*FPL) of each record of element k)
-    double* srec = smem + (slot * NEN + k) * KS;
-    if (act) {
-      const double* src = rec + e * NGP * RS + b * FPL;
-#pragma unroll
-      for (int g = 0; g < NGP; ++g)
-#pragma unroll
-        for (int q = 0; q < FPL; ++q) srec[g * GS + b * FPL + q] = src[g * RS + q];
-    }
-    __syncthreads();
     double blk[ND][ND];
 #pragma unroll
     for (int i = 0; i < ND; ++i)
@@ -644,13 +640,28 @@ __device__ __forceinline__ void node_block(int64_t blk, const NodeArgs& A, const
     double f[DIM + 2];
 #pragma unroll
     for (int i = 0; i < DIM + 2; ++i) f[i] = 0.0;
-    if (act) {
-      const bool wf = (b == 0);
+    // phase 1, in LD::NSTAGE rounds of LD::GPS Gauss points: lane (k, b)
+    // copies doubles [b*FPL, (b+1)*FPL) of each record of element k, then
+    // every lane sums its block over the round's points (ascending g)
+    double* srec = smem + (slot * NEN + k) * KS;
 #pragma unroll 1
-      for (int g = 0; g < NGP; ++g)
-        block_and_force<DIM, double, CPL>(srec + g * GS, g, la, b, mp, WANT_K, wf, blk, f);
+    for (int h = 0; h < LD::NSTAGE; ++h) {
+      if (act) {
+        const double* src = rec + (e * NGP + h * LD::GPS) * RS + b * FPL;
+#pragma unroll
+        for (int g = 0; g < LD::GPS; ++g)
+#pragma unroll
+          for (int q = 0; q < FPL; ++q) srec[g * GS + b * FPL + q] = src[g * RS + q];
+      }
+      __syncthreads();
+      if (act) {
+        const bool wf = (b == 0);
+#pragma unroll 1
+        for (int g = 0; g < LD::GPS; ++g)
+          block_and_force<DIM, double, CPL>(srec + g * GS, h * LD::GPS + g, la, b, mp, WANT_K, wf, blk, f);
+      }
+      __syncthreads();
     }
-    __syncthreads();
     // phase 2: blocks to LDS, position -> local node table
 #pragma unroll
     for (int q = 0; q < NEN; ++q) s_slot[(slot * NEN + k) * L + b * NEN + q] = -1;

@@ -416,7 +416,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the LGDM hot path here is built and measured on a single "
-              "MI355X; multi-GPU runs are not part of this build (requested --gpus %d)" % args.gpus,
+              "MI355X; multi-GPU runs are not implemented (requested --gpus %d)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
     import torch

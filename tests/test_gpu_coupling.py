@@ -95,12 +95,16 @@ def test_coupled_differs_from_executed_form():
     ctx.close()
 
 
-@pytest.mark.parametrize("name", ["bar1d_37", "sen2d_13x7_ps", "beam3d_10x4x3"])
-def test_coupled_load_path_damage_parity(name):
+@pytest.mark.parametrize("name,precision", [("bar1d_37", 0), ("sen2d_13x7_ps", 0), ("beam3d_10x4x3", 0),
+                                            ("sen2d_13x7_ps", 1), ("beam3d_10x4x3", 1)])
+def test_coupled_load_path_damage_parity(name, precision):
+    """Damage after every increment of the whole path against the oracle:
+    1e-8 in FP64 contexts, 1e-7 in mixed ones (FP32 tangent, FP64 residual,
+    so the converged states differ only by the Newton tolerance)."""
     from paper_2301_06503_amd import binding
-    _print_case(name)
+    _print_case("%s precision %d" % (name, precision))
     prob = _coupled(name, 0.01)
-    ctx = context(prob)
+    ctx = context(prob, precision)
     o = Oracle(prob)
     opts = binding.solver_opts(tol_newton=1e-10, tol_krylov=1e-13, max_krylov=50000)
     worst = 0.0
@@ -113,7 +117,7 @@ def test_coupled_load_path_damage_parity(name):
         worst = max(worst, float(np.abs(ctx.query(2) - ro["D"]).max()))
         assert rg["reaction"] == pytest.approx(ro["reaction"], rel=1e-7, abs=1e-10)
     print("max damage error over the path", worst, "max D", float(ro["D"].max()))
-    assert worst <= 1e-8
+    assert worst <= (1e-8 if precision == 0 else 1e-7)
     ctx.close()
 
 

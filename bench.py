@@ -40,6 +40,8 @@ WORKLOADS = {
     "c1": "2D plane-stress single-edge-notched plate 200x100 Q4 (80,000 Gauss points, 60,903 "
           "dofs), 200 increments to 0.1 mm",
     "c0": "1D bar, 100 line2 elements, 100 increments to 0.02 mm",
+    "c3p": "3D notched beam, three-point bending, 64x16x8 hex8 (8,192 elements, 65,536 Gauss points, "
+           "39,780 dofs), notch E x 0.01, 150 increments to 0.5 mm",
 }
 
 
@@ -70,11 +72,7 @@ class PathRunner:
             if not conv:
                 acc["step_ms"].append((time.perf_counter() - t_it) * 1e3)
             if self.verbose:
-                log("  inc %d it %d |R_u|/|F_u|=%.3e |R_e|/|F_e|=%.3e krylov=%d spmv=%d restarts=%d "
-                    "asm=%.3fms solve=%.1fms" % (
-                        self.inc + 1, it, r.res_u / max(r.ref_u, 1e-300), r.res_e / max(r.ref_e, 1e-300),
-                        r.krylov_iters - before[4], r.krylov_spmv - before[5], r.restarts,
-                        r.t_assembly_ms - before[0], r.t_solve_ms - before[1]))
+                log(newton_line(self.inc + 1, it, r, before))
             acc["t_asm"] += r.t_assembly_ms - before[0]
             acc["t_sol"] += r.t_solve_ms - before[1]
             acc["t_upd"] += r.t_update_ms - before[2]
@@ -92,6 +90,17 @@ class PathRunner:
             acc["newton"] += 1
             if it > self.opts.max_newton:
                 raise RuntimeError("Newton did not converge in increment %d" % (self.inc + 1))
+
+
+def newton_line(inc, it, r, before):
+    """One log line per Newton iteration: residuals of the assembly, then the
+    linear solve that followed it (steps, reached relative residual, status)."""
+    return ("  inc %d it %d |R_u|/|F_u|=%.3e |R_e|/|F_e|=%.3e krylov=%d spmv=%d rel=(%.1e, %.1e) "
+            "status=%d inexact=%d restarts=%d asm=%.3fms solve=%.1fms" % (
+                inc, it, r.res_u / max(r.ref_u, 1e-300), r.res_e / max(r.ref_e, 1e-300),
+                r.krylov_iters - before[4], r.krylov_spmv - before[5], r.krylov_rel_u, r.krylov_rel_e,
+                r.krylov_status, r.inexact_solves, r.restarts, r.t_assembly_ms - before[0],
+                r.t_solve_ms - before[1]))
 
 
 def new_acc():
@@ -212,7 +221,8 @@ def run_precision(prob, precision, args, binding):
 
 def load_path_run(prob, precision, args, binding, n_inc):
     """Whole load path: increments 1..n_inc, each solved to the Newton test
-    inside the library (lgdm_solve_increment) and timed on the host.  Each
+    through the stepwise C ABI (one log line per Newton iteration) and timed
+    on the host.  Each
     increment's reaction force and maximum damage classify it as elastic (no
     damage yet), near the peak (reaction within 2% of the path maximum) or
     post-peak (after the maximum), the three phases the step time is
@@ -226,30 +236,69 @@ def load_path_run(prob, precision, args, binding, n_inc):
                                max_krylov=args.max_krylov, check_every=32, krylov_method=binding.KRYLOV_IDRS,
                                idr_s=args.idr_s, forcing=binding.FORCING_ADAPTIVE,
                                precond={"default": binding.PRECOND_DEFAULT, "bj": binding.PRECOND_BLOCK_JACOBI,
-                                        "amg": binding.PRECOND_AMG}[args.precond])
+                                        "amg": binding.PRECOND_AMG}[args.precond],
+                               max_increment_krylov=args.max_increment_krylov,
+                               max_increment_seconds=args.max_increment_seconds)
     incs = []
     stop = None
     keys = ("newton_iters", "n_assemblies", "krylov_iters", "t_assembly_ms", "t_solve_ms")
+    label = "mixed" if precision == binding.MIXED else "fp64"
 
-    def advance(lam0, lam1, depth):
+    def solve_step(lam, inc):
+        """One load step through the stepwise C ABI (the same sequence as
+        lgdm_solve_increment, with the same work bounds in the options),
+        printing one line per Newton iteration."""
+        rep = binding.IncrementReport()
+        ctx.begin_increment(lam)
+        it = 0
+        status = 0
+        while True:
+            before = (rep.t_assembly_ms, rep.t_solve_ms, rep.t_update_ms, rep.n_assemblies,
+                      rep.krylov_iters, rep.krylov_spmv)
+            try:
+                conv, r = ctx.newton_iteration(opts, rep)
+            except binding.LgdmError as e:
+                status = e.status
+                log("  %s inc %d it %d: %s" % (label, inc, it, e))
+                break
+            log(label + newton_line(inc, it, r, before))
+            if conv:
+                break
+            it += 1
+            if it > opts.max_newton:
+                status = binding.LGDM_ERR_NOT_CONVERGED
+                log("  %s inc %d: no convergence within %d Newton iterations" % (label, inc, opts.max_newton))
+                break
+        d = rep.as_dict()
+        if status == 0:
+            ctx.commit_increment()
+            d["max_damage"] = float(ctx.query(binding.FIELD_DAMAGE).max())
+            d["converged"] = 1
+        else:
+            ctx.abort_increment()
+        d["status"] = status
+        return d
+
+    def advance(lam0, lam1, depth, inc):
         """Solve the load step lam0 -> lam1; a step that fails (the state is
-        restored by the library) is split into two halves, at most
-        `cutback` times.  Returns (status, summed report, sub-steps)."""
-        d = ctx.solve_increment(lam1, opts, raise_on_fail=False)
+        restored) is split into two halves, at most `cutback` times.
+        Returns (status, summed report, sub-steps)."""
+        d = solve_step(lam1, inc)
         if d["status"] == 0 or depth >= args.cutback:
             return d["status"], d, 1
         mid = 0.5 * (lam0 + lam1)
-        st1, d1, n1 = advance(lam0, mid, depth + 1)
+        log("  %s inc %d: load step split (depth %d)" % (label, inc, depth + 1))
+        st1, d1, n1 = advance(lam0, mid, depth + 1, inc)
         if st1 != 0:
             return st1, d1, n1
-        st2, d2, n2 = advance(mid, lam1, depth + 1)
+        st2, d2, n2 = advance(mid, lam1, depth + 1, inc)
         for k in keys:
             d2[k] = d2[k] + d1[k]
         return st2, d2, n1 + n2
 
     for i in range(n_inc):
         t0 = time.perf_counter()
-        status, d, nsub = advance(i / prob.n_increments, (i + 1) / prob.n_increments, 0)
+        status, d, nsub = advance(i / prob.n_increments, (i + 1) / prob.n_increments, 0, i + 1)
         dt = time.perf_counter() - t0
         if status != 0:
             stop = {"increment": i + 1, "status": status, "cutbacks": args.cutback,
@@ -259,10 +308,9 @@ def load_path_run(prob, precision, args, binding, n_inc):
         incs.append({"inc": i + 1, "ms": dt * 1e3, "newton": d["newton_iters"], "assemblies": d["n_assemblies"],
                      "krylov": d["krylov_iters"], "t_asm": d["t_assembly_ms"], "t_sol": d["t_solve_ms"],
                      "reaction": d["reaction"], "max_damage": d["max_damage"], "substeps": nsub})
-        if (i + 1) % 10 == 0 or dt > 5.0 or nsub > 1:
-            log("load path %s: increment %d, %.1f ms, %d Newton, reaction %.4e, max D %.4f, %d sub-steps" % (
-                "mixed" if precision == binding.MIXED else "fp64", i + 1, dt * 1e3, d["newton_iters"],
-                d["reaction"], d["max_damage"], nsub))
+        log("load path %s: increment %d, %.1f ms, %d Newton, %d Krylov, reaction %.4e, max D %.4f, "
+            "%d sub-steps" % (label, i + 1, dt * 1e3, d["newton_iters"], d["krylov_iters"], d["reaction"],
+                              d["max_damage"], nsub))
     ctx.close()
     del ctx
     torch.cuda.empty_cache()
@@ -407,6 +455,10 @@ def main():
     ap.add_argument("--coupling", type=int, default=0, choices=[0, 1],
                     help="1: the stress of Eq. 2 with its h term and the consistent tangent (material coupling "
                          "variant); 0: the executed-code form (default)")
+    ap.add_argument("--max-increment-krylov", type=int, default=0,
+                    help="load-path mode: Krylov iterations one load step may spend before it fails (0: no bound)")
+    ap.add_argument("--max-increment-seconds", type=float, default=300.0,
+                    help="load-path mode: wall time one load step may spend before it fails (0: no bound)")
     ap.add_argument("--cutback", type=int, default=0,
                     help="load-path mode: split a load step that fails into halves, at most this many times")
     ap.add_argument("--load-path", type=int, default=0,

@@ -67,7 +67,11 @@ enum {
   LGDM_FIELD_KAPPA_TRIAL = 3, /* [nGP] kappa at the last assembly (A.2 update)    */
   LGDM_FIELD_DAMAGE_TRIAL = 4,/* [nGP] D at the last assembly                     */
   LGDM_FIELD_RESIDUAL = 5, /* [ndof]  R = -f_int of the last assembly, R_c = 0    */
-  LGDM_FIELD_REACTION = 6  /* [1]     sum of f_int,u over loaded dofs (last asm.) */
+  LGDM_FIELD_REACTION = 6, /* [1]     sum of f_int,u over loaded dofs (last asm.) */
+  LGDM_FIELD_EEQ = 7       /* [nGP]   local equivalent strain eeq (modified von
+                                      Mises, A.3) at the last assembly; after a
+                                      converged increment, that of the committed
+                                      state                                     */
 };
 
 /* Material and numerical parameters (Eq. 1 and Appendix A).
@@ -99,8 +103,10 @@ typedef struct lgdm_material {
 enum { LGDM_COUPLING_EXECUTED = 0, LGDM_COUPLING_EQ2 = 1 };
 
 /* Krylov method of the linear solve of the Newton system (Eq. 11).  Both are
- * right-preconditioned with per-node block-Jacobi and work on the same
- * scaled operator; 0 selects the default, LGDM_KRYLOV_IDRS.
+ * right-preconditioned (see lgdm_solver_opts.precond: aggregation multigrid
+ * by default for IDR(s) on 3D meshes, per-node block-Jacobi otherwise) and
+ * work on the same scaled operator; 0 selects the default, LGDM_KRYLOV_IDRS
+ * with s = 8.
  *  LGDM_KRYLOV_BICGSTAB  BiCGSTAB (van der Vorst 1992): 2 operator
  *                        applications per iteration.
  *  LGDM_KRYLOV_IDRS      IDR(s) (Sonneveld & van Gijzen 2008, biorthogonal
@@ -146,6 +152,22 @@ typedef struct lgdm_solver_opts {
                                      values round up to the next of these, max 8) */
   int32_t forcing;         /* LGDM_FORCING_ADAPTIVE                                 */
   int32_t precond;         /* LGDM_PRECOND_DEFAULT                                  */
+  int32_t reserved;        /* must be 0                                             */
+  int64_t max_increment_krylov;  /* 0 = no bound.  Krylov iterations summed over the
+                                    solves of one increment (lgdm_begin_increment to
+                                    commit / abort): each solve is limited to what is
+                                    left (IDR(s) runs whole cycles of s + 1 steps and
+                                    can pass it by up to s), and once it is spent the
+                                    next Newton
+                                    iteration returns LGDM_ERR_NOT_CONVERGED
+                                    (lgdm_solve_increment then restores the
+                                    committed state)                               */
+  double max_increment_seconds;  /* 0 = no bound.  Host wall time of one increment,
+                                    checked before every solve and at every host
+                                    read of a solve (check_every iterations): a
+                                    solve that runs out returns its best iterate,
+                                    and the next Newton iteration returns
+                                    LGDM_ERR_NOT_CONVERGED as above               */
 } lgdm_solver_opts;
 
 /* Tolerance of the linear solves inside Newton (lgdm_newton_iteration,
@@ -168,7 +190,8 @@ enum { LGDM_FORCING_ADAPTIVE = 0, LGDM_FORCING_FIXED = 1 };
 typedef struct lgdm_increment_report {
   int32_t converged;
   int32_t newton_iters;    /* linear solves performed                              */
-  int64_t krylov_iters;    /* BiCGSTAB iterations, summed over the solves          */
+  int64_t krylov_iters;    /* Krylov iterations (IDR(s) or BiCGSTAB), summed over
+                              the solves                                           */
   double res_u, res_e;     /* ||R_u||, ||R_ebar|| at the last assembly             */
   double ref_u, ref_e;     /* ||f_int,u||, ||int N h eeq|| at the last assembly     */
   double du_norm, de_norm; /* ||delta u||, ||delta ebar|| of the last solve        */
@@ -178,7 +201,7 @@ typedef struct lgdm_increment_report {
   double t_solve_ms;       /* device time in the linear solves                      */
   double t_update_ms;      /* device time in update / norms / commit               */
   int32_t n_assemblies;
-  int32_t restarts;        /* BiCGSTAB restarts after breakdown, summed             */
+  int32_t restarts;        /* Krylov restarts after breakdown, summed               */
   int32_t krylov_status;   /* status of the last linear solve (LGDM_OK, or the
                               NOT_CONVERGED / BREAKDOWN of an inexact correction
                               that Newton accepted)                                */
@@ -258,10 +281,13 @@ lgdm_status lgdm_set_dirichlet(lgdm_ctx* ctx, int64_t n, const int64_t* dofs,
 lgdm_status lgdm_assemble_tangent_residual(lgdm_ctx* ctx, double lambda, lgdm_csr_view* K_out,
                                            double* R_out);
 
-/* Solve the assembled tangent K delta = b with right-preconditioned
- * BiCGSTAB and per-node block-Jacobi (Eq. 11, Algorithm 2 "Solve").
- * b, delta: host or device, [ndof].  delta receives the solution; rep
- * (nullable) receives krylov_iters and restarts.  Needs a prior assembly. */
+/* Solve the assembled tangent K delta = b (Eq. 11, Algorithm 2 "Solve") with
+ * the Krylov method and preconditioner the options select (default: IDR(8),
+ * preconditioned by aggregation multigrid on 3D meshes and by per-node
+ * block-Jacobi otherwise), to tol_krylov per field.  b, delta: host or
+ * device, [ndof].  delta receives the solution; rep (nullable) receives
+ * krylov_iters, krylov_spmv, restarts and the reached relative residuals.
+ * Needs a prior assembly. */
 lgdm_status lgdm_solve_linear(lgdm_ctx* ctx, const double* b, double* delta,
                               const lgdm_solver_opts* o, lgdm_increment_report* rep);
 
@@ -420,6 +446,14 @@ lgdm_status lgdm_batch_create(lgdm_batch** out, int32_t device, void* hip_stream
                               int32_t max_slots, int64_t hbm_budget_bytes);
 lgdm_status lgdm_batch_destroy(lgdm_batch* b);
 const char* lgdm_batch_last_error(const lgdm_batch* b);
+
+/* Route the batch's device allocations (its launch tables and solve
+ * buffers) and those of every request it admits through a caller allocator,
+ * as lgdm_set_allocator does for one context.  Call it while no request is
+ * admitted (else LGDM_ERR_STATE); the batch's buffers are reallocated
+ * through the new allocator.  Both NULL returns to hipMalloc / hipFree. */
+lgdm_status lgdm_batch_set_allocator(lgdm_batch* b, void* (*alloc)(size_t, void*),
+                                     void (*free_fn)(void*, void*), void* user);
 
 /* Upper bound of the device bytes one request of this size holds. */
 lgdm_status lgdm_request_footprint(int32_t dim, int64_t n_nodes, int64_t n_elems, int32_t precision,

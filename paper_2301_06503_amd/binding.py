@@ -20,7 +20,7 @@ LGDM_OK, LGDM_ERR_INVALID_ARG, LGDM_ERR_OOM, LGDM_ERR_DEVICE = 0, 1, 2, 3
 LGDM_ERR_NOT_CONVERGED, LGDM_ERR_NAN, LGDM_ERR_BREAKDOWN, LGDM_ERR_STATE = 4, 5, 6, 7
 FP64, MIXED = 0, 1
 FIELD_X, FIELD_KAPPA, FIELD_DAMAGE, FIELD_KAPPA_TRIAL, FIELD_DAMAGE_TRIAL = 0, 1, 2, 3, 4
-FIELD_RESIDUAL, FIELD_REACTION = 5, 6
+FIELD_RESIDUAL, FIELD_REACTION, FIELD_EEQ = 5, 6, 7
 
 LGDM_ERR_BUSY = 8
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "OOM", 3: "DEVICE", 4: "NOT_CONVERGED", 5: "NAN",
@@ -42,7 +42,7 @@ EXPORTS = [
     "lgdm_amg_levels", "lgdm_probe_start", "lgdm_probe_stop",
     "lgdm_batch_create", "lgdm_batch_destroy", "lgdm_batch_last_error", "lgdm_request_footprint",
     "lgdm_batch_admit", "lgdm_batch_tick", "lgdm_batch_slot_info", "lgdm_batch_query",
-    "lgdm_batch_retire", "lgdm_batch_usage",
+    "lgdm_batch_retire", "lgdm_batch_usage", "lgdm_batch_set_allocator",
 ]
 
 
@@ -58,7 +58,8 @@ class SolverOpts(ctypes.Structure):
                 ("tol_newton", ctypes.c_double), ("tol_krylov", ctypes.c_double),
                 ("check_every", ctypes.c_int32), ("max_restarts", ctypes.c_int32),
                 ("krylov_method", ctypes.c_int32), ("idr_s", ctypes.c_int32),
-                ("forcing", ctypes.c_int32), ("precond", ctypes.c_int32)]
+                ("forcing", ctypes.c_int32), ("precond", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("max_increment_krylov", ctypes.c_int64), ("max_increment_seconds", ctypes.c_double)]
 
 
 class IncrementReport(ctypes.Structure):
@@ -162,6 +163,7 @@ def load_library(path: str = LIB_PATH):
         "lgdm_batch_query": [P, I32, I32, P, I64],
         "lgdm_batch_retire": [P, I32],
         "lgdm_batch_usage": [P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I32)],
+        "lgdm_batch_set_allocator": [P, _ALLOC_T, _FREE_T, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -443,7 +445,7 @@ class Batch:
     """Continuous batching of requests on one device (lgdm_batch_* of the C ABI)."""
 
     def __init__(self, device: int = 0, precision: int = MIXED, max_slots: int = 64,
-                 hbm_budget_bytes: int = 0, stream=None):
+                 hbm_budget_bytes: int = 0, stream=None, torch_allocator=True):
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -458,6 +460,22 @@ class Batch:
         self.h = h
         self.precision = precision
         self._keep = {}
+        self._cb = None
+        if torch_allocator:
+            dev = device
+            strm = stream
+
+            def _alloc(n, user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(n), dev, strm)
+                except Exception:
+                    return None
+
+            def _free(p, user):
+                torch.cuda.caching_allocator_delete(p)
+
+            self._cb = (_ALLOC_T(_alloc), _FREE_T(_free))
+            self._check(self.lib.lgdm_batch_set_allocator(self.h, self._cb[0], self._cb[1], None))
 
     def _check(self, st, ok=(LGDM_OK,)):
         if st not in ok:

@@ -54,6 +54,11 @@ struct lgdm_batch {
   std::unique_ptr<BatchRun> run;  // requests whose linear solve is in progress (IDR(s))
   int run_s = 0, run_nd = 0;      // the run's shadow-space dimension and unknowns per node
   std::string err;
+  // device allocator of the batch and of every request's context (null:
+  // hipMalloc / hipFree)
+  void* (*alloc_fn)(size_t, void*) = nullptr;
+  void (*free_fn)(void*, void*) = nullptr;
+  void* alloc_user = nullptr;
 };
 
 namespace {
@@ -76,6 +81,22 @@ bool converged(const lgdm_ctx* c, double tol) {
          std::sqrt(c->last_norms[1]) <= tol * std::max(std::sqrt(c->last_norms[3]), tiny);
 }
 
+
+void* batch_dalloc(lgdm_batch* b, size_t bytes) {
+  void* p = nullptr;
+  if (b->alloc_fn) return b->alloc_fn(bytes, b->alloc_user);
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void batch_dfree(lgdm_batch* b, void* p) {
+  if (!p) return;
+  if (b->free_fn) b->free_fn(p, b->alloc_user);
+  else (void)hipFree(p);
+}
 
 void release(lgdm_batch* b, Slot& s) {
   if (s.ctx) {
@@ -121,7 +142,7 @@ lgdm_status lgdm_request_footprint(int32_t dim, int64_t n_nodes, int64_t n_elems
   s += n_elems * nen * nen;                                     // positions
   s += (ndof + 1) * 4 + nnz * 4 + nnz * sval;                   // CSR
   s += ndof * 8 * (4 + KV_VECS) + ndof;                         // state, Krylov vectors, flags
-  s += ng * 8 * 4 + ng * rs * 8;                                // Gauss-point state, records
+  s += ng * 8 * 5 + ng * rs * 8;                                // Gauss-point state, records
   s += n_nodes * nd * nd * sval;                                // block-Jacobi
   s += ((int64_t)KPART_BLOCKS * KPART_PER_BLOCK + 1024 * 6 + KSCAL_DOUBLES + 64) * 8;  // partials, scalars
   s += ((n_nodes + 3) / 4 + 1) * 6 * 8;
@@ -151,7 +172,7 @@ lgdm_status lgdm_batch_create(lgdm_batch** out, int32_t device, void* hip_stream
   }
   b->budget = hbm_budget_bytes;
   if (hipHostMalloc((void**)&b->desc_host, max_slots * sizeof(SlotDesc), hipHostMallocDefault) != hipSuccess ||
-      hipMalloc((void**)&b->desc_dev, max_slots * sizeof(SlotDesc)) != hipSuccess ||
+      !(b->desc_dev = (SlotDesc*)batch_dalloc(b, max_slots * sizeof(SlotDesc))) ||
       hipEventCreate(&b->ev0) != hipSuccess || hipEventCreate(&b->ev1) != hipSuccess ||
       batch_solve_alloc(b->bsolve, max_slots) != hipSuccess) {
     lgdm_batch_destroy(b);
@@ -167,7 +188,7 @@ lgdm_status lgdm_batch_destroy(lgdm_batch* b) {
   for (auto& s : b->slots)
     if (s.ctx || s.stream) release(b, s);
   if (b->desc_host) (void)hipHostFree(b->desc_host);
-  if (b->desc_dev) (void)hipFree(b->desc_dev);
+  batch_dfree(b, b->desc_dev);
   if (b->ev0) (void)hipEventDestroy(b->ev0);
   if (b->ev1) (void)hipEventDestroy(b->ev1);
   b->run.reset();
@@ -177,6 +198,32 @@ lgdm_status lgdm_batch_destroy(lgdm_batch* b) {
 }
 
 const char* lgdm_batch_last_error(const lgdm_batch* b) { return b ? b->err.c_str() : "null batch"; }
+
+lgdm_status lgdm_batch_set_allocator(lgdm_batch* b, void* (*alloc)(size_t, void*), void (*free_fn)(void*, void*),
+                                     void* user) {
+  if (!b) return LGDM_ERR_INVALID_ARG;
+  if ((alloc == nullptr) != (free_fn == nullptr))
+    return bfail(b, LGDM_ERR_INVALID_ARG, "alloc and free must both be given or both be NULL");
+  for (auto& s : b->slots)
+    if (s.state != LGDM_SLOT_FREE) return bfail(b, LGDM_ERR_STATE, "set the allocator before admitting requests");
+  BHIP(b, hipSetDevice(b->device), "set device");
+  BHIP(b, hipStreamSynchronize(b->stream), "sync");
+  // the batch's own device buffers move to the new allocator
+  b->run.reset();
+  batch_dfree(b, b->desc_dev);
+  b->desc_dev = nullptr;
+  batch_solve_free(b->bsolve);
+  b->alloc_fn = alloc;
+  b->free_fn = free_fn;
+  b->alloc_user = user;
+  b->bsolve.alloc_fn = alloc;
+  b->bsolve.free_fn = free_fn;
+  b->bsolve.alloc_user = user;
+  b->desc_dev = (SlotDesc*)batch_dalloc(b, b->slots.size() * sizeof(SlotDesc));
+  if (!b->desc_dev || batch_solve_alloc(b->bsolve, (int)b->slots.size()) != hipSuccess)
+    return bfail(b, LGDM_ERR_OOM, "device allocation failed (batch buffers)");
+  return LGDM_OK;
+}
 
 lgdm_status lgdm_batch_admit(lgdm_batch* b, const lgdm_request* r, int32_t* slot_out) {
   if (!b || !r || !slot_out) return bfail(b, LGDM_ERR_INVALID_ARG, "NULL argument");
@@ -204,6 +251,7 @@ lgdm_status lgdm_batch_admit(lgdm_batch* b, const lgdm_request* r, int32_t* slot
   BHIP(b, hipSetDevice(b->device), "set device");
   BHIP(b, hipStreamCreate(&s.stream), "slot stream");
   lgdm_status st = lgdm_create(&s.ctx, b->device, s.stream, b->precision);
+  if (st == LGDM_OK && b->alloc_fn) st = lgdm_set_allocator(s.ctx, b->alloc_fn, b->free_fn, b->alloc_user);
   if (st == LGDM_OK) st = lgdm_upload_mesh(s.ctx, r->dim, r->elem_type, r->n_nodes, r->coords, r->n_elems,
                                            r->conn, r->e_scale);
   if (st == LGDM_OK) st = lgdm_set_material(s.ctx, &r->material);

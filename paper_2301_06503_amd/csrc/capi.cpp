@@ -138,7 +138,7 @@ void free_mesh(lgdm_ctx* c) {
   c->n2e_ptr = c->n2e = c->nbr_ptr = c->nbr = c->dpos = nullptr;
   c->pos = nullptr; c->row_ptr = c->col_idx = nullptr;
   c->dof_flags = nullptr; c->bc_dofs = nullptr; c->bc_vals = nullptr; c->nbc = 0;
-  c->x = c->x_save = c->kappa_n = c->D_n = c->kappa_t = c->D_t = nullptr;
+  c->x = c->x_save = c->kappa_n = c->D_n = c->kappa_t = c->D_t = c->eeq_t = nullptr;
   c->rec = c->vals = c->R = c->partials = c->norms_dev = c->red2 = nullptr;
   c->vals32 = nullptr;
   c->kv = nullptr; c->minv = nullptr; c->minv32 = nullptr;
@@ -214,12 +214,16 @@ lgdm_status linear_solve(lgdm_ctx* c, const double* b_dev, double* x_dev, const 
   }
   KrylovResult kr{};
   HIPCHECK(c, krylov_solve(c, b_dev, x_dev, o, tol_u, tol_e, kr), "Krylov solve");
-  if (o.precond == LGDM_PRECOND_AMG && kr.status != LGDM_OK && !kr.improved) {
+  const bool out_of_time = c->solve_deadline > 0.0 && host_seconds() > c->solve_deadline;
+  if (o.precond == LGDM_PRECOND_AMG && kr.status != LGDM_OK && !kr.improved && kr.iters < o.max_krylov &&
+      !out_of_time) {
     // the smoother can amplify where block-Jacobi sees a far-spread spectrum
     // (strongly indefinite tangents): a multigrid solve that made no
-    // progress is repeated with block-Jacobi alone
+    // progress is repeated with block-Jacobi alone, within the iterations
+    // left to this solve
     lgdm_solver_opts bj = o;
     bj.precond = LGDM_PRECOND_BLOCK_JACOBI;
+    bj.max_krylov = (int32_t)(o.max_krylov - kr.iters);
     const int64_t it0 = kr.iters, sp0 = kr.spmv;
     const int rs0 = kr.restarts;
     HIPCHECK(c, krylov_solve(c, b_dev, x_dev, bj, tol_u, tol_e, kr), "Krylov solve");
@@ -229,6 +233,7 @@ lgdm_status linear_solve(lgdm_ctx* c, const double* b_dev, double* x_dev, const 
     if (rep) rep->precond_fallbacks += 1;
   }
   c->last_solve_improved = kr.status == LGDM_OK || kr.improved;
+  c->inc_krylov += kr.iters;
   if (rep) {
     rep->krylov_iters += kr.iters;
     rep->restarts += kr.restarts;
@@ -375,6 +380,7 @@ lgdm_status lgdm_upload_mesh(lgdm_ctx* c, int32_t dim, int32_t elem_type, int64_
   c->D_n = (double*)dalloc(c, ng * sizeof(double));
   c->kappa_t = (double*)dalloc(c, ng * sizeof(double));
   c->D_t = (double*)dalloc(c, ng * sizeof(double));
+  c->eeq_t = (double*)dalloc(c, ng * sizeof(double));
   const int rs = rec_stride(dim, c->has_mat && c->mat.coupling == LGDM_COUPLING_EQ2);
   c->rec = (double*)dalloc(c, ng * rs * sizeof(double));
   c->rec_stride = rs;
@@ -392,7 +398,7 @@ lgdm_status lgdm_upload_mesh(lgdm_ctx* c, int32_t dim, int32_t elem_type, int64_
   c->kpart = (double*)dalloc(c, c->n_kpart * sizeof(double));
   c->kscal = (double*)dalloc(c, KSCAL_DOUBLES * sizeof(double));
   c->kcount = (unsigned*)dalloc(c, 16 * sizeof(unsigned));
-  if (!c->x || !c->x_save || !c->R || !c->delta || !c->kappa_n || !c->D_n || !c->kappa_t || !c->D_t ||
+  if (!c->x || !c->x_save || !c->R || !c->delta || !c->kappa_n || !c->D_n || !c->kappa_t || !c->D_t || !c->eeq_t ||
       !c->rec || (!c->vals && !c->vals32) || !c->partials || !c->norms_dev || !c->red2 || !c->dof_flags ||
       !c->kv || (!c->minv && !c->minv32) || !c->kpart || !c->kscal || !c->kcount) {
     free_mesh(c);
@@ -412,6 +418,7 @@ lgdm_status lgdm_upload_mesh(lgdm_ctx* c, int32_t dim, int32_t elem_type, int64_
   HIPCHECK(c, zero(c, c->D_n, ng * sizeof(double)), "zero");
   HIPCHECK(c, zero(c, c->kappa_t, ng * sizeof(double)), "zero");
   HIPCHECK(c, zero(c, c->D_t, ng * sizeof(double)), "zero");
+  HIPCHECK(c, zero(c, c->eeq_t, ng * sizeof(double)), "zero");
   HIPCHECK(c, zero(c, c->dof_flags, nd), "zero");
   HIPCHECK(c, zero(c, c->kcount, 16 * sizeof(unsigned)), "zero");
   HIPCHECK(c, hipStreamSynchronize(c->stream), "upload");
@@ -527,6 +534,8 @@ lgdm_status lgdm_begin_increment(lgdm_ctx* c, double lambda) {
   HIPCHECK(c, launch_set_dirichlet(c, lambda), "set Dirichlet values");
   c->in_increment = true;
   c->nw_iter = 0;
+  c->inc_krylov = 0;
+  c->inc_t0 = host_seconds();
   return LGDM_OK;
 }
 
@@ -548,10 +557,31 @@ lgdm_status lgdm_newton_iteration(lgdm_ctx* c, const lgdm_solver_opts* o, int32_
     *converged = 1;
     return LGDM_OK;
   }
+  // work bound of the increment: the Krylov iterations and the wall time
+  // left to it
+  lgdm_solver_opts ob = op;
+  if (op.max_increment_krylov > 0) {
+    const int64_t left = op.max_increment_krylov - c->inc_krylov;
+    if (left <= 0)
+      return fail(c, LGDM_ERR_NOT_CONVERGED, "increment work bound reached: " + std::to_string(c->inc_krylov) +
+                                                 " Krylov iterations (max_increment_krylov)");
+    ob.max_krylov = (int32_t)std::min<int64_t>(op.max_krylov, left);
+  }
+  c->solve_deadline = 0.0;
+  if (op.max_increment_seconds > 0) {
+    c->solve_deadline = c->inc_t0 + op.max_increment_seconds;
+    if (host_seconds() > c->solve_deadline) {
+      c->solve_deadline = 0.0;
+      return fail(c, LGDM_ERR_NOT_CONVERGED, "increment work bound reached: wall time above " +
+                                                 std::to_string(op.max_increment_seconds) +
+                                                 " s (max_increment_seconds)");
+    }
+  }
   HIPCHECK(c, hipEventRecord(c->ev[2], c->stream), "event");
   double tol_u = op.tol_krylov, tol_e = op.tol_krylov;
   newton_forcing(c, op, tol_u, tol_e);
-  s = linear_solve(c, c->R, c->delta, op, tol_u, tol_e, rep);
+  s = linear_solve(c, c->R, c->delta, ob, tol_u, tol_e, rep);
+  c->solve_deadline = 0.0;
   HIPCHECK(c, hipEventRecord(c->ev[3], c->stream), "event");
   if (!tolerable_in_newton(s)) return s;
   // a correction no better than none would repeat this iteration unchanged
@@ -674,6 +704,7 @@ lgdm_status lgdm_query_state(lgdm_ctx* c, int32_t field, double* out, int64_t n)
     case LGDM_FIELD_KAPPA_TRIAL: src = c->kappa_t; sz = c->ngauss; break;
     case LGDM_FIELD_DAMAGE_TRIAL: src = c->D_t; sz = c->ngauss; break;
     case LGDM_FIELD_RESIDUAL: src = c->R; sz = c->ndof; break;
+    case LGDM_FIELD_EEQ: src = c->eeq_t; sz = c->ngauss; break;
     case LGDM_FIELD_REACTION:
       if (n != 1) return fail(c, LGDM_ERR_INVALID_ARG, "reaction has size 1");
       HIPCHECK(c, hipMemcpy(out, &c->last_norms[4], sizeof(double), hipMemcpyDefault), "copy reaction");

@@ -328,6 +328,7 @@ __device__ __forceinline__ void gp_point(int64_t gid, const GpArgs& A, const Mat
   for (int f = RC::USED; f < RC::STRIDE; ++f) r[f] = 0.0;
   kappa_t[gid] = kap;
   D_t[gid] = D;
+  A.eeq_t[gid] = eeq;
 }
 
 template <int DIM, bool CPL>
@@ -909,7 +910,8 @@ int64_t node_kernel_blocks(const lgdm_ctx* c) {
 }
 
 GpArgs gp_args(const lgdm_ctx* c) {
-  return GpArgs{c->ngauss, c->coords, c->conn, c->e_scale, c->x, c->kappa_n, c->rec, c->kappa_t, c->D_t};
+  return GpArgs{c->ngauss, c->coords, c->conn, c->e_scale, c->x, c->kappa_n, c->rec, c->kappa_t, c->D_t,
+                c->eeq_t};
 }
 
 NodeArgs node_args(const lgdm_ctx* c) {

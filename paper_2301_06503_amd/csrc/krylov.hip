@@ -1460,8 +1460,11 @@ struct KrylovRunImpl final : KrylovRun {
 
   hipError_t launch() override {
     if (rc.fin) return hipSuccess;
-    S.iterate(xout, every);
-    ran = every;
+    // no further than the solve's iteration limit (IDR(s) runs whole cycles
+    // of s + 1 steps, so it can pass the limit by up to s steps)
+    const int n = (int)std::max<int64_t>(1, std::min<int64_t>(every, (int64_t)o.max_krylov - rc.res.iters));
+    S.iterate(xout, n);
+    ran = n;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return read_scalars();
@@ -1475,8 +1478,14 @@ struct KrylovRunImpl final : KrylovRun {
     if (e != hipSuccess) return e;
     pending_read = false;
     bool save_best = false;
-    const RunControl::Action a = rc.decide(c->kscal_host, o, ran, save_best);
+    RunControl::Action a = rc.decide(c->kscal_host, o, ran, save_best);
     ran = 0;
+    if (!rc.fin && c->solve_deadline > 0.0 && host_seconds() > c->solve_deadline) {
+      // the increment's wall-time bound: stop with the best iterate so far
+      rc.fin = true;
+      rc.res.status = LGDM_ERR_NOT_CONVERGED;
+      a = RunControl::RETURN_BEST;
+    }
     if (save_best) {
       e = hipMemcpyAsync(xbest, xout, c->ndof * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
       if (e != hipSuccess) return e;
@@ -1772,29 +1781,47 @@ std::unique_ptr<BatchRun> make_batch_run(hipStream_t st, int nd, bool mixed, con
   }
 }
 
+// device memory of the batch's solve buffers, through the batch's allocator
+static hipError_t bs_alloc(BatchSolveBuffers& B, void** p, size_t bytes) {
+  if (!B.alloc_fn) return hipMalloc(p, bytes);
+  *p = B.alloc_fn(bytes, B.alloc_user);
+  return *p ? hipSuccess : hipErrorOutOfMemory;
+}
+static void bs_free(BatchSolveBuffers& B, void* p) {
+  if (!p) return;
+  if (B.free_fn) B.free_fn(p, B.alloc_user);
+  else (void)hipFree(p);
+}
+
 hipError_t batch_solve_alloc(BatchSolveBuffers& B, int max_requests) {
   B.max_requests = max_requests;
-  hipError_t e = hipMalloc(&B.table_dev, max_requests * sizeof(KSlot));
+  hipError_t e = bs_alloc(B, &B.table_dev, max_requests * sizeof(KSlot));
   if (e == hipSuccess) e = hipHostMalloc(&B.table_host, max_requests * sizeof(KSlot), hipHostMallocDefault);
-  if (e == hipSuccess) e = hipMalloc((void**)&B.sc_dev, (size_t)max_requests * KSCAL_DOUBLES * sizeof(double));
+  if (e == hipSuccess) e = bs_alloc(B, (void**)&B.sc_dev, (size_t)max_requests * KSCAL_DOUBLES * sizeof(double));
   if (e == hipSuccess)
     e = hipHostMalloc((void**)&B.sc_host, (size_t)max_requests * KSCAL_DOUBLES * sizeof(double),
                       hipHostMallocDefault);
   if (e == hipSuccess) e = hipHostMalloc((void**)&B.one_host, sizeof(double), hipHostMallocDefault);
   if (e == hipSuccess)
-    e = hipMalloc((void**)&B.part, (size_t)max_requests * BATCH_PART_PER_REQUEST * sizeof(double));
+    e = bs_alloc(B, (void**)&B.part, (size_t)max_requests * BATCH_PART_PER_REQUEST * sizeof(double));
   if (e == hipSuccess) *B.one_host = 1.0;
   return e;
 }
 
 void batch_solve_free(BatchSolveBuffers& B) {
-  if (B.table_dev) (void)hipFree(B.table_dev);
+  bs_free(B, B.table_dev);
   if (B.table_host) (void)hipHostFree(B.table_host);
-  if (B.sc_dev) (void)hipFree(B.sc_dev);
+  bs_free(B, B.sc_dev);
   if (B.sc_host) (void)hipHostFree(B.sc_host);
   if (B.one_host) (void)hipHostFree(B.one_host);
-  if (B.part) (void)hipFree(B.part);
+  bs_free(B, B.part);
+  auto af = B.alloc_fn;
+  auto ff = B.free_fn;
+  void* au = B.alloc_user;
   B = BatchSolveBuffers{};
+  B.alloc_fn = af;
+  B.free_fn = ff;
+  B.alloc_user = au;
 }
 
 hipError_t krylov_solve(lgdm_ctx* c, const double* b, double* xout, const lgdm_solver_opts& o,

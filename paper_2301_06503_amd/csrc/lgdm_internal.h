@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cstdint>
 #include <memory>
 #include <string>
@@ -74,6 +75,7 @@ struct GpArgs {
   double* rec;
   double* kappa_t;
   double* D_t;
+  double* eeq_t;       // [ngauss] local equivalent strain of A.3 at this assembly
 };
 
 // arguments of the node-row assembly kernel for one problem
@@ -204,12 +206,21 @@ struct lgdm_ctx {
   bool amg_unavailable = false;     // the mesh has no usable hierarchy (default: block-Jacobi)
   bool last_solve_improved = true;  // the last linear solve returned a better-than-zero correction
   int nw_iter = 0;                  // Newton corrections of the current increment
+  int64_t inc_krylov = 0;           // Krylov iterations spent in the current increment
+  double inc_t0 = 0.0;              // host time the current increment began (lgdm::host_seconds)
+  double solve_deadline = 0.0;      // host time a running solve must stop by (0: none)
+  double* eeq_t = nullptr;          // [ngauss] equivalent strain (A.3) of the last assembly
 
   hipEvent_t ev[8] = {};
   bool events_ready = false;
 };
 
 namespace lgdm {
+
+// monotonic host clock in seconds (work bounds of an increment)
+inline double host_seconds() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
 
 // allocation helpers (capi.cpp)
 void* dalloc(lgdm_ctx* c, size_t bytes);
@@ -264,6 +275,10 @@ lgdm_solver_opts fill_opts(const lgdm_solver_opts* o);  // defaults for zero fie
 // type and precision) as one IDR(s) run: every kernel of a cycle is one
 // launch over all of them.  Buffers are owned by the batch.
 struct BatchSolveBuffers {
+  // device allocator of the batch (null: hipMalloc / hipFree)
+  void* (*alloc_fn)(size_t, void*) = nullptr;
+  void (*free_fn)(void*, void*) = nullptr;
+  void* alloc_user = nullptr;
   void* table_dev = nullptr;    // per-request descriptors
   void* table_host = nullptr;   // pinned
   double* sc_dev = nullptr;     // [max_requests][KSCAL_DOUBLES]

@@ -46,7 +46,7 @@ def test_struct_layouts_match_header():
 #include "lgdm.h"
 int main(void) {
   printf("%zu %zu %zu\n", sizeof(lgdm_material), offsetof(lgdm_material, plane), offsetof(lgdm_material, thickness));
-  printf("%zu %zu %zu %zu\n", sizeof(lgdm_solver_opts), offsetof(lgdm_solver_opts, max_restarts), offsetof(lgdm_solver_opts, idr_s), offsetof(lgdm_solver_opts, precond));
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(lgdm_solver_opts), offsetof(lgdm_solver_opts, max_restarts), offsetof(lgdm_solver_opts, idr_s), offsetof(lgdm_solver_opts, precond), offsetof(lgdm_solver_opts, max_increment_krylov), offsetof(lgdm_solver_opts, max_increment_seconds));
   printf("%zu %zu %zu %zu %zu %zu\n", sizeof(lgdm_increment_report), offsetof(lgdm_increment_report, reaction), offsetof(lgdm_increment_report, restarts), offsetof(lgdm_increment_report, krylov_rel_e), offsetof(lgdm_increment_report, krylov_spmv), offsetof(lgdm_increment_report, precond_fallbacks));
   printf("%zu %zu\n", sizeof(lgdm_csr_view), offsetof(lgdm_csr_view, vals32));
   return 0;
@@ -64,7 +64,8 @@ int main(void) {
                  binding.Material.thickness.offset]
     o = [int(v) for v in lines[1].split()]
     assert o == [ctypes.sizeof(binding.SolverOpts), binding.SolverOpts.max_restarts.offset,
-                 binding.SolverOpts.idr_s.offset, binding.SolverOpts.precond.offset]
+                 binding.SolverOpts.idr_s.offset, binding.SolverOpts.precond.offset,
+                 binding.SolverOpts.max_increment_krylov.offset, binding.SolverOpts.max_increment_seconds.offset]
     r = [int(v) for v in lines[2].split()]
     assert r == [ctypes.sizeof(binding.IncrementReport), binding.IncrementReport.reaction.offset,
                  binding.IncrementReport.restarts.offset, binding.IncrementReport.krylov_rel_e.offset,

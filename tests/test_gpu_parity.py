@@ -57,6 +57,8 @@ def test_injected_state_assembly_parity(name, seed):
     assert max(ferr.values()) <= 1e-12, ferr
     np.testing.assert_allclose(ctx.query(3), st["kappa"].ravel(), rtol=0, atol=1e-12 * prob.material.kappa0)
     np.testing.assert_allclose(ctx.query(4), st["D"].ravel(), rtol=0, atol=1e-12)
+    eeq = st["eeq"].ravel()
+    np.testing.assert_allclose(ctx.query(7), eeq, rtol=0, atol=1e-12 * np.abs(eeq).max())
     rx = ctx.query(6)[0]
     assert rx == pytest.approx(st["reaction"], rel=1e-10, abs=1e-12)
     ctx.close()

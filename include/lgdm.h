@@ -291,6 +291,34 @@ lgdm_status lgdm_assemble_tangent_residual(lgdm_ctx* ctx, double lambda, lgdm_cs
 lgdm_status lgdm_solve_linear(lgdm_ctx* ctx, const double* b, double* delta,
                               const lgdm_solver_opts* o, lgdm_increment_report* rep);
 
+/* For callers that cannot allocate device memory while they run (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same solve as lgdm_solve_linear (same kernels, same preconditioner and
+ * options, bitwise the same delta and report), with no device allocation in
+ * the call.  lgdm_solve_linear allocates a solution buffer on every call;
+ * this variant writes the solution straight into delta, and the solve's
+ * scratch (the per-workgroup partial sums of its reductions and its device
+ * scalars: 257 KiB, independent of the mesh size) lives in one static device
+ * array of LGDM_NOALLOC_SCRATCH_BYTES per GPU, resolved at lgdm_create.
+ *  - b, delta: DEVICE memory of ctx's device, [ndof] doubles each, delta
+ *    aligned to 32 bytes (host pointers, other devices' memory and a
+ *    misaligned delta are rejected with LGDM_ERR_INVALID_ARG).  b is read
+ *    only and may alias delta.
+ *  - The multigrid hierarchy is allocated at a context's first multigrid
+ *    solve.  If the options select multigrid (the 3D default) and the
+ *    hierarchy does not exist yet, the call returns LGDM_ERR_STATE and does
+ *    nothing: run one lgdm_solve_linear / lgdm_solve_increment /
+ *    lgdm_newton_iteration first, or select block-Jacobi.
+ *  - The static array is shared by every call on one GPU and keeps the last
+ *    call's contents (the call clears its device scalars first).  Calls that
+ *    overlap on one GPU (several host threads, or contexts on different
+ *    streams) race on it: the caller serialises them.
+ *  - Errors as lgdm_solve_linear; LGDM_ERR_INVALID_ARG if the solve would
+ *    need more scratch than the static array holds. */
+#define LGDM_NOALLOC_SCRATCH_BYTES (1u << 20)
+lgdm_status lgdm_solve_linear_noalloc(lgdm_ctx* ctx, const double* b, double* delta,
+                                      const lgdm_solver_opts* o, lgdm_increment_report* rep);
+
 /* One load increment of Algorithm 2 with load factor lambda: set the
  * constrained dofs, iterate {assemble, convergence test, solve, update}
  * until the per-field residual test holds, then commit the history variable

@@ -35,7 +35,7 @@ PROBE_IDR_SPMV, PROBE_MG_FINEST = 0, 1
 EXPORTS = [
     "lgdm_create", "lgdm_destroy", "lgdm_last_error", "lgdm_set_allocator", "lgdm_upload_mesh",
     "lgdm_set_material", "lgdm_set_dirichlet", "lgdm_assemble_tangent_residual",
-    "lgdm_solve_linear", "lgdm_solve_increment", "lgdm_begin_increment",
+    "lgdm_solve_linear", "lgdm_solve_linear_noalloc", "lgdm_solve_increment", "lgdm_begin_increment",
     "lgdm_newton_iteration", "lgdm_commit_increment", "lgdm_abort_increment", "lgdm_get_csr",
     "lgdm_get_connectivity", "lgdm_get_sizes", "lgdm_query_state", "lgdm_set_state",
     "lgdm_debug_element_blocks", "lgdm_kernel_times", "lgdm_footprint", "lgdm_amg_aggregate",
@@ -135,6 +135,7 @@ def load_library(path: str = LIB_PATH):
         "lgdm_set_dirichlet": [P, I64, P, P],
         "lgdm_assemble_tangent_residual": [P, D, ctypes.POINTER(CsrView), P],
         "lgdm_solve_linear": [P, P, P, ctypes.POINTER(SolverOpts), ctypes.POINTER(IncrementReport)],
+        "lgdm_solve_linear_noalloc": [P, P, P, ctypes.POINTER(SolverOpts), ctypes.POINTER(IncrementReport)],
         "lgdm_solve_increment": [P, D, ctypes.POINTER(SolverOpts), ctypes.POINTER(IncrementReport)],
         "lgdm_begin_increment": [P, D],
         "lgdm_newton_iteration": [P, ctypes.POINTER(SolverOpts), ctypes.POINTER(I32),
@@ -320,6 +321,15 @@ class Context:
         self._check(self.lib.lgdm_solve_linear(self.h, self._ptr(b), self._ptr(x), ctypes.byref(o),
                                                ctypes.byref(rep)))
         return x, rep.as_dict()
+
+    def solve_linear_noalloc(self, b, delta, opts: Optional[SolverOpts] = None):
+        """lgdm_solve_linear_noalloc: b, delta are device tensors of ndof doubles;
+        delta receives the solution.  Returns the report."""
+        rep = IncrementReport()
+        o = opts or SolverOpts()
+        self._check(self.lib.lgdm_solve_linear_noalloc(self.h, self._ptr(b), self._ptr(delta),
+                                                       ctypes.byref(o), ctypes.byref(rep)))
+        return rep.as_dict()
 
     def solve_increment(self, lam: float, opts: Optional[SolverOpts] = None, raise_on_fail=True):
         rep = IncrementReport()

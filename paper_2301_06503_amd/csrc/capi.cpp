@@ -274,6 +274,11 @@ lgdm_status lgdm_create(lgdm_ctx** out, int32_t device, void* hip_stream, int32_
     return LGDM_ERR_DEVICE;
   }
   if (hipSetDevice(device) != hipSuccess) return LGDM_ERR_DEVICE;
+  // the address of the allocation-free solve's static scratch on this device
+  if (noalloc_init(device) != hipSuccess) {
+    (void)hipGetLastError();
+    return LGDM_ERR_DEVICE;
+  }
   lgdm_ctx* c = new (std::nothrow) lgdm_ctx();
   if (!c) return LGDM_ERR_OOM;
   c->device = device;
@@ -524,6 +529,54 @@ lgdm_status lgdm_solve_linear(lgdm_ctx* c, const double* b, double* delta, const
     if (e != hipSuccess) s = hip_fail(c, e, "copy solution");
   }
   dfree(c, xdev);
+  return s;
+}
+
+lgdm_status lgdm_solve_linear_noalloc(lgdm_ctx* c, const double* b, double* delta, const lgdm_solver_opts* o,
+                                      lgdm_increment_report* rep) {
+  if (!c || !b || !delta) return fail(c, LGDM_ERR_INVALID_ARG, "NULL vector");
+  if (!ready(c) || !c->assembled) return fail(c, LGDM_ERR_STATE, "assemble before solving");
+  for (const void* p : {(const void*)b, (const void*)delta}) {
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, p) != hipSuccess || a.type != hipMemoryTypeDevice || a.device != c->device) {
+      (void)hipGetLastError();
+      return fail(c, LGDM_ERR_INVALID_ARG, "b and delta must be device memory of the context's device");
+    }
+  }
+  if (reinterpret_cast<uintptr_t>(delta) % 32 != 0)
+    return fail(c, LGDM_ERR_INVALID_ARG, "delta must be aligned to 32 bytes (the SpMV reads it in 4-wide vectors)");
+  double* scratch = noalloc_scratch(c->device);
+  if (!scratch) return fail(c, LGDM_ERR_DEVICE, "the static scratch of this device is not resolved");
+  // the solve's scratch: its reduction partials and its device scalars
+  const size_t need = ((size_t)c->n_kpart + KSCAL_DOUBLES) * sizeof(double);
+  if (need > LGDM_NOALLOC_SCRATCH_BYTES)
+    return fail(c, LGDM_ERR_INVALID_ARG, "the solve needs " + std::to_string(need) +
+                                             " bytes of scratch; the static array holds " +
+                                             std::to_string((size_t)LGDM_NOALLOC_SCRATCH_BYTES));
+  const lgdm_solver_opts op = fill_opts(o);
+  const bool amg = (op.precond == LGDM_PRECOND_AMG ||
+                    (op.precond == LGDM_PRECOND_DEFAULT && c->dim == 3 && op.krylov_method == LGDM_KRYLOV_IDRS &&
+                     !c->amg_unavailable));
+  if (amg && !c->amg)
+    return fail(c, LGDM_ERR_STATE, "the multigrid hierarchy is allocated at the context's first multigrid solve; "
+                                   "run one lgdm_solve_linear first or select block-Jacobi");
+  if (rep) std::memset(rep, 0, sizeof(*rep));
+  // b is staged in the context's own right-hand-side buffer, as lgdm_solve_linear does
+  HIPCHECK(c, hipMemcpyAsync(c->delta, b, c->ndof * sizeof(double), hipMemcpyDeviceToDevice, c->stream), "copy b");
+  double* const own_kpart = c->kpart;
+  double* const own_kscal = c->kscal;
+  c->kpart = scratch;
+  c->kscal = scratch + c->n_kpart;
+  // the array keeps the previous call's values: the scalars start at zero
+  hipError_t e = launch_fill(c->kscal, KSCAL_DOUBLES, 0.0, c->stream);
+  lgdm_status s = e == hipSuccess ? linear_solve(c, c->delta, delta, op, op.tol_krylov, op.tol_krylov, rep)
+                                  : hip_fail(c, e, "clear scratch");
+  if (e == hipSuccess) {
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess && s == LGDM_OK) s = hip_fail(c, e, "solve");
+  }
+  c->kpart = own_kpart;
+  c->kscal = own_kscal;
   return s;
 }
 

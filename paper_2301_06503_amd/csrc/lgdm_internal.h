@@ -331,6 +331,11 @@ struct AmgInfo {
 void amg_info(const lgdm_ctx* c, AmgInfo& info);
 hipError_t launch_field_norms(lgdm_ctx* c, const double* v, double* out_dev);  // |v_u|^2, |v_e|^2
 
+// static scratch of the allocation-free linear solve (noalloc.hip)
+hipError_t noalloc_init(int device);       // resolve the scratch address on `device` (current)
+double* noalloc_scratch(int device);       // that address, or null before noalloc_init
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
+
 // around a launch of the kernel `kind` on st (no-ops unless that kind is probed)
 void probe_before(lgdm_ctx* c, int kind, hipStream_t st);
 void probe_after(lgdm_ctx* c, int kind, hipStream_t st);

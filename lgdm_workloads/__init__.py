@@ -13,7 +13,8 @@ Meshes are structured:
   element id = i + nx * (j + ny * k)
   local node order: line2 (x0, x1); quad4 counter-clockwise from the
   (i, j) corner; hex8 bottom face counter-clockwise, then the top face in
-  the same order.
+  the same order.  Mixed-order meshes (line3, quad9) number the nodes of the
+  finer node grid the same way and list each element's vertices first.
 
 The problems stand in for the paper's 1D bar (Sec. 3.1, Fig. 10), 2D
 side-edge-notch (Sec. 3.2) and 3D notched specimen (Sec. 3.3), whose exact
@@ -28,6 +29,10 @@ from typing import Dict, List, Optional
 import numpy as np
 
 LINE2, QUAD4, HEX8 = 1, 2, 3
+# mixed-order elements (Sec. 2.1: quadratic u, linear ebar): the u element's
+# nodes with the ebar element on its vertices
+LINE3, QUAD9 = 4, 5
+MIXED_ORDER = (LINE3, QUAD9)
 PLANE_STRESS, PLANE_STRAIN = 0, 1
 
 
@@ -101,7 +106,21 @@ class Problem:
 
     @property
     def ngp(self) -> int:
+        """Gauss points per element: 2 per direction for equal-order elements,
+        3 per direction for the mixed-order ones."""
+        return (3 if self.elem_type in MIXED_ORDER else 2) ** self.dim
+
+    @property
+    def nen_e(self) -> int:
+        """Nodes of the ebar element: the first 2^dim of each element's list."""
         return 2 ** self.dim
+
+    def ebar_nodes(self) -> np.ndarray:
+        """Sorted ids of the nodes that carry an ebar dof (every node for
+        equal-order elements, the vertices of the mixed-order elements)."""
+        if self.elem_type not in MIXED_ORDER:
+            return np.arange(self.n_nodes, dtype=np.int64)
+        return np.unique(np.asarray(self.conn[:, :self.nen_e], dtype=np.int64))
 
     def bc_dofs(self) -> np.ndarray:
         """Node-interleaved dof numbering: dof = node * (dim + 1) + comp."""
@@ -144,6 +163,32 @@ def mesh_hex8(nx: int, ny: int, nz: int, lx: float, ly: float, lz: float):
     conn = np.stack([n(i, j, k), n(i + 1, j, k), n(i + 1, j + 1, k), n(i, j + 1, k),
                      n(i, j, k + 1), n(i + 1, j, k + 1), n(i + 1, j + 1, k + 1),
                      n(i, j + 1, k + 1)], axis=1)
+    return coords, conn.astype(np.int32)
+
+
+def mesh_line3(nx: int, lx: float):
+    """Quadratic line elements: 2 nx + 1 equally spaced nodes; element e has
+    local nodes (left end, right end, midpoint) = (2e, 2e + 2, 2e + 1)."""
+    coords = np.linspace(0.0, lx, 2 * nx + 1).reshape(-1, 1).astype(np.float64)
+    i = np.arange(nx)
+    conn = np.stack([2 * i, 2 * i + 2, 2 * i + 1], axis=1).astype(np.int32)
+    return coords, conn
+
+
+def mesh_quad9(nx: int, ny: int, lx: float, ly: float):
+    """Nine-node quadrilaterals on a (2 nx + 1) x (2 ny + 1) node grid, node id
+    I + (2 nx + 1) J.  Local order: the corners counter-clockwise from the
+    (i, j) corner, the mid-side nodes of edges 0-1, 1-2, 2-3, 3-0, the centre."""
+    xs = np.linspace(0.0, lx, 2 * nx + 1)
+    ys = np.linspace(0.0, ly, 2 * ny + 1)
+    X, Y = np.meshgrid(xs, ys, indexing="xy")
+    coords = np.stack([X.ravel(), Y.ravel()], axis=1).astype(np.float64)
+    j, i = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    I = 2 * i.ravel(); J = 2 * j.ravel()
+    n = lambda ii, jj: ii + (2 * nx + 1) * jj
+    conn = np.stack([n(I, J), n(I + 2, J), n(I + 2, J + 2), n(I, J + 2),
+                     n(I + 1, J), n(I + 2, J + 1), n(I + 1, J + 2), n(I, J + 1),
+                     n(I + 1, J + 1)], axis=1)
     return coords, conn.astype(np.int32)
 
 
@@ -244,6 +289,43 @@ def beam3d(nx: int = 128, ny: int = 32, nz: int = 16, lx: float = 400.0, ly: flo
                    e_scale, n[order], c[order], v[order], material or base_material(), n_increments)
 
 
+def bar1d_quadratic(nx: int = 100, lx: float = 100.0, u_end: float = 0.02,
+                    weak_elem: Optional[int] = None, weak_factor: float = 0.9,
+                    n_increments: int = 100, material: Optional[Material] = None) -> Problem:
+    """The 1D bar of bar1d with quadratic u / linear ebar elements (Sec. 3.1)."""
+    coords, conn = mesh_line3(nx, lx)
+    e_scale = np.ones(nx)
+    if weak_elem is None:
+        weak_elem = nx // 2
+    if weak_elem >= 0:
+        e_scale[weak_elem] = weak_factor
+    bc_nodes = np.array([0, 2 * nx], dtype=np.int64)
+    return Problem("bar1dq_%d" % nx, 1, LINE3, (nx,), coords, conn, e_scale, bc_nodes,
+                   np.zeros(2, dtype=np.int64), np.array([0.0, u_end]),
+                   material or base_material(), n_increments)
+
+
+def sen2d_quadratic(nx: int = 200, ny: int = 100, lx: float = 200.0, ly: float = 100.0,
+                    notch_len: Optional[int] = None, notch_factor: float = 0.01, u_top: float = 0.1,
+                    n_increments: int = 200, material: Optional[Material] = None) -> Problem:
+    """The notched plate of sen2d with biquadratic u / bilinear ebar elements
+    (Sec. 3.2): same notch band, bottom edge fixed, top edge displaced in y."""
+    coords, conn = mesh_quad9(nx, ny, lx, ly)
+    if notch_len is None:
+        notch_len = nx // 4
+    e_scale = np.ones(nx * ny)
+    e_scale[np.arange(notch_len) + nx * (ny // 2)] = notch_factor
+    nxn = 2 * nx + 1
+    bottom = np.arange(nxn, dtype=np.int64)
+    top = np.arange(nxn, dtype=np.int64) + nxn * (2 * ny)
+    n0, c0, v0 = _bc(bottom, [0, 1], [0.0, 0.0])
+    n1, c1, v1 = _bc(top, [1], [u_top])
+    n = np.concatenate([n0, n1]); c = np.concatenate([c0, c1]); v = np.concatenate([v0, v1])
+    order = np.lexsort((c, n))
+    return Problem("sen2dq_%dx%d" % (nx, ny), 2, QUAD9, (nx, ny), coords, conn, e_scale,
+                   n[order], c[order], v[order], material or base_material(), n_increments)
+
+
 def config(name: str) -> Problem:
     """The named workloads.
 
@@ -252,6 +334,8 @@ def config(name: str) -> Problem:
     c2  3D beam 128 x 32 x 16 hex8, 400 x 100 x 50 mm, 0.5 mm in 150 increments
     c3  3D beam 256 x 64 x 32 hex8 (mixed precision workload)
     c3p 3D beam 64 x 16 x 8 hex8 (parity subsample of c3)
+    c0q the c0 bar with quadratic u / linear ebar elements (line3)
+    c1q the c1 plate with biquadratic u / bilinear ebar elements (quad9)
     """
     if name == "c0":
         return bar1d()
@@ -263,6 +347,10 @@ def config(name: str) -> Problem:
         return beam3d(256, 64, 32)
     if name == "c3p":
         return beam3d(64, 16, 8)
+    if name == "c0q":
+        return bar1d_quadratic()
+    if name == "c1q":
+        return sen2d_quadratic(material=base_material(nu=0.2, k=10.0))
     raise KeyError(name)
 
 
@@ -348,6 +436,10 @@ def injected_state(prob: Problem, seed: int, load: float = 1.0, noise: float = 0
     strain_scale = umax / lref
     x[prob.dim::nd] = ebar_scale * (strain_scale * rng.uniform(0.2, 2.5, prob.n_nodes)
                                     + prob.material.kappa0 * rng.uniform(0.0, 2.0, prob.n_nodes))
+    if prob.elem_type in MIXED_ORDER:             # ebar lives on the vertices only
+        keep = np.zeros(prob.n_nodes, dtype=bool)
+        keep[prob.ebar_nodes()] = True
+        x[prob.dim::nd][~keep] = 0.0
     dofs = prob.bc_dofs()
     x[dofs] = prob.bc_values * load
     kappa_n = prob.material.kappa0 * kappa_spread * rng.uniform(0.0, 1.0, prob.n_elems * prob.ngp)

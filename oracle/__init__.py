@@ -11,8 +11,11 @@ passages that are silent, ambiguous or garbled are listed in the module
 docstring of oracle.lgdm.
 
 Parity status: every function here is pinned by the not-gpu tests in
-tests/test_oracle_pins.py and tests/test_oracle_fe.py, except the full
-load-displacement curve shapes, which the paper only shows in figures
-(parity unpinned for the curve shapes).
+tests/test_oracle_pins.py, tests/test_oracle_fe.py, tests/test_oracle_coupling.py
+(the Eq. 2 coupling variant) and tests/test_oracle_mixed.py (the mixed-order
+elements of oracle.mixed_order), except the full load-displacement curve
+shapes, which the paper only shows in figures (parity unpinned for the curve
+shapes).
 """
 from .lgdm import *  # noqa: F401,F403
+from .mixed_order import *  # noqa: F401,F403

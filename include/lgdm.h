@@ -29,7 +29,8 @@
  *    [0, dim) the displacement components and comp = dim the
  *    micro-equivalent strain (ebar).
  *  - Gauss-point arrays are indexed element * 2^dim + g with
- *    g = i_xi + 2 i_eta + 4 i_zeta (2-point Gauss-Legendre per direction).
+ *    g = i_xi + 2 i_eta + 4 i_zeta (2-point Gauss-Legendre per direction);
+ *    mixed-order elements (LGDM_LINE3 / LGDM_QUAD9) have 3^dim points each.
  *  - One context per host thread.
  */
 #ifndef LGDM_H
@@ -56,7 +57,25 @@ enum {
 };
 
 enum { LGDM_FP64 = 0, LGDM_MIXED = 1 };          /* precision of a context      */
-enum { LGDM_LINE2 = 1, LGDM_QUAD4 = 2, LGDM_HEX8 = 3 };
+/* Element types.  Equal-order elements interpolate u and ebar with the same
+ * multilinear functions (2-point Gauss per direction).  The mixed-order
+ * elements are the paper's 1D / 2D discretisation (Sec. 2.1 after Eqs. 9-10;
+ * Secs. 3.1, 3.2): quadratic u, linear ebar on the element's vertices,
+ * geometry from the quadratic element, 3-point Gauss-Legendre per direction
+ * (points -sqrt(3/5), 0, sqrt(3/5); weights 5/9, 8/9, 5/9; point
+ * g = i_xi + 3 i_eta, so Gauss-point arrays have 3^dim entries per element).
+ *  LGDM_LINE3  dim 1: 3 nodes per element (left end, right end, midpoint);
+ *              ebar on the two ends.
+ *  LGDM_QUAD9  dim 2: 9 nodes (corners counter-clockwise from (-1, -1), the
+ *              mid-side nodes of the edges 0-1, 1-2, 2-3, 3-0, the centre);
+ *              ebar on the 4 corners.
+ * With mixed-order elements the dof layout stays node-interleaved with
+ * dim + 1 dofs per node: the ebar dof of a node that is no element's vertex
+ * carries no unknown and is held at zero (identity row, zero column, zero
+ * residual, like a Dirichlet dof; lgdm_set_state zeroes it).  Mixed-order
+ * contexts use the executed-code coupling only, and the batch does not
+ * serve them. */
+enum { LGDM_LINE2 = 1, LGDM_QUAD4 = 2, LGDM_HEX8 = 3, LGDM_LINE3 = 4, LGDM_QUAD9 = 5 };
 enum { LGDM_PLANE_STRESS = 0, LGDM_PLANE_STRAIN = 1 };
 
 /* fields for lgdm_query_state */
@@ -246,10 +265,12 @@ lgdm_status lgdm_set_allocator(lgdm_ctx* ctx, void* (*alloc)(size_t, void*),
  * once-per-mesh work: dof numbering, node graph, CSR pattern of all
  * element-coupled dof pairs (structural zeros kept), node-to-element lists
  * (Fig. 2 assembly hoisted out of the Newton loop).
- *  dim        1, 2 or 3; elem_type LGDM_LINE2 / LGDM_QUAD4 / LGDM_HEX8 matching dim
+ *  dim        1, 2 or 3; elem_type LGDM_LINE2 / LGDM_QUAD4 / LGDM_HEX8 matching dim,
+ *             or the mixed-order LGDM_LINE3 (dim 1) / LGDM_QUAD9 (dim 2)
  *  coords     host, [n_nodes * dim] FP64, node-major
- *  conn       host, [n_elems * 2^dim] int32, local node order line2 (x0, x1),
- *             quad4 counter-clockwise, hex8 bottom face then top face
+ *  conn       host, [n_elems * nen] int32 (nen = 2^dim; 3 / 9 for the mixed-order
+ *             types), local node order line2 (x0, x1), quad4 counter-clockwise,
+ *             hex8 bottom face then top face; line3 / quad9 as their enum says
  *  e_scale    host, [n_elems] factor on the elasticity tensor only, or NULL (1)
  * Resets the state (x = 0, kappa_n = 0, increment 0).  INVALID_ARG for bad
  * sizes, out-of-range node ids, a node shared by more elements or neighbours

@@ -413,8 +413,9 @@ class Context:
         return out
 
     def element_blocks(self, e0: int, e1: int):
-        nen = 1 << self.dim
-        nl = nen * (self.dim + 1)
+        c, n, nen = ctypes.c_void_p(), ctypes.c_int64(), ctypes.c_int32()
+        self._check(self.lib.lgdm_get_connectivity(self.h, ctypes.byref(c), ctypes.byref(n), ctypes.byref(nen)))
+        nl = nen.value * (self.dim + 1)
         Ke = np.empty((e1 - e0, nl, nl))
         fe = np.empty((e1 - e0, nl))
         self._check(self.lib.lgdm_debug_element_blocks(self.h, e0, e1, self._ptr(Ke), self._ptr(fe)))

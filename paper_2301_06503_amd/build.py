@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblgdm.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["element.hip", "pattern.hip", "krylov.hip", "amg.hip", "capi.cpp", "batch.cpp", "noalloc.hip"]
+SOURCES = ["element.hip", "pattern.hip", "krylov.hip", "amg.hip", "capi.cpp", "batch.cpp", "noalloc.hip", "mixed_order.hip"]
 ARCH = os.environ.get("LGDM_OFFLOAD_ARCH", "gfx950")
 
 

@@ -234,6 +234,8 @@ lgdm_status lgdm_batch_admit(lgdm_batch* b, const lgdm_request* r, int32_t* slot
     if (any) return bfail(b, LGDM_ERR_INVALID_ARG, "all requests of a batch share one element type");
   }
   if (r->n_increments <= 0) return bfail(b, LGDM_ERR_INVALID_ARG, "n_increments must be positive");
+  if (r->elem_type != r->dim)
+    return bfail(b, LGDM_ERR_INVALID_ARG, "the batch serves equal-order elements (LINE2 / QUAD4 / HEX8)");
   int64_t est = 0;
   if (lgdm_request_footprint(r->dim, r->n_nodes, r->n_elems, b->precision, &est) != LGDM_OK)
     return bfail(b, LGDM_ERR_INVALID_ARG, "bad request sizes");

@@ -331,17 +331,23 @@ lgdm_status lgdm_upload_mesh(lgdm_ctx* c, int32_t dim, int32_t elem_type, int64_
                              const double* coords, int64_t n_elems, const int32_t* conn,
                              const double* e_scale) {
   if (!c) return LGDM_ERR_INVALID_ARG;
-  if (dim < 1 || dim > 3 || elem_type != dim)
-    return fail(c, LGDM_ERR_INVALID_ARG, "dim must be 1, 2 or 3 with element type LINE2, QUAD4, HEX8");
+  const bool order2 = (elem_type == LGDM_LINE3 && dim == 1) || (elem_type == LGDM_QUAD9 && dim == 2);
+  if (dim < 1 || dim > 3 || (elem_type != dim && !order2))
+    return fail(c, LGDM_ERR_INVALID_ARG, "dim must be 1, 2 or 3 with element type LINE2, QUAD4, HEX8, "
+                                         "or 1 with LINE3, 2 with QUAD9");
   if (n_nodes <= 0 || n_elems <= 0 || !coords || !conn)
     return fail(c, LGDM_ERR_INVALID_ARG, "empty mesh or NULL coords / conn");
-  if (n_elems >= ((int64_t)1 << 28) || n_nodes * (dim + 1) >= ((int64_t)1 << 31))
+  if (n_elems >= ((int64_t)1 << (31 - N2E_SHIFT)) || n_nodes * (dim + 1) >= ((int64_t)1 << 31))
     return fail(c, LGDM_ERR_INVALID_ARG, "mesh too large for int32 indexing");
+  if (order2 && c->has_mat && c->mat.coupling != LGDM_COUPLING_EXECUTED)
+    return fail(c, LGDM_ERR_INVALID_ARG, "the coupling variant is not available for mixed-order elements");
   (void)hipSetDevice(c->device);
   free_mesh(c);
   c->dim = dim;
-  c->nen = 1 << dim;
-  c->ngp = 1 << dim;
+  c->order2 = order2;
+  c->nen = order2 ? (dim == 1 ? 3 : 9) : 1 << dim;
+  c->nen_e = 1 << dim;
+  c->ngp = order2 ? (dim == 1 ? 3 : 9) : 1 << dim;
   c->nd = dim + 1;
   c->n_nodes = n_nodes;
   c->n_elems = n_elems;
@@ -373,6 +379,20 @@ lgdm_status lgdm_upload_mesh(lgdm_ctx* c, int32_t dim, int32_t elem_type, int64_
   if (status != LGDM_OK) {
     free_mesh(c);
     return fail(c, status, msg);
+  }
+  if (order2 && c->max_nbr > (dim == 1 ? 8 : 32)) {
+    free_mesh(c);
+    return fail(c, LGDM_ERR_INVALID_ARG, "a node has more neighbours than the mixed-order assembly handles");
+  }
+  // ebar dofs of nodes that are no element's vertex carry no unknown: they
+  // are constrained to zero like Dirichlet dofs
+  c->base_flags.assign(c->ndof, 0);
+  if (order2) {
+    std::vector<uint8_t> vert(n_nodes, 0);
+    for (int64_t el = 0; el < n_elems; ++el)
+      for (int a = 0; a < c->nen_e; ++a) vert[conn[el * c->nen + a]] = 1;
+    for (int64_t n = 0; n < n_nodes; ++n)
+      if (!vert[n]) c->base_flags[n * c->nd + dim] = 1 | 4;
   }
   // state, assembly and solver buffers
   const int64_t nd = c->ndof, ng = c->ngauss;
@@ -424,7 +444,7 @@ lgdm_status lgdm_upload_mesh(lgdm_ctx* c, int32_t dim, int32_t elem_type, int64_
   HIPCHECK(c, zero(c, c->kappa_t, ng * sizeof(double)), "zero");
   HIPCHECK(c, zero(c, c->D_t, ng * sizeof(double)), "zero");
   HIPCHECK(c, zero(c, c->eeq_t, ng * sizeof(double)), "zero");
-  HIPCHECK(c, zero(c, c->dof_flags, nd), "zero");
+  HIPCHECK(c, hipMemcpyAsync(c->dof_flags, c->base_flags.data(), nd, hipMemcpyHostToDevice, c->stream), "flags");
   HIPCHECK(c, zero(c, c->kcount, 16 * sizeof(unsigned)), "zero");
   HIPCHECK(c, hipStreamSynchronize(c->stream), "upload");
   c->increment = 0;
@@ -440,6 +460,8 @@ lgdm_status lgdm_set_material(lgdm_ctx* c, const lgdm_material* m) {
       !(m->tol_hist >= 0) || !(m->tol_dmg >= 0) || (m->plane != 0 && m->plane != 1) ||
       (m->coupling != LGDM_COUPLING_EXECUTED && m->coupling != LGDM_COUPLING_EQ2))
     return fail(c, LGDM_ERR_INVALID_ARG, "material parameter out of range");
+  if (c->order2 && m->coupling != LGDM_COUPLING_EXECUTED)
+    return fail(c, LGDM_ERR_INVALID_ARG, "the coupling variant is not available for mixed-order elements");
   // the coupling variant's Gauss-point records are longer
   if (c->dim != 0 && c->rec_stride < rec_stride(c->dim, m->coupling == LGDM_COUPLING_EQ2)) {
     const int rs = rec_stride(c->dim, true);
@@ -459,7 +481,7 @@ lgdm_status lgdm_set_dirichlet(lgdm_ctx* c, int64_t n, const int64_t* dofs, cons
   if (!c) return LGDM_ERR_INVALID_ARG;
   if (c->dim == 0) return fail(c, LGDM_ERR_STATE, "upload a mesh first");
   if (n < 0 || (n > 0 && (!dofs || !ref_values))) return fail(c, LGDM_ERR_INVALID_ARG, "bad Dirichlet arrays");
-  std::vector<uint8_t> flags(c->ndof, 0);
+  std::vector<uint8_t> flags(c->base_flags);
   std::vector<int32_t> d32(n);
   std::vector<double> v(n);
   for (int64_t i = 0; i < n; ++i) {
@@ -774,7 +796,10 @@ lgdm_status lgdm_set_state(lgdm_ctx* c, const double* x, const double* kappa_n, 
   if (!c) return LGDM_ERR_INVALID_ARG;
   if (!ready(c)) return fail(c, LGDM_ERR_STATE, "upload a mesh and set the material first");
   if (increment < 0) return fail(c, LGDM_ERR_INVALID_ARG, "negative increment");
-  if (x) HIPCHECK(c, hipMemcpyAsync(c->x, x, c->ndof * sizeof(double), hipMemcpyDefault, c->stream), "copy x");
+  if (x) {
+    HIPCHECK(c, hipMemcpyAsync(c->x, x, c->ndof * sizeof(double), hipMemcpyDefault, c->stream), "copy x");
+    if (c->order2) HIPCHECK(c, launch_zero_flagged(c, c->x, 4), "zero ebar of non-vertex nodes");
+  }
   if (kappa_n) {
     HIPCHECK(c, hipMemcpyAsync(c->kappa_n, kappa_n, c->ngauss * sizeof(double), hipMemcpyDefault, c->stream), "copy kappa");
     HIPCHECK(c, launch_damage_from_kappa(c, make_params(c->mat, c->dim)), "damage");

@@ -28,6 +28,7 @@
 //   K^ee = int h N_a N_b + h c g' D' chi (dN_a . grad ebar) N_b + g h c dN_a . dN_b.
 #include <cmath>
 
+#include "gp_state.h"
 #include "lgdm_internal.h"
 
 namespace lgdm {
@@ -68,15 +69,6 @@ __device__ __forceinline__ void shape_fast(int a, int g, T& N, T dN[DIM]) {
       if (d != j) p *= f[d];
     dN[j] = p;
   }
-}
-
-// index of the symmetric tensor entry (i, j) in the record ordering
-template <int DIM> __device__ __forceinline__ constexpr int sym_idx(int i, int j) {
-  if (DIM == 1) return 0;
-  if (DIM == 2) return (i == j) ? i : 2;
-  if (i == j) return i;
-  const int lo = i < j ? i : j, hi = i < j ? j : i;
-  return (lo == 0 && hi == 1) ? 3 : ((lo == 1 && hi == 2) ? 4 : 5);
 }
 
 // ---------------------------------------------------------------------------
@@ -187,58 +179,6 @@ __device__ __forceinline__ void gp_point(int64_t gid, const GpArgs& A, const Mat
     for (int j = 0; j < DIM; ++j) eps[i][j] = 0.5 * (gu[i][j] + gu[j][i]);
   if (DIM == 2) eps[2][2] = mp.ezz_fac * (eps[0][0] + eps[1][1]);
 
-  // modified von Mises equivalent strain (A.3) and its gradient G = d eeq / d eps
-  double eeq;
-  double G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  double q3[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // coupling variant: ds / deps
-  double al = 0.0, be = 0.0;                          // coupling variant: coefficients of d^2 eeq
-  if (DIM == 1) {
-    eeq = eps[0][0];
-    G[0][0] = 1.0;
-  } else {
-    const double I1 = eps[0][0] + eps[1][1] + eps[2][2];
-    double dev[3][3];
-    double J2 = 0.0;
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        dev[i][j] = eps[i][j] - (i == j ? I1 / 3.0 : 0.0);
-        J2 += dev[i][j] * dev[i][j];
-      }
-    J2 *= 0.5;
-    const double s = mp.c2 * mp.c2 * I1 * I1 + mp.c3 * J2;
-    if (CPL) {
-      // d^2 eeq / deps^2 = al (2 c2^2 1 (x) 1 + c3 P_dev) - be q (x) q, dropped at the cone point
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) q3[i][j] = (i == j ? 2.0 * mp.c2 * mp.c2 * I1 : 0.0) + mp.c3 * dev[i][j];
-      const double sqv = s > 0.0 ? sqrt(s) : 0.0;
-      if (sqv > mp.sq_guard) {
-        al = 1.0 / (4.0 * mp.k * sqv);
-        be = al / (2.0 * s);
-      }
-    }
-    if (s > 0.0) {
-      const double sq = sqrt(s);
-      eeq = mp.c1 * I1 + sq / (2.0 * mp.k);
-      const double f = 1.0 / (4.0 * mp.k * sq);
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-          G[i][j] = (i == j ? mp.c1 + f * 2.0 * mp.c2 * mp.c2 * I1 : 0.0) + f * mp.c3 * dev[i][j];
-    } else {  // minimum-norm subgradient where the root argument vanishes
-      eeq = mp.c1 * I1;
-#pragma unroll
-      for (int i = 0; i < 3; ++i) G[i][i] = mp.c1;
-    }
-    if (DIM == 2) {  // plane stress: eps_zz depends on the in-plane strains
-      G[0][0] += mp.ezz_fac * G[2][2];
-      G[1][1] += mp.ezz_fac * G[2][2];
-    }
-  }
   // micro-equivalent strain and its gradient at the Gauss point
   double ebar = 0.0, gb[DIM];
 #pragma unroll
@@ -249,83 +189,9 @@ __device__ __forceinline__ void gp_point(int64_t gid, const GpArgs& A, const Mat
 #pragma unroll
     for (int d = 0; d < DIM; ++d) gb[d] += eb[a] * dNx[a][d];
   }
-  // history (A.2, condition vector cond1 of Fig. 8b)
-  const double kn = kappa_n[gid];
-  const bool chi = (ebar - kn) > mp.tol_hist;
-  const double kap = chi ? ebar : kn;
-  // damage (A.1, condition vector cond2 of Fig. 8b)
-  double D = 0.0, dD = 0.0;
-  if (!((kap - mp.kappa0) < mp.tol_dmg)) {
-    const double ex = exp(-mp.beta * (kap - mp.kappa0));
-    const double br = 1.0 - mp.alpha + mp.alpha * ex;
-    const double q = mp.kappa0 / kap;
-    D = 1.0 - q * br;
-    dD = q / kap * br + q * mp.alpha * mp.beta * ex;
-  }
-  // interaction function (A.4)
-  const double en = exp(-mp.eta * D);
-  const double gv = ((1.0 - mp.R) * en + mp.R - exp(-mp.eta)) / mp.g_den;
-  const double dg = -mp.eta * (1.0 - mp.R) * en / mp.g_den;
-
-  // unscaled stress S = C : eps
-  double S[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  if (DIM == 1) {
-    S[0][0] = mp.E * eps[0][0];
-  } else {
-    double tr = 0.0;
-#pragma unroll
-    for (int i = 0; i < DIM; ++i) tr += eps[i][i];
-#pragma unroll
-    for (int i = 0; i < DIM; ++i)
-#pragma unroll
-      for (int j = 0; j < DIM; ++j) S[i][j] = 2.0 * mp.mu * eps[i][j] + (i == j ? mp.lam * tr : 0.0);
-  }
-  const double wJ = detJ * mp.thick;  // Gauss weights are 1
-  const double se = e_scale[e];
-  const double chid = chi ? 1.0 : 0.0;
-
-  double* r = rec + gid * RC::STRIDE;
-#pragma unroll
-  for (int j = 0; j < DIM; ++j)
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) r[RC::JINV + j * DIM + d] = Ji[j][d];
-  r[RC::CUU] = wJ * (1.0 - D) * se;
-  r[RC::CUE] = wJ * dD * chid * se;
-#pragma unroll
-  for (int i = 0; i < DIM; ++i)
-#pragma unroll
-    for (int j = i; j < DIM; ++j) {
-      r[RC::S + sym_idx<DIM>(i, j)] = S[i][j];
-      r[RC::GH + sym_idx<DIM>(i, j)] = wJ * mp.h * G[i][j];
-    }
-#pragma unroll
-  for (int d = 0; d < DIM; ++d) r[RC::GB + d] = gb[d];
-  r[RC::CEE] = wJ * mp.h;
-  r[RC::CGP] = wJ * mp.h * mp.c * dg * dD * chid;
-  r[RC::CG] = wJ * gv * mp.h * mp.c;
-  r[RC::RE] = wJ * mp.h * (ebar - eeq);
-  r[RC::FR] = wJ * mp.h * eeq;
-  if (CPL) {
-#pragma unroll
-    for (int i = 0; i < DIM; ++i)
-#pragma unroll
-      for (int j = i; j < DIM; ++j) r[RC::GU + sym_idx<DIM>(i, j)] = G[i][j];
-    r[RC::AL] = al;
-    r[RC::BE] = be;
-    if (DIM == 3) {
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = i; j < 3; ++j) r[RC::Q + sym_idx<3>(i, j)] = q3[i][j];
-    } else if (DIM == 2) {
-      r[RC::Q + 0] = q3[0][0];
-      r[RC::Q + 1] = q3[1][1];
-      r[RC::Q + 2] = q3[0][1];
-      r[RC::Q + 3] = q3[2][2];
-    }
-  }
-#pragma unroll
-  for (int f = RC::USED; f < RC::STRIDE; ++f) r[f] = 0.0;
+  double kap, D, eeq;
+  gp_state_record<DIM, CPL>(eps, ebar, gb, Ji, detJ * mp.thick, e_scale[e], kappa_n[gid], mp,
+                            rec + gid * RC::STRIDE, kap, D, eeq);
   kappa_t[gid] = kap;
   D_t[gid] = D;
   A.eeq_t[gid] = eeq;
@@ -629,8 +495,8 @@ __device__ __forceinline__ void node_block(int64_t blk, const NodeArgs& A, const
     int64_t e = 0;
     if (act) {
       const int ent = n2e[e0 + kk];
-      e = ent >> 3;
-      la = ent & 7;
+      e = ent >> N2E_SHIFT;
+      la = ent & N2E_MASK;
       p = pos[(e * NEN + la) * NEN + b];
     }
     double blk[ND][ND];
@@ -904,6 +770,10 @@ MatParams make_params(const lgdm_material& m, int dim) {
 }
 
 int64_t node_kernel_blocks(const lgdm_ctx* c) {
+  if (c->order2) {
+    const int npb = q_node_kernel_nodes_per_block(c->dim);
+    return (c->n_nodes + npb - 1) / npb;
+  }
   const int L = c->dim == 1 ? node_lanes<1>() : (c->dim == 2 ? node_lanes<2>() : node_lanes<3>());
   const int npb = NODE_BLOCK / L;
   return (c->n_nodes + npb - 1) / npb;
@@ -923,6 +793,7 @@ NodeArgs node_args(const lgdm_ctx* c) {
 int64_t gp_kernel_blocks(const lgdm_ctx* c) { return (c->ngauss + 255) / 256; }
 
 hipError_t launch_gp_kernel(lgdm_ctx* c, const MatParams& mp) {
+  if (c->order2) return launch_q_gp_kernel(c, mp);
   const int64_t grid = gp_kernel_blocks(c);
   if (grid == 0) return hipSuccess;
   const GpArgs A = gp_args(c);
@@ -958,6 +829,7 @@ static void node_launch(lgdm_ctx* c, const MatParams& mp, bool want_k) {
 }
 
 hipError_t launch_node_kernel(lgdm_ctx* c, const MatParams& mp, bool want_k) {
+  if (c->order2) return launch_q_node_kernel(c, mp, want_k);
   const bool mixed = c->precision == LGDM_MIXED;
   switch (c->dim) {
     case 1:
@@ -1028,6 +900,7 @@ hipError_t launch_damage_from_kappa(lgdm_ctx* c, const MatParams& mp) {
 
 hipError_t launch_element_blocks(lgdm_ctx* c, const MatParams& mp, int64_t e0, int64_t e1,
                                  double* Ke, double* fe) {
+  if (c->order2) return launch_q_element_blocks(c, mp, e0, e1, Ke, fe);
   const int64_t n = (e1 - e0) * c->nen * c->nen;
   const int64_t grid = (n + 255) / 256;
   if (grid == 0) return hipSuccess;

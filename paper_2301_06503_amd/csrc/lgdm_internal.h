@@ -104,6 +104,10 @@ struct SlotDesc {
   int64_t node_block0;
 };
 
+// node -> element list entries: (element << N2E_SHIFT) | local node
+constexpr int N2E_SHIFT = 4;
+constexpr int N2E_MASK = (1 << N2E_SHIFT) - 1;
+
 constexpr int NORM_SLOTS = 6;  // |R_u|^2, |R_e|^2, |f_u|^2, |fref_e|^2, reaction, non-finite count
 constexpr int RED_CHUNKS = 1024;  // stage-one workgroups of the two-stage reductions
 // Krylov workspace: IDR(8) needs r, v, t and 8 + 8 direction vectors; the
@@ -143,6 +147,9 @@ struct lgdm_ctx {
 
   // mesh and pattern (H0)
   int dim = 0, nen = 0, ngp = 0, nd = 0;
+  bool order2 = false;          // mixed-order elements (line3 / quad9 u, linear ebar on the vertices)
+  int nen_e = 0;                // ebar nodes per element (the first nen_e of each element's list)
+  std::vector<uint8_t> base_flags;  // per dof: constraints of the mesh itself (ebar of non-vertex nodes)
   int64_t n_nodes = 0, n_elems = 0, ndof = 0, ngauss = 0, nnz = 0, npairs = 0;
   int max_elem_per_node = 0, max_nbr = 0;
   double* coords = nullptr;
@@ -158,7 +165,8 @@ struct lgdm_ctx {
   int32_t* col_idx = nullptr;
 
   // boundary conditions
-  uint8_t* dof_flags = nullptr;  // bit0 Dirichlet, bit1 loaded (nonzero reference value)
+  uint8_t* dof_flags = nullptr;  // bit0 constrained (Dirichlet, or an ebar dof of a non-vertex node),
+                                 // bit1 loaded (nonzero reference value), bit2 ebar dof of a non-vertex node
   int32_t* bc_dofs = nullptr;
   double* bc_vals = nullptr;
   int64_t nbc = 0;
@@ -244,6 +252,13 @@ int64_t node_kernel_blocks(const lgdm_ctx* c);
 int64_t gp_kernel_blocks(const lgdm_ctx* c);
 GpArgs gp_args(const lgdm_ctx* c);
 NodeArgs node_args(const lgdm_ctx* c);
+// mixed-order elements (mixed_order.hip)
+int q_node_kernel_nodes_per_block(int dim);
+hipError_t launch_q_gp_kernel(lgdm_ctx* c, const MatParams& mp);
+hipError_t launch_q_node_kernel(lgdm_ctx* c, const MatParams& mp, bool want_k);
+hipError_t launch_q_element_blocks(lgdm_ctx* c, const MatParams& mp, int64_t e0, int64_t e1, double* Ke,
+                                   double* fe);
+hipError_t launch_zero_flagged(lgdm_ctx* c, double* v, uint8_t mask);  // v[d] = 0 where flags[d] & mask
 hipError_t launch_fused_assembly(hipStream_t st, int dim, bool mixed, const SlotDesc* slots_dev,
                                  int nslots, int64_t gp_blocks, int64_t node_blocks);
 

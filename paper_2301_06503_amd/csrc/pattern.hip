@@ -14,7 +14,7 @@ namespace lgdm {
 namespace {
 
 constexpr int MAX_ELEM_PER_NODE = 16;   // per node, any element type
-constexpr int MAX_CAND = MAX_ELEM_PER_NODE * 8;
+constexpr int MAX_CAND = 160;          // element nodes gathered per node: elements x nodes per element
 
 __global__ void count_n2e_kernel(int64_t n, const int32_t* __restrict__ conn,
                                  int32_t* __restrict__ cnt) {
@@ -30,7 +30,7 @@ __global__ void fill_n2e_kernel(int64_t n, int nen, const int32_t* __restrict__ 
   const int32_t node = conn[i];
   const int32_t e = (int32_t)(i / nen), la = (int32_t)(i % nen);
   const int32_t slot = atomicAdd(&cursor[node], 1);
-  n2e[ptr[node] + slot] = (e << 3) | la;
+  n2e[ptr[node] + slot] = (e << N2E_SHIFT) | la;
 }
 
 __device__ void isort(int32_t* v, int n) {
@@ -69,10 +69,14 @@ __global__ void nbr_kernel(int64_t n_nodes, int nen, const int32_t* __restrict__
   if (a >= n_nodes) return;
   const int s = n2e_ptr[a], ne = n2e_ptr[a + 1] - s;
   if (ne > MAX_ELEM_PER_NODE) return;
+  if (ne * nen > MAX_CAND) {
+    if (pass == 0) atomicMax(&stats[4], ne * nen);
+    return;
+  }
   int32_t cand[MAX_CAND];
   int nc = 0;
   for (int i = 0; i < ne; ++i) {
-    const int64_t e = n2e[s + i] >> 3;
+    const int64_t e = n2e[s + i] >> N2E_SHIFT;
     for (int b = 0; b < nen; ++b) cand[nc++] = conn[e * nen + b];
   }
   isort(cand, nc);
@@ -206,6 +210,11 @@ hipError_t build_pattern(lgdm_ctx* c, std::string& msg, int& status) {
   if (h_stats[0] > MAX_ELEM_PER_NODE) {
     status = LGDM_ERR_INVALID_ARG;
     msg = "a node is shared by more than 16 elements";
+    return hipSuccess;
+  }
+  if (h_stats[4] > 0) {
+    status = LGDM_ERR_INVALID_ARG;
+    msg = "a node's elements list more node entries than the pattern builder handles";
     return hipSuccess;
   }
   if (h_stats[1] > lanes || h_stats[1] > 255) {

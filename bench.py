@@ -42,6 +42,10 @@ WORKLOADS = {
     "c0": "1D bar, 100 line2 elements, 100 increments to 0.02 mm",
     "c3p": "3D notched beam, three-point bending, 64x16x8 hex8 (8,192 elements, 65,536 Gauss points, "
            "39,780 dofs), notch E x 0.01, 150 increments to 0.5 mm",
+    "c0q": "1D bar, 100 quadratic-u / linear-ebar elements (line3, 3 Gauss points), 100 increments to 0.02 mm",
+    "c1q": "2D plane-stress single-edge-notched plate 200x100 biquadratic-u / bilinear-ebar elements (quad9, "
+           "180,000 Gauss points, 80,601 nodes, 241,803 dofs of which 161,202 u and 20,301 ebar), "
+           "200 increments to 0.1 mm",
 }
 
 
@@ -305,6 +309,14 @@ def load_path_run(prob, precision, args, binding, n_inc):
                     "error": ctx.lib.lgdm_last_error(ctx.h).decode()}
             log("load path stops at increment %d: %s" % (i + 1, stop["error"]))
             break
+        if (i + 1) in args.dump_state:
+            # the committed state, for re-solving a later increment elsewhere
+            import numpy as np
+            os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
+            path = os.path.join(ROOT, "gpurun_out", "state_%s_%s_%04d.npz" % (args.config, label, i + 1))
+            np.savez_compressed(path, x=ctx.query(binding.FIELD_X), kappa=ctx.query(binding.FIELD_KAPPA),
+                                increment=i + 1, n_increments=prob.n_increments)
+            log("saved the committed state of increment %d to %s" % (i + 1, path))
         incs.append({"inc": i + 1, "ms": dt * 1e3, "newton": d["newton_iters"], "assemblies": d["n_assemblies"],
                      "krylov": d["krylov_iters"], "t_asm": d["t_assembly_ms"], "t_sol": d["t_solve_ms"],
                      "reaction": d["reaction"], "max_damage": d["max_damage"], "substeps": nsub})
@@ -348,22 +360,28 @@ def load_path_run(prob, precision, args, binding, n_inc):
 
 
 def cpu_baseline(name, prob, budget_s=20.0):
-    """The oracle on the host, one BLAS thread (the sparse LU is single
-    threaded): whole Newton iterations (element evaluation, triplet
-    assembly, Dirichlet rows, sparse LU solve, update) of the first load
-    increment, scaled to Gauss points per second of wall time like the GPU
-    value.  The 3D beams are sampled at 64x16x8 (a sparse LU of the full
-    mesh does not fit a bounded run); the element evaluation + assembly rate
-    on a slab of the full mesh is reported beside it."""
+    """The oracle on the host with BLAS on every host core (its dense
+    element contractions run there; the sparse LU is single threaded):
+    whole Newton iterations (element evaluation, triplet assembly, Dirichlet
+    rows, sparse LU solve, update) of the first load increment, scaled to
+    Gauss points per second of wall time like the GPU value.  The 3D beams
+    are sampled at 64x16x8 (a sparse LU of the full mesh does not fit a
+    bounded run); the element evaluation + assembly rate on a slab of the
+    full mesh is reported beside it."""
     import numpy as np
     import scipy.sparse.linalg as spla
-    from threadpoolctl import threadpool_limits
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle.lgdm import Oracle, eval_elements, assemble
+    from oracle.mixed_order import MixedOracle, eval_elements_mixed
     import lgdm_workloads as W
     sample_name = "c3p" if name in ("c2", "c3") else name
     sample = W.config(sample_name)
-    with threadpool_limits(limits=1):
-        o = Oracle(sample)
+    mixed_order = prob.elem_type in W.MIXED_ORDER
+    host_cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    with threadpool_limits(limits=host_cores, user_api="blas"):
+        blas_threads = max([p.get("num_threads", 1) for p in threadpool_info() if p.get("user_api") == "blas"]
+                           or [1])
+        o = MixedOracle(sample) if mixed_order else Oracle(sample)
         o.x[o.bc_dofs] = (1.0 / sample.n_increments) * o.bc_vals
         its = 0
         t0 = time.perf_counter()
@@ -379,18 +397,35 @@ def cpu_baseline(name, prob, budget_s=20.0):
         n_el = min(prob.n_elems, 2048)
         done_el = 0
         t1 = time.perf_counter()
+        if mixed_order:
+            mo = MixedOracle(prob)
+            xo = mo.from_interleaved(x)
+            u_nodal = xo[:prob.n_nodes * prob.dim].reshape(-1, prob.dim)
+            ebar_v = xo[prob.n_nodes * prob.dim:]
         while True:
             sl = np.arange(done_el, done_el + n_el) % prob.n_elems
-            ev = eval_elements(prob.dim, prob.coords, prob.conn, prob.e_scale, mat, x, kn, elems=sl)
-            assemble(prob.dim, prob.conn[sl], prob.n_nodes, ev["fint"], ev["Ke"])
+            if mixed_order:
+                # element evaluation + triplet assembly (sum of duplicates) of the slab
+                import scipy.sparse as sps
+                ev = eval_elements_mixed(prob.dim, prob.coords, prob.conn[sl], prob.e_scale[sl], mat, u_nodal,
+                                         ebar_v, mo.vidx, kn.reshape(prob.n_elems, -1)[sl])
+                ed = mo.edofs[sl]
+                nl = ed.shape[1]
+                sps.coo_matrix((ev["Ke"].ravel(), (np.repeat(ed, nl, axis=1).ravel(), np.tile(ed, (1, nl)).ravel())),
+                               shape=(mo.ndof, mo.ndof)).tocsr()
+            else:
+                ev = eval_elements(prob.dim, prob.coords, prob.conn, prob.e_scale, mat, x, kn, elems=sl)
+                assemble(prob.dim, prob.conn[sl], prob.n_nodes, ev["fint"], ev["Ke"])
             done_el += n_el
             if time.perf_counter() - t1 > budget_s * 0.25 or done_el >= prob.n_elems:
                 break
         dt_asm = time.perf_counter() - t1
-    return {"value": whole, "unit": "GP/s", "cores": 1, "kind": "oracle",
+    return {"value": whole, "unit": "GP/s", "cores": blas_threads, "kind": "oracle",
             "sample": "%d Newton iterations (assembly + sparse LU + update) of the oracle on %s (%d Gauss "
-                      "points, %d dofs) in %.1f s, one thread; host has %d cores" % (
-                          its, sample_name, sample.n_elems * sample.ngp, sample.ndof, dt, os.cpu_count()),
+                      "points, %d dofs) in %.1f s; BLAS on %d threads (the SuperLU factorisation is single "
+                      "threaded); %d cores in the affinity mask" % (
+                          its, sample_name, sample.n_elems * sample.ngp, sample.ndof, dt, blas_threads,
+                          host_cores),
             "assembly_only_gp_per_s": done_el * prob.ngp / dt_asm,
             "assembly_only_sample": "element evaluation + triplet assembly of %d of %d elements of %s (%.1f s)"
                                     % (done_el, prob.n_elems, name, dt_asm)}
@@ -461,11 +496,15 @@ def main():
                     help="load-path mode: wall time one load step may spend before it fails (0: no bound)")
     ap.add_argument("--cutback", type=int, default=0,
                     help="load-path mode: split a load step that fails into halves, at most this many times")
+    ap.add_argument("--dump-state", type=str, default="",
+                    help="load-path mode: comma-separated increments whose committed state (x, kappa_n) is "
+                         "saved to gpurun_out/state_<config>_<precision>_<increment>.npz")
     ap.add_argument("--load-path", type=int, default=0,
                     help="instead of the bench line: run this many increments of the load path (-1: all) in "
                          "mixed precision and FP64 and report the step time per phase (elastic, near the "
                          "peak, post-peak)")
     args = ap.parse_args()
+    args.dump_state = {int(v) for v in args.dump_state.split(",") if v.strip()}
     if args.gpus != 1:
         print("bench.py runs on one GPU: the LGDM hot path here is built and measured on a single "
               "MI355X; multi-GPU runs are not implemented (requested --gpus %d)" % args.gpus,
@@ -484,8 +523,9 @@ def main():
         lp = {"workload": WORKLOADS[args.config], "name": args.config, "increments_requested": n_inc,
               "columns": ["increment", "ms", "newton", "krylov", "reaction", "max_damage", "substeps"],
               "cutback": args.cutback}
-        for label, pr in (("mixed", binding.MIXED), ("fp64", binding.FP64)):
-            if label == "fp64" and args.no_fp64_compare:
+        runs = [("mixed", binding.MIXED), ("fp64", binding.FP64)] if prec == binding.MIXED else [("fp64", binding.FP64)]
+        for label, pr in runs:
+            if label == "fp64" and prec == binding.MIXED and args.no_fp64_compare:
                 continue
             lp[label] = load_path_run(prob, pr, args, binding, n_inc)
         print(json.dumps({"metric": METRIC, "load_path": lp}))

@@ -19,7 +19,10 @@ increment, stored sparsely: the history variable is a running maximum
 (Eq. A.2) and D is nondecreasing in it (Eq. A.1), so a Gauss point damaged
 at some increment stays damaged after it; `idx` lists the Gauss points
 damaged at the last stored increment and `D[n]` their damage after increment
-n+1 (every other Gauss point has D = 0 throughout).  `stopped` is the first
+n+1 (every other Gauss point has D = 0 throughout); with --kappa, `kappa[n]`
+holds their history variable after increment n+1 (to tell a history-band
+tie, reading A18, from a damage error; stored for c3p, left out of the
+larger c1 file).  `stopped` is the first
 increment the oracle could not converge (0 if none), `peak` the increment of
 the largest |reaction|.
 
@@ -29,7 +32,8 @@ stopped and resumed; `pack` builds the stored file from the parts.
 Usage:
   python tests/golden/make_golden.py run c3p [--post 12] [--parts DIR]
   python tests/golden/make_golden.py run c1 [--parts DIR]
-  python tests/golden/make_golden.py pack c3p|c1 [--parts DIR]
+  python tests/golden/make_golden.py pack c3p --kappa [--parts DIR]
+  python tests/golden/make_golden.py pack c1 [--parts DIR]
 """
 import argparse
 import glob
@@ -98,7 +102,7 @@ def run(name, parts, post, max_inc):
             return
 
 
-def pack(name, parts):
+def pack(name, parts, with_kappa):
     ps = _load_parts(parts, name)
     ok = [p for p in ps if not int(p["failed"])]
     stopped = next((int(p["n"]) for p in ps if int(p["failed"])), 0)
@@ -106,6 +110,7 @@ def pack(name, parts):
     Dlast = ok[-1]["D"]
     idx = np.flatnonzero(Dlast > 0).astype(np.int32)
     D = np.stack([p["D"][idx] for p in ok])
+    extra = {"kappa": np.stack([p["kappa"][idx] for p in ok])} if with_kappa else {}
     for p in ok:
         assert not np.any(np.delete(p["D"], idx) != 0.0)
     reaction = np.array([float(p["reaction"]) for p in ok])
@@ -113,7 +118,7 @@ def pack(name, parts):
                         newton=np.array([int(p["newton"]) for p in ok]),
                         max_D=np.array([float(p["D"].max()) for p in ok]),
                         n_gauss=len(Dlast), tol_newton=TOL, max_newton=MAX_NEWTON, stopped=stopped,
-                        peak=int(np.argmax(np.abs(reaction))) + 1)
+                        peak=int(np.argmax(np.abs(reaction))) + 1, **extra)
     print("%s: %d increments, %d damaged Gauss points of %d, peak at %d, stopped %d" %
           (name, len(ok), len(idx), len(Dlast), int(np.argmax(np.abs(reaction))) + 1, stopped))
 
@@ -125,8 +130,9 @@ if __name__ == "__main__":
     ap.add_argument("--parts", default=os.path.join(HERE, "parts"))
     ap.add_argument("--post", type=int, default=None, help="stop this many increments after the peak")
     ap.add_argument("--max-inc", type=int, default=10 ** 9)
+    ap.add_argument("--kappa", action="store_true", help="pack: also store the history variable")
     a = ap.parse_args()
     if a.cmd == "run":
         run(a.name, a.parts, a.post if a.post is not None else (12 if a.name == "c3p" else None), a.max_inc)
     else:
-        pack(a.name, a.parts)
+        pack(a.name, a.parts, a.kappa)

@@ -65,6 +65,7 @@ class PathRunner:
 
     def step(self, acc):
         lam = (self.inc + 1) / self.prob.n_increments
+        t_inc = time.perf_counter()
         self.ctx.begin_increment(lam)
         rep = self.b.IncrementReport()
         it = 0
@@ -87,6 +88,8 @@ class PathRunner:
                 self.ctx.commit_increment()
                 self.inc += 1
                 acc["increments"] += 1
+                acc["per_increment"].append([self.inc, round((time.perf_counter() - t_inc) * 1e3, 1), it,
+                                             r.krylov_iters, r.reaction])
                 acc["last_rel_u"] = r.res_u / max(r.ref_u, 1e-300)
                 acc["last_rel_e"] = r.res_e / max(r.ref_e, 1e-300)
                 return
@@ -109,7 +112,35 @@ def newton_line(inc, it, r, before):
 
 def new_acc():
     return dict(t_asm=0.0, t_sol=0.0, t_upd=0.0, n_asm=0, krylov=0, spmv=0, newton=0, increments=0,
-                last_rel_u=None, last_rel_e=None, step_ms=[])
+                last_rel_u=None, last_rel_e=None, step_ms=[], per_increment=[])
+
+
+def window_phases(per_inc):
+    """Split the timed increments by load-path phase, judged from the
+    reactions the run has seen so far (the peak is the largest |reaction|
+    up to the last timed increment): before the peak, within 2% of it, and
+    after it.  Per phase: increments, ms per increment, Newton iterations per
+    increment and Krylov steps per Newton iteration (medians)."""
+    if not per_inc:
+        return None
+    rmax = max(abs(v[4]) for v in per_inc)
+    ipk = max(range(len(per_inc)), key=lambda j: abs(per_inc[j][4]))
+    groups = {"pre_peak": [], "near_peak": [], "post_peak": []}
+    for j, v in enumerate(per_inc):
+        if abs(abs(v[4]) - rmax) <= 0.02 * rmax:
+            groups["near_peak"].append(v)
+        elif j > ipk:
+            groups["post_peak"].append(v)
+        else:
+            groups["pre_peak"].append(v)
+    out = {}
+    for k, vs in groups.items():
+        if vs:
+            out[k] = {"increments": [vs[0][0], vs[-1][0]], "count": len(vs),
+                      "ms_per_increment_median": statistics.median(v[1] for v in vs),
+                      "newton_per_increment_median": statistics.median(v[2] for v in vs),
+                      "krylov_per_newton_median": statistics.median(v[3] / max(v[2], 1) for v in vs)}
+    return out
 
 
 def algorithmic_bytes(prob, nnz, npairs, s_val):
@@ -202,6 +233,9 @@ def run_precision(prob, precision, args, binding):
         "krylov_iters": acc["krylov"], "spmv_launches": acc["spmv"],
         "spmv_per_newton_step": acc["spmv"] / max(acc["newton"], 1),
         "final_rel_residual": [acc["last_rel_u"], acc["last_rel_e"]],
+        "per_increment": {"columns": ["increment", "ms", "newton", "krylov", "reaction"],
+                          "rows": acc["per_increment"]},
+        "window_phases": window_phases(acc["per_increment"]),
         "kernel_ms": {"gauss_point": kt[0], "node_assembly": kt[1], "spmv": kt[2], "block_jacobi": kt[3]},
         "assembly_bytes": asm_b, "spmv_bytes": spmv_b,
         "assembly_gbs": asm_b / ((kt[0] + kt[1]) * 1e-3) / 1e9,

@@ -328,7 +328,13 @@ __device__ __forceinline__ void coupling_terms(const double* r, const double ga[
 
 // tangent block d f_a / d x_b and (want_f) the internal force on node a of
 // one element at Gauss point g: one read of the record serves both;
-// gradients in FP64, block arithmetic in the working precision T
+// gradients in FP64, block arithmetic in the working precision T.
+//
+// Displacement block: with A = sum_g (1 - D) s_e wJ grad N_a (x) grad N_b,
+// K^uu_ab = lam A + mu A^T + mu tr(A) I (Eq. 11a for an isotropic C), so the
+// Gauss-point loop accumulates A in the block's uu entries (one product per
+// entry) and finish_uu applies lam / mu once after the loop.  The coupling
+// variant adds its own uu terms per Gauss point and keeps the direct form.
 template <int DIM, typename T, bool CPL>
 __device__ __forceinline__ void block_and_force(const double* __restrict__ rv, int g, int la, int lb,
                                                 const MatParams& mp, bool want_k, bool want_f,
@@ -372,7 +378,14 @@ __device__ __forceinline__ void block_and_force(const double* __restrict__ rv, i
   T dab = 0;
 #pragma unroll
   for (int d = 0; d < DIM; ++d) dab += ta[d] * tb[d];
-  if (DIM == 1) {
+  if constexpr (!CPL) {
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) {
+      const T ca = cuu * ta[i];
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) blk[i][j] += ca * tb[j];
+    }
+  } else if (DIM == 1) {
     blk[0][0] += cuu * (T)mp.E * ta[0] * tb[0];
   } else {
     const T lam = (T)mp.lam, mu = (T)mp.mu;
@@ -395,6 +408,30 @@ __device__ __forceinline__ void block_and_force(const double* __restrict__ rv, i
   }
   blk[DIM][DIM] += (T)r[RC::CEE] * tNa * (T)Nb + (T)r[RC::CGP] * (T)ga_geb * (T)Nb + (T)r[RC::CG] * dab;
   if constexpr (CPL) coupling_terms<DIM, T>(r, ga, gbv, Nb, mp, want_k, want_f, blk, fa);
+}
+
+// after the Gauss-point loop: K^uu_ab = lam A + mu A^T + mu tr(A) I from the
+// accumulated A (1D: E A); the coupling variant's blocks are already final
+template <int DIM, typename T, bool CPL>
+__device__ __forceinline__ void finish_uu(T blk[DIM + 1][DIM + 1], const MatParams& mp) {
+  if constexpr (CPL) return;
+  if (DIM == 1) {
+    blk[0][0] *= (T)mp.E;
+    return;
+  }
+  T a[DIM][DIM];
+  T tr = 0;
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) {
+    tr += blk[i][i];
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) a[i][j] = blk[i][j];
+  }
+  const T lam = (T)mp.lam, mu = (T)mp.mu;
+#pragma unroll
+  for (int i = 0; i < DIM; ++i)
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) blk[i][j] = lam * a[i][j] + mu * a[j][i] + (i == j ? mu * tr : (T)0);
 }
 
 // ---------------------------------------------------------------------------
@@ -529,6 +566,7 @@ __device__ __forceinline__ void node_block(int64_t blk, const NodeArgs& A, const
       }
       __syncthreads();
     }
+    if (WANT_K) finish_uu<DIM, double, CPL>(blk, mp);
     // phase 2: blocks to LDS, position -> local node table
 #pragma unroll
     for (int q = 0; q < NEN; ++q) s_slot[(slot * NEN + k) * L + b * NEN + q] = -1;
@@ -702,6 +740,7 @@ __global__ void element_blocks_kernel(int64_t e0, int64_t e1, const double* __re
   for (int g = 0; g < E::NGP; ++g)
     block_and_force<DIM, double, CPL>(rec + (e * E::NGP + g) * RC::STRIDE, g, la, lb, mp, Ke != nullptr,
                                       lb == 0, blk, f);
+  if (Ke) finish_uu<DIM, double, CPL>(blk, mp);
   if (Ke) {
     double* out = Ke + el * NL * NL;
 #pragma unroll

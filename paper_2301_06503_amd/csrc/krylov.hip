@@ -271,12 +271,25 @@ __global__ void __launch_bounds__(BS) spmv_kernel(int64_t n_nodes, const int32_t
   spmv_body<T, ND, G, MODE, NP>(blockIdx.x, gridDim.x, n_nodes, row_ptr, nbr_ptr, nbr, vals, x, y, w, sc, part);
 }
 
+// The one-workgroup scalar kernels end in one thread's chain of dependent
+// reads and writes of the solve's scalars (forward substitutions, breakdown
+// tests).  They run on a copy of the scalars in LDS, staged by the whole
+// workgroup and written back after: the same arithmetic on the same values,
+// without a device-memory round trip per dependent access.
+__device__ __forceinline__ void stage_scalars(double* s, const double* __restrict__ sc) {
+  for (int i = threadIdx.x; i < KSCAL_DOUBLES; i += BS) s[i] = sc[i];
+  __syncthreads();
+}
+__device__ __forceinline__ void unstage_scalars(double* __restrict__ sc, const double* s) {
+  __syncthreads();
+  for (int i = threadIdx.x; i < KSCAL_DOUBLES; i += BS) sc[i] = s[i];
+}
+
 // finishing reductions (one workgroup): fixed-order sums of the partials and
 // the BiCGSTAB scalar updates.  KIND 1: alpha; 2: omega; 3: after the x/r
 // update (rho, norms, convergence, beta); 4: after init.
 template <int KIND, int NQ>
-__global__ void __launch_bounds__(BS) scalar_kernel(int nblk, const double* __restrict__ part,
-                                                    double* __restrict__ sc) {
+__device__ __forceinline__ void scalar_body(int nblk, const double* __restrict__ part, double* sc) {
   __shared__ double sm[NQ][BS];
   if (KIND != 4 && sc[K_DONE] != 0.0) return;
   double acc[NQ];
@@ -358,6 +371,15 @@ __global__ void __launch_bounds__(BS) scalar_kernel(int nblk, const double* __re
       sc[K_DONE] = 0.0;
     }
   }
+}
+
+template <int KIND, int NQ>
+__global__ void __launch_bounds__(BS) scalar_kernel(int nblk, const double* __restrict__ part,
+                                                    double* __restrict__ sc) {
+  __shared__ double s_sc[KSCAL_DOUBLES];
+  stage_scalars(s_sc, sc);
+  scalar_body<KIND, NQ>(nblk, part, s_sc);
+  unstage_scalars(sc, s_sc);
 }
 
 // p = r + beta (p - omega v); ph = M^-1 p    (one thread per node)
@@ -977,7 +999,10 @@ __global__ void __launch_bounds__(BS) idr_init_kernel(int64_t n, const double* _
 template <int S>
 __global__ void __launch_bounds__(BS) idr_init_scalar(int nblk, const double* __restrict__ part,
                                                       double* __restrict__ sc) {
-  idr_init_scalar_body<S>(nblk, part, sc);
+  __shared__ double s_sc[KSCAL_DOUBLES];
+  stage_scalars(s_sc, sc);
+  idr_init_scalar_body<S>(nblk, part, s_sc);
+  unstage_scalars(sc, s_sc);
 }
 template <typename T, int ND, int S, int K>
 __global__ void __launch_bounds__(BS) idr_dir_kernel(int64_t n_nodes, const T* __restrict__ minv,
@@ -989,7 +1014,10 @@ __global__ void __launch_bounds__(BS) idr_dir_kernel(int64_t n_nodes, const T* _
 template <int S>
 __global__ void __launch_bounds__(BS) idr_g_scalar(int nblk, const double* __restrict__ part,
                                                    double* __restrict__ sc, int k, double pnorm2) {
-  idr_g_scalar_body<S>(nblk, part, sc, k, pnorm2);
+  __shared__ double s_sc[KSCAL_DOUBLES];
+  stage_scalars(s_sc, sc);
+  idr_g_scalar_body<S>(nblk, part, s_sc, k, pnorm2);
+  unstage_scalars(sc, s_sc);
 }
 template <typename T, int ND, int S, int K>
 __global__ void __launch_bounds__(BS) idr_upd_kernel(int64_t n_nodes, const T* __restrict__ minv,
@@ -1001,11 +1029,17 @@ __global__ void __launch_bounds__(BS) idr_upd_kernel(int64_t n_nodes, const T* _
 }
 __global__ void __launch_bounds__(BS) idr_r_scalar(int nblk, const double* __restrict__ part,
                                                    double* __restrict__ sc) {
-  idr_r_scalar_body(nblk, part, sc);
+  __shared__ double s_sc[KSCAL_DOUBLES];
+  stage_scalars(s_sc, sc);
+  idr_r_scalar_body(nblk, part, s_sc);
+  unstage_scalars(sc, s_sc);
 }
 __global__ void __launch_bounds__(BS) idr_om_scalar(int nblk, const double* __restrict__ part,
                                                     double* __restrict__ sc) {
-  idr_om_scalar_body(nblk, part, sc);
+  __shared__ double s_sc[KSCAL_DOUBLES];
+  stage_scalars(s_sc, sc);
+  idr_om_scalar_body(nblk, part, s_sc);
+  unstage_scalars(sc, s_sc);
 }
 template <int ND, int S>
 __global__ void __launch_bounds__(BS) idr_om_kernel(int64_t n, double* __restrict__ r, double* __restrict__ x,
@@ -1016,7 +1050,10 @@ __global__ void __launch_bounds__(BS) idr_om_kernel(int64_t n, double* __restric
 template <int S>
 __global__ void __launch_bounds__(BS) idr_f_scalar(int nblk, const double* __restrict__ part,
                                                    double* __restrict__ sc) {
-  idr_f_scalar_body<S>(nblk, part, sc);
+  __shared__ double s_sc[KSCAL_DOUBLES];
+  stage_scalars(s_sc, sc);
+  idr_f_scalar_body<S>(nblk, part, s_sc);
+  unstage_scalars(sc, s_sc);
 }
 
 // --- batched kernels: one launch over the requests of a serving batch -------
@@ -1073,7 +1110,10 @@ template <int S>
 __global__ void __launch_bounds__(BS) idr_g_scalar_batch(const KSlot* __restrict__ ks, int k,
                                                          const double* __restrict__ part) {
   const KSlot& q = ks[blockIdx.x];
-  idr_g_scalar_body<S>(q.nblk[FAM_SPMV], part + q.blk0[FAM_SPMV] * (S + 1), q.sc, k, (double)q.n / 3.0);
+  __shared__ double s_sc[KSCAL_DOUBLES];
+  stage_scalars(s_sc, q.sc);
+  idr_g_scalar_body<S>(q.nblk[FAM_SPMV], part + q.blk0[FAM_SPMV] * (S + 1), s_sc, k, (double)q.n / 3.0);
+  unstage_scalars(q.sc, s_sc);
 }
 template <typename T, int ND, int S, int K>
 __global__ void __launch_bounds__(BS) idr_upd_batch(const KSlot* __restrict__ ks, int nks,
@@ -1085,12 +1125,18 @@ __global__ void __launch_bounds__(BS) idr_upd_batch(const KSlot* __restrict__ ks
 __global__ void __launch_bounds__(BS) idr_r_scalar_batch(const KSlot* __restrict__ ks,
                                                          const double* __restrict__ part) {
   const KSlot& q = ks[blockIdx.x];
-  idr_r_scalar_body(q.nblk[FAM_NODE], part + q.blk0[FAM_NODE] * 2, q.sc);
+  __shared__ double s_sc[KSCAL_DOUBLES];
+  stage_scalars(s_sc, q.sc);
+  idr_r_scalar_body(q.nblk[FAM_NODE], part + q.blk0[FAM_NODE] * 2, s_sc);
+  unstage_scalars(q.sc, s_sc);
 }
 __global__ void __launch_bounds__(BS) idr_om_scalar_batch(const KSlot* __restrict__ ks,
                                                           const double* __restrict__ part) {
   const KSlot& q = ks[blockIdx.x];
-  idr_om_scalar_body(q.nblk[FAM_SPMV], part + q.blk0[FAM_SPMV] * 2, q.sc);
+  __shared__ double s_sc[KSCAL_DOUBLES];
+  stage_scalars(s_sc, q.sc);
+  idr_om_scalar_body(q.nblk[FAM_SPMV], part + q.blk0[FAM_SPMV] * 2, s_sc);
+  unstage_scalars(q.sc, s_sc);
 }
 template <int ND, int S>
 __global__ void __launch_bounds__(BS) idr_om_batch(const KSlot* __restrict__ ks, int nks,
@@ -1103,7 +1149,10 @@ template <int S>
 __global__ void __launch_bounds__(BS) idr_f_scalar_batch(const KSlot* __restrict__ ks,
                                                           const double* __restrict__ part) {
   const KSlot& q = ks[blockIdx.x];
-  idr_f_scalar_body<S>(q.nblk[FAM_DOF], part + q.blk0[FAM_DOF] * (2 + S), q.sc);
+  __shared__ double s_sc[KSCAL_DOUBLES];
+  stage_scalars(s_sc, q.sc);
+  idr_f_scalar_body<S>(q.nblk[FAM_DOF], part + q.blk0[FAM_DOF] * (2 + S), s_sc);
+  unstage_scalars(q.sc, s_sc);
 }
 
 // compute units of the current device

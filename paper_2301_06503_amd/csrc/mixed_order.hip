@@ -266,18 +266,14 @@ __device__ __forceinline__ void q_block_force(const double* __restrict__ r, int 
     fa[DIM + 1] += r[RC::FR] * Nea;
   }
   if (!want_k) return;
+  // uu entries accumulate A = sum_g (1 - D) s_e wJ grad N_a (x) grad N_b;
+  // q_finish_uu forms K^uu_ab = lam A + mu A^T + mu tr(A) I (1D: E A)
   const double cuu = r[RC::CUU];
-  double dab = 0.0;
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) dab += ga[d] * gbv[d];
-  if (DIM == 1) {
-    blk[0][0] += cuu * mp.E * ga[0] * gbv[0];
-  } else {
+  for (int i = 0; i < DIM; ++i) {
+    const double ca = cuu * ga[i];
 #pragma unroll
-    for (int i = 0; i < DIM; ++i)
-#pragma unroll
-      for (int j = 0; j < DIM; ++j)
-        blk[i][j] += cuu * (mp.lam * ga[i] * gbv[j] + mp.mu * ga[j] * gbv[i] + (i == j ? mp.mu * dab : 0.0));
+    for (int j = 0; j < DIM; ++j) blk[i][j] += ca * gbv[j];
   }
   const double cueN = r[RC::CUE] * Neb;
 #pragma unroll
@@ -293,6 +289,24 @@ __device__ __forceinline__ void q_block_force(const double* __restrict__ r, int 
 #pragma unroll
   for (int d = 0; d < DIM; ++d) eab += ea[d] * eb[d];
   blk[DIM][DIM] += r[RC::CEE] * Nea * Neb + r[RC::CGP] * ea_geb * Neb + r[RC::CG] * eab;
+}
+
+template <int DIM> __device__ __forceinline__ void q_finish_uu(double blk[DIM + 1][DIM + 1], const MatParams& mp) {
+  if (DIM == 1) {
+    blk[0][0] *= mp.E;
+    return;
+  }
+  double a[DIM][DIM], tr = 0.0;
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) {
+    tr += blk[i][i];
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) a[i][j] = blk[i][j];
+  }
+#pragma unroll
+  for (int i = 0; i < DIM; ++i)
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) blk[i][j] = mp.lam * a[i][j] + mp.mu * a[j][i] + (i == j ? mp.mu * tr : 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -343,6 +357,7 @@ __global__ void __launch_bounds__(QBLOCK) q_node_kernel(NodeArgs A, MatParams mp
         for (int j = 0; j < ND; ++j) blk[i][j] = 0.0;
       for (int g = 0; g < NGP; ++g)
         q_block_force<DIM>(A.rec + (e * NGP + g) * RC::STRIDE, g, la, lb, mp, true, false, blk, f);
+      q_finish_uu<DIM>(blk, mp);
 #pragma unroll
       for (int i = 0; i < ND; ++i)
 #pragma unroll
@@ -439,6 +454,7 @@ __global__ void q_element_blocks_kernel(int64_t e0, int64_t e1, const double* __
   for (int i = 0; i < DIM + 2; ++i) f[i] = 0.0;
   for (int g = 0; g < E::NGP; ++g)
     q_block_force<DIM>(rec + (e * E::NGP + g) * RC::STRIDE, g, la, lb, mp, Ke != nullptr, lb == 0, blk, f);
+  q_finish_uu<DIM>(blk, mp);
   if (Ke) {
     double* out = Ke + el * NL * NL;
 #pragma unroll

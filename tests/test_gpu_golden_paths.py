@@ -11,7 +11,8 @@ only oracle/:
        increment 143 (at 144 the oracle's Newton iteration does not converge).
 
 The GPU runs the same increments with Newton corrections solved accurately
-(IDR(8) to 1e-8; multigrid on the beam, block-Jacobi on the plate) and must
+(IDR(8) to 1e-8; multigrid on the beam, block-Jacobi on the plate), Newton to
+1e-12 / 1e-11 (beam / plate) in FP64 and 1e-10 in mixed precision, and must
 match the damage of every Gauss point after every committed increment to
 1e-8 (FP64) and 1e-7 (mixed precision), and the reactions to 1e-6.  Gauss
 points at a band tie (reading A18: the history or damage band edge of
@@ -69,18 +70,24 @@ def _ties(g, n, diff, kap, m, bound):
     return ties
 
 
-CASES = [("c3p", B.FP64, None), ("c3p", B.MIXED, None), ("c1", B.FP64, None), ("c1", B.MIXED, 60)]
+# (workload, precision, increments compared (None: all stored), Newton tolerance)
+CASES = [("c3p", B.FP64, None, 1e-12), ("c3p", B.MIXED, None, 1e-10), ("c1", B.FP64, None, 1e-11),
+         ("c1", B.MIXED, 60, 1e-10)]
 
 
-@pytest.mark.parametrize("name,precision,limit", CASES)
-def test_load_path_vs_stored_oracle(name, precision, limit):
+@pytest.mark.parametrize("name,precision,limit,tol_newton", CASES)
+def test_load_path_vs_stored_oracle(name, precision, limit, tol_newton):
     g = _golden(name)
     prob = W.config(name)
     n_inc = len(g["reaction"]) if limit is None else min(limit, len(g["reaction"]))
     print("case: %s precision %d, %d increments (stored: %d, peak at %d, oracle stopped at %d)"
           % (name, precision, n_inc, len(g["reaction"]), int(g["peak"]), int(g["stopped"])), flush=True)
     ctx = context(prob, precision)
-    opts = B.solver_opts(max_newton=40, tol_newton=1e-10, tol_krylov=1e-8, max_krylov=50000)
+    # FP64 runs Newton past the oracle's 1e-10 test: the oracle's last
+    # (exact, quadratic) step lands far below it, and on the softening branch
+    # a residual of 1e-10 still leaves damage differences near 1e-8 (the
+    # post-peak plate stalls before 1e-12 with these inexact corrections)
+    opts = B.solver_opts(max_newton=60, tol_newton=tol_newton, tol_krylov=1e-8, max_krylov=50000)
     bound = 1e-8 if precision == B.FP64 else 1e-7
     errs, tie = [], 0
     for n in range(n_inc):
@@ -102,6 +109,8 @@ def test_load_path_vs_stored_oracle(name, precision, limit):
         assert abs(rep["reaction"] - ro) <= 1e-6 * abs(ro), "increment %d reaction" % (n + 1)
     print("max damage error over %d increments: %.3e (band ties beyond the bound, reported apart: %d)"
           % (n_inc, max(errs), tie))
+    # ties are isolated points, not a population
+    assert tie <= 0.01 * len(g["idx"]) * n_inc
     if n_inc >= int(g["peak"]) + 3:
         assert max(g["max_D"][:n_inc]) > 0.99          # the compared path reaches the softening branch
     ctx.close()

@@ -181,7 +181,7 @@ def run_precision(prob, precision, args, binding):
     torch.cuda.synchronize()
     setup_s = time.time() - t0
     log("setup %.2fs precision=%s ndof=%d nGP=%d" % (setup_s, precision, ctx.ndof, ctx.ngauss))
-    opts = binding.solver_opts(max_newton=40, tol_newton=1e-8, tol_krylov=args.tol_krylov,
+    opts = binding.solver_opts(max_newton=args.max_newton, tol_newton=1e-8, tol_krylov=args.tol_krylov,
                                max_krylov=args.max_krylov, check_every=32,
                                krylov_method=binding.KRYLOV_BICGSTAB if args.krylov == "bicgstab"
                                else binding.KRYLOV_IDRS, idr_s=args.idr_s,
@@ -270,7 +270,7 @@ def load_path_run(prob, precision, args, binding, n_inc):
     ctx = binding.Context(device=0, precision=precision)
     ctx.setup_problem(prob)
     torch.cuda.synchronize()
-    opts = binding.solver_opts(max_newton=40, tol_newton=1e-8, tol_krylov=args.tol_krylov,
+    opts = binding.solver_opts(max_newton=args.max_newton, tol_newton=1e-8, tol_krylov=args.tol_krylov,
                                max_krylov=args.max_krylov, check_every=32, krylov_method=binding.KRYLOV_IDRS,
                                idr_s=args.idr_s, forcing=binding.FORCING_ADAPTIVE,
                                precond={"default": binding.PRECOND_DEFAULT, "bj": binding.PRECOND_BLOCK_JACOBI,
@@ -519,6 +519,7 @@ def main():
     ap.add_argument("--fixed-forcing", action="store_true",
                     help="solve every Newton correction to --tol-krylov (default: adaptive forcing)")
     ap.add_argument("--max-krylov", type=int, default=20000)
+    ap.add_argument("--max-newton", type=int, default=40)
     ap.add_argument("--kernel-reps", type=int, default=5)
     ap.add_argument("--serving-seconds", type=float, default=30.0)
     ap.add_argument("--coupling", type=int, default=0, choices=[0, 1],

@@ -92,6 +92,10 @@ class PathRunner:
                                              r.krylov_iters, r.reaction])
                 acc["last_rel_u"] = r.res_u / max(r.ref_u, 1e-300)
                 acc["last_rel_e"] = r.res_e / max(r.ref_e, 1e-300)
+                acc["zone_ms"] += r.t_zone_ms
+                acc["zone_factorizations"] += r.zone_factorizations
+                acc["zone_restarts"] += r.zone_restarts
+                acc["backtracks"] += r.backtracks
                 return
             it += 1
             acc["newton"] += 1
@@ -103,16 +107,27 @@ def newton_line(inc, it, r, before):
     """One log line per Newton iteration: residuals of the assembly, then the
     linear solve that followed it (steps, reached relative residual, status)."""
     return ("  inc %d it %d |R_u|/|F_u|=%.3e |R_e|/|F_e|=%.3e krylov=%d spmv=%d rel=(%.1e, %.1e) "
-            "status=%d inexact=%d restarts=%d asm=%.3fms solve=%.1fms" % (
+            "status=%d inexact=%d restarts=%d backtracks=%d zone<=%d asm=%.3fms solve=%.1fms "
+            "(so far: zone setup %.1fms, %d factorizations, %d restarts without zone)" % (
                 inc, it, r.res_u / max(r.ref_u, 1e-300), r.res_e / max(r.ref_e, 1e-300),
                 r.krylov_iters - before[4], r.krylov_spmv - before[5], r.krylov_rel_u, r.krylov_rel_e,
-                r.krylov_status, r.inexact_solves, r.restarts, r.t_assembly_ms - before[0],
-                r.t_solve_ms - before[1]))
+                r.krylov_status, r.inexact_solves, r.restarts, r.backtracks, r.zone_dofs,
+                r.t_assembly_ms - before[0], r.t_solve_ms - before[1], r.t_zone_ms, r.zone_factorizations,
+                r.zone_restarts))
+
+
+def zone_opts(args, binding):
+    """Process-zone and line-search options of the Newton solves."""
+    return dict(process_zone={"default": binding.ZONE_DEFAULT, "off": binding.ZONE_OFF,
+                              "every": binding.ZONE_EVERY_TANGENT}[args.zone],
+                zone_damage=args.zone_damage,
+                line_search=binding.LINE_SEARCH_OFF if args.no_line_search else binding.LINE_SEARCH_DEFAULT)
 
 
 def new_acc():
     return dict(t_asm=0.0, t_sol=0.0, t_upd=0.0, n_asm=0, krylov=0, spmv=0, newton=0, increments=0,
-                last_rel_u=None, last_rel_e=None, step_ms=[], per_increment=[])
+                last_rel_u=None, last_rel_e=None, step_ms=[], per_increment=[], zone_ms=0.0,
+                zone_factorizations=0, zone_restarts=0, backtracks=0)
 
 
 def window_phases(per_inc):
@@ -187,7 +202,8 @@ def run_precision(prob, precision, args, binding):
                                else binding.KRYLOV_IDRS, idr_s=args.idr_s,
                                forcing=binding.FORCING_FIXED if args.fixed_forcing else binding.FORCING_ADAPTIVE,
                                precond={"default": binding.PRECOND_DEFAULT, "bj": binding.PRECOND_BLOCK_JACOBI,
-                                        "amg": binding.PRECOND_AMG}[args.precond])
+                                        "amg": binding.PRECOND_AMG}[args.precond],
+                               **zone_opts(args, binding))
     runner = PathRunner(ctx, prob, opts, binding)
     warm = new_acc()
     for i in range(args.warmup):
@@ -229,7 +245,11 @@ def run_precision(prob, precision, args, binding):
         "increments_in_timed_region": acc["increments"], "increments_committed": runner.inc,
         "assembly_gp_per_s_device": ng * acc["n_asm"] / (acc["t_asm"] / 1e3) if acc["t_asm"] > 0 else None,
         "phase_ms_per_increment": {"assembly": acc["t_asm"] / args.steps, "solve": acc["t_sol"] / args.steps,
-                                   "update": acc["t_upd"] / args.steps},
+                                   "update": acc["t_upd"] / args.steps,
+                                   "zone_setup_within_solve": acc["zone_ms"] / args.steps},
+        "process_zone": {"factorizations": acc["zone_factorizations"],
+                         "increments_restarted_without_zone": acc["zone_restarts"],
+                         "line_search_halvings": acc["backtracks"]},
         "krylov_iters": acc["krylov"], "spmv_launches": acc["spmv"],
         "spmv_per_newton_step": acc["spmv"] / max(acc["newton"], 1),
         "final_rel_residual": [acc["last_rel_u"], acc["last_rel_e"]],
@@ -249,7 +269,8 @@ def run_precision(prob, precision, args, binding):
         "setup_ms": setup_s * 1e3,   # mesh upload, CSR pattern build (once per mesh), material, Dirichlet set
         "solver": {"krylov": args.krylov, "idr_s": args.idr_s if args.krylov == "idr" else None,
                    "forcing": "fixed" if args.fixed_forcing else "adaptive", "tol_krylov": args.tol_krylov,
-                   "precond": args.precond},
+                   "precond": args.precond, "process_zone": args.zone, "zone_damage": args.zone_damage,
+                   "line_search": not args.no_line_search},
     }
     ctx.close()
     del ctx
@@ -276,7 +297,7 @@ def load_path_run(prob, precision, args, binding, n_inc):
                                precond={"default": binding.PRECOND_DEFAULT, "bj": binding.PRECOND_BLOCK_JACOBI,
                                         "amg": binding.PRECOND_AMG}[args.precond],
                                max_increment_krylov=args.max_increment_krylov,
-                               max_increment_seconds=args.max_increment_seconds)
+                               max_increment_seconds=args.max_increment_seconds, **zone_opts(args, binding))
     incs = []
     stop = None
     keys = ("newton_iters", "n_assemblies", "krylov_iters", "t_assembly_ms", "t_solve_ms")
@@ -516,6 +537,14 @@ def main():
     ap.add_argument("--idr-s", type=int, default=8)
     ap.add_argument("--precond", default="default", choices=["default", "bj", "amg"],
                     help="block-Jacobi or aggregation multigrid (IDR only); the default is multigrid on 3D meshes")
+    ap.add_argument("--zone", default="default", choices=["default", "off", "every"],
+                    help="dense process-zone solve in the multigrid preconditioner: default (inverse kept while "
+                         "the zone's nodes stay the same within an increment), off, or every (rebuilt for every "
+                         "tangent)")
+    ap.add_argument("--zone-damage", type=float, default=0.999,
+                    help="trial damage from which a loading element joins the process zone")
+    ap.add_argument("--no-line-search", action="store_true",
+                    help="full Newton steps (no backtracking on a correction that blows the residual up)")
     ap.add_argument("--fixed-forcing", action="store_true",
                     help="solve every Newton correction to --tol-krylov (default: adaptive forcing)")
     ap.add_argument("--max-krylov", type=int, default=20000)

@@ -171,7 +171,8 @@ typedef struct lgdm_solver_opts {
                                      values round up to the next of these, max 8) */
   int32_t forcing;         /* LGDM_FORCING_ADAPTIVE                                 */
   int32_t precond;         /* LGDM_PRECOND_DEFAULT                                  */
-  int32_t reserved;        /* must be 0                                             */
+  int32_t process_zone;    /* LGDM_ZONE_DEFAULT: with the multigrid preconditioner,
+                              the dense process-zone solve (below)                  */
   int64_t max_increment_krylov;  /* 0 = no bound.  Krylov iterations summed over the
                                     solves of one increment (lgdm_begin_increment to
                                     commit / abort): each solve is limited to what is
@@ -187,6 +188,11 @@ typedef struct lgdm_solver_opts {
                                     solve that runs out returns its best iterate,
                                     and the next Newton iteration returns
                                     LGDM_ERR_NOT_CONVERGED as above               */
+  int32_t line_search;     /* LGDM_LINE_SEARCH_DEFAULT: backtracking on a Newton
+                              correction that blows the residual up (below)        */
+  double zone_damage;      /* 0.999  trial damage from which a loading element
+                              joins the process zone (below); values outside
+                              (0, 1) select the default                            */
 } lgdm_solver_opts;
 
 /* Tolerance of the linear solves inside Newton (lgdm_newton_iteration,
@@ -203,6 +209,44 @@ typedef struct lgdm_solver_opts {
  * lgdm_solve_linear always solves to tol_krylov.  Convergence of Newton is
  * judged on the FP64 residual either way. */
 enum { LGDM_FORCING_ADAPTIVE = 0, LGDM_FORCING_FIXED = 1 };
+
+/* Process zone of the multigrid preconditioner (3D meshes).  Where damaged
+ * Gauss points load in the current Newton iterate, the consistent tangent's
+ * softening terms (the D' chi terms of Eqs. 11b and 11d) make S K indefinite
+ * on those elements, and neither the smoother nor the rigid-body coarse space
+ * of the cycle represents those modes.  With LGDM_ZONE_DEFAULT the
+ * preconditioner solves that zone exactly before the cycle:
+ *   zone   the nodes of the elements with a loading Gauss point of trial
+ *          damage >= zone_damage (raised tenfold closer to 1, twice at most,
+ *          while it exceeds 24,576 unknowns; no zone beyond that);
+ *   apply  x_z = Z^-1 b_z with Z the zone's block of S K (dense LU with
+ *          partial pivoting and explicit inverse, rocSOLVER getrf/getri,
+ *          applied as one matrix-vector product); r = b - S K x_z;
+ *          out = x_z + (multigrid cycle)(r).
+ * Inside a Newton increment, Z^-1 is rebuilt only when the zone's node set
+ * changes (a later tangent of the increment with the same zone keeps it; r
+ * and the cycle always use the current tangent); LGDM_ZONE_EVERY_TANGENT
+ * rebuilds it for every tangent, and lgdm_solve_linear always does.
+ * Should Newton with the zone stop reducing the merit of the line search
+ * (no new smallest value in 5 iterations), the increment restarts from its
+ * beginning without the zone (zone_restarts in the report).
+ * The zone's dense block is allocated through the context's allocator the
+ * first time a zone of that size occurs (up to 4.8 GB) and kept.
+ * LGDM_ZONE_OFF: the plain cycle. */
+enum { LGDM_ZONE_DEFAULT = 0, LGDM_ZONE_OFF = 1, LGDM_ZONE_EVERY_TANGENT = 2 };
+
+/* Safeguard of the Newton corrections (lgdm_newton_iteration,
+ * lgdm_solve_increment; the batch takes full steps).  With the merit
+ * phi = (||R_u|| / ||F_u||)^2 + (||R_ebar|| / ||F_ebar||)^2 of an assembly,
+ * LGDM_LINE_SEARCH_DEFAULT halves the last correction (x -= alpha/2 delta,
+ * one more assembly each) while phi exceeds 4 times its value before that
+ * correction, at most 4 times (alpha >= 1/16); the iterate is then kept
+ * whatever phi is.  A correction that at most doubles the residual is taken
+ * whole, so increments that converge with full steps are not changed.  The
+ * solution of an increment does not depend on the path to it: the history
+ * variable of a trial state is max(kappa_n, eeq(trial)) (Eq. A.2).
+ * LGDM_LINE_SEARCH_OFF: full steps (Algorithm 2 as written). */
+enum { LGDM_LINE_SEARCH_DEFAULT = 0, LGDM_LINE_SEARCH_OFF = 1 };
 
 /* Per-increment / per-iteration report (the paper's time-per-iteration split
  * into assembly, solve and variable update, Sec. 3.1). */
@@ -230,7 +274,13 @@ typedef struct lgdm_increment_report {
   int64_t krylov_spmv;     /* operator applications (SpMV) in the linear solves     */
   int32_t precond_fallbacks; /* multigrid solves without progress, repeated with
                                 block-Jacobi                                        */
-  int32_t reserved;
+  int32_t backtracks;      /* halvings of a Newton correction (line search)         */
+  int64_t zone_dofs;       /* largest process zone solved densely in the solves
+                              (unknowns; 0: none), see LGDM_ZONE_DEFAULT           */
+  double t_zone_ms;        /* host time choosing and factoring the process zones,
+                              part of t_solve_ms                                    */
+  int32_t zone_factorizations; /* process-zone blocks factored                      */
+  int32_t zone_restarts;   /* increments restarted without the zone                */
 } lgdm_increment_report;
 
 /* View of the assembled tangent.  Device pointers owned by the context. */

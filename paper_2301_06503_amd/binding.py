@@ -21,6 +21,8 @@ LGDM_ERR_NOT_CONVERGED, LGDM_ERR_NAN, LGDM_ERR_BREAKDOWN, LGDM_ERR_STATE = 4, 5,
 FP64, MIXED = 0, 1
 FIELD_X, FIELD_KAPPA, FIELD_DAMAGE, FIELD_KAPPA_TRIAL, FIELD_DAMAGE_TRIAL = 0, 1, 2, 3, 4
 FIELD_RESIDUAL, FIELD_REACTION, FIELD_EEQ = 5, 6, 7
+ZONE_DEFAULT, ZONE_OFF, ZONE_EVERY_TANGENT = 0, 1, 2
+LINE_SEARCH_DEFAULT, LINE_SEARCH_OFF = 0, 1
 
 LGDM_ERR_BUSY = 8
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "OOM", 3: "DEVICE", 4: "NOT_CONVERGED", 5: "NAN",
@@ -58,8 +60,9 @@ class SolverOpts(ctypes.Structure):
                 ("tol_newton", ctypes.c_double), ("tol_krylov", ctypes.c_double),
                 ("check_every", ctypes.c_int32), ("max_restarts", ctypes.c_int32),
                 ("krylov_method", ctypes.c_int32), ("idr_s", ctypes.c_int32),
-                ("forcing", ctypes.c_int32), ("precond", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("max_increment_krylov", ctypes.c_int64), ("max_increment_seconds", ctypes.c_double)]
+                ("forcing", ctypes.c_int32), ("precond", ctypes.c_int32), ("process_zone", ctypes.c_int32),
+                ("max_increment_krylov", ctypes.c_int64), ("max_increment_seconds", ctypes.c_double),
+                ("line_search", ctypes.c_int32), ("zone_damage", ctypes.c_double)]
 
 
 class IncrementReport(ctypes.Structure):
@@ -71,7 +74,9 @@ class IncrementReport(ctypes.Structure):
         ("n_assemblies", ctypes.c_int32), ("restarts", ctypes.c_int32),
         ("krylov_status", ctypes.c_int32), ("inexact_solves", ctypes.c_int32),
         ("krylov_rel_u", ctypes.c_double), ("krylov_rel_e", ctypes.c_double),
-        ("krylov_spmv", ctypes.c_int64), ("precond_fallbacks", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+        ("krylov_spmv", ctypes.c_int64), ("precond_fallbacks", ctypes.c_int32), ("backtracks", ctypes.c_int32),
+        ("zone_dofs", ctypes.c_int64), ("t_zone_ms", ctypes.c_double),
+        ("zone_factorizations", ctypes.c_int32), ("zone_restarts", ctypes.c_int32)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

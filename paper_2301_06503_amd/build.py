@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblgdm.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["element.hip", "pattern.hip", "krylov.hip", "amg.hip", "capi.cpp", "batch.cpp", "noalloc.hip", "mixed_order.hip"]
+SOURCES = ["element.hip", "pattern.hip", "krylov.hip", "amg.hip", "capi.cpp", "batch.cpp", "noalloc.hip", "mixed_order.hip", "zone.hip"]
 ARCH = os.environ.get("LGDM_OFFLOAD_ARCH", "gfx950")
 
 
@@ -46,7 +46,9 @@ def build(verbose=True):
     with ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
         objs = list(ex.map(compile_one, SOURCES))
     tmp = OUT + ".tmp"
-    cmd = [_hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
+    rocm_lib = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
+    cmd = [_hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + [
+        "-L" + rocm_lib, "-lrocsolver", "-lrocblas", "-Wl,-rpath," + rocm_lib]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (" ".join(cmd), r.stderr[-8000:]))

@@ -965,6 +965,11 @@ hipError_t amg_setup(lgdm_ctx* c, std::string& msg) {
 }
 
 hipError_t amg_apply(lgdm_ctx* c, const double* in, double* out, const double* sc, hipStream_t st) {
+  if (zone_active(c)) return zone_apply(c, in, out, sc, st);
+  return amg_cycle(c, in, out, sc, st);
+}
+
+hipError_t amg_cycle(lgdm_ctx* c, const double* in, double* out, const double* sc, hipStream_t st) {
   if (!c->amg) return hipErrorInvalidValue;
   if (c->amg->mixed) vcycle<float>(c, *c->amg, 0, in, out, sc, st);
   else vcycle<double>(c, *c->amg, 0, in, out, sc, st);

@@ -129,6 +129,7 @@ lgdm_status hip_fail(lgdm_ctx* c, hipError_t e, const char* where) {
 
 void free_mesh(lgdm_ctx* c) {
   amg_release(c);
+  zone_release(c);
   c->amg_unavailable = false;
   // keep pinned host buffers; release every device allocation
   std::vector<std::pair<void*, size_t>> all = c->allocs;
@@ -182,6 +183,15 @@ void fill_norms(const lgdm_ctx* c, lgdm_increment_report* rep) {
   rep->reaction = c->last_norms[4];
 }
 
+// merit of the line search: the squared relative residuals of both fields
+double newton_merit(const lgdm_ctx* c) {
+  const double tiny = 1e-300;
+  const double ru = std::sqrt(c->last_norms[0]), re = std::sqrt(c->last_norms[1]);
+  const double fu = std::sqrt(c->last_norms[2]), fe = std::sqrt(c->last_norms[3]);
+  const double a = ru / std::max(fu, tiny), b = re / std::max(fe, tiny);
+  return a * a + b * b;
+}
+
 bool residual_converged(const lgdm_ctx* c, double tol) {
   const double tiny = 1e-300;
   const double ru = std::sqrt(c->last_norms[0]), re = std::sqrt(c->last_norms[1]);
@@ -212,6 +222,24 @@ lgdm_status linear_solve(lgdm_ctx* c, const double* b_dev, double* x_dev, const 
                                 "multigrid setup: " + msg);
     }
   }
+  // the process zone of this tangent, solved densely inside the multigrid cycle
+  zone_disable(c);
+  if (o.precond == LGDM_PRECOND_AMG && o.process_zone != LGDM_ZONE_OFF && !(c->in_increment && c->inc_zone_off)) {
+    std::string msg;
+    const double t0 = host_seconds();
+    bool factored = false;
+    const hipError_t e = zone_setup(c, !c->noalloc_call, c->zone_may_reuse && o.process_zone == LGDM_ZONE_DEFAULT,
+                                    o.zone_damage, &factored, msg);
+    if (rep) {
+      rep->t_zone_ms += 1e3 * (host_seconds() - t0);
+      rep->zone_factorizations += factored ? 1 : 0;
+    }
+    if (c->in_increment && zone_active(c)) c->inc_zone_used = true;
+    if (e == hipErrorNotReady)
+      return fail(c, LGDM_ERR_STATE, "the process-zone block of this tangent needs device memory the context has "
+                                     "not allocated yet: run lgdm_solve_linear on it first, or turn the zone off");
+    if (e != hipSuccess) return msg.empty() ? hip_fail(c, e, "process-zone setup") : fail(c, LGDM_ERR_DEVICE, msg);
+  }
   KrylovResult kr{};
   HIPCHECK(c, krylov_solve(c, b_dev, x_dev, o, tol_u, tol_e, kr), "Krylov solve");
   const bool out_of_time = c->solve_deadline > 0.0 && host_seconds() > c->solve_deadline;
@@ -235,6 +263,7 @@ lgdm_status linear_solve(lgdm_ctx* c, const double* b_dev, double* x_dev, const 
   c->last_solve_improved = kr.status == LGDM_OK || kr.improved;
   c->inc_krylov += kr.iters;
   if (rep) {
+    rep->zone_dofs = std::max<int64_t>(rep->zone_dofs, zone_dofs(c));
     rep->krylov_iters += kr.iters;
     rep->restarts += kr.restarts;
     rep->krylov_status = kr.status;
@@ -589,6 +618,7 @@ lgdm_status lgdm_solve_linear_noalloc(lgdm_ctx* c, const double* b, double* delt
   double* const own_kscal = c->kscal;
   c->kpart = scratch;
   c->kscal = scratch + c->n_kpart;
+  c->noalloc_call = true;
   // the array keeps the previous call's values: the scalars start at zero
   hipError_t e = launch_fill(c->kscal, KSCAL_DOUBLES, 0.0, c->stream);
   lgdm_status s = e == hipSuccess ? linear_solve(c, c->delta, delta, op, op.tol_krylov, op.tol_krylov, rep)
@@ -599,6 +629,7 @@ lgdm_status lgdm_solve_linear_noalloc(lgdm_ctx* c, const double* b, double* delt
   }
   c->kpart = own_kpart;
   c->kscal = own_kscal;
+  c->noalloc_call = false;
   return s;
 }
 
@@ -609,6 +640,13 @@ lgdm_status lgdm_begin_increment(lgdm_ctx* c, double lambda) {
   HIPCHECK(c, launch_set_dirichlet(c, lambda), "set Dirichlet values");
   c->in_increment = true;
   c->nw_iter = 0;
+  c->nw_stepped = false;
+  c->nw_best_phi = HUGE_VAL;
+  c->nw_since_best = 0;
+  c->inc_lambda = lambda;
+  c->inc_serial += 1;
+  c->inc_zone_used = false;
+  c->inc_zone_off = false;
   c->inc_krylov = 0;
   c->inc_t0 = host_seconds();
   return LGDM_OK;
@@ -628,9 +666,62 @@ lgdm_status lgdm_newton_iteration(lgdm_ctx* c, const lgdm_solver_opts* o, int32_
     fill_norms(c, rep);
   }
   if (s != LGDM_OK) return s;
+  // line search: a correction that raised the merit more than fourfold is
+  // halved (at most four times), each trial assembled like an iterate
+  constexpr double LS_GROWTH = 4.0;
+  constexpr int LS_MAX_CUTS = 4;
+  if (op.line_search != LGDM_LINE_SEARCH_OFF && c->nw_stepped) {
+    while (!residual_converged(c, op.tol_newton) && newton_merit(c) > LS_GROWTH * c->nw_phi &&
+           c->nw_cuts < LS_MAX_CUTS) {
+      HIPCHECK(c, launch_axpy(c, c->x, c->delta, -0.5 * c->nw_alpha, c->ndof), "line search");
+      c->nw_alpha *= 0.5;
+      c->nw_cuts += 1;
+      s = assemble_now(c, &t_asm);
+      if (rep) {
+        rep->t_assembly_ms += t_asm;
+        rep->n_assemblies += 1;
+        rep->backtracks += 1;
+        fill_norms(c, rep);
+      }
+      if (s != LGDM_OK) return s;
+    }
+  }
+  c->nw_stepped = false;
   if (residual_converged(c, op.tol_newton)) {
     *converged = 1;
     return LGDM_OK;
+  }
+  // Newton with the process zone that no longer reduces the merit restarts
+  // the increment from its beginning without the zone
+  constexpr int ZONE_PATIENCE = 5;
+  const double phi = newton_merit(c);
+  if (phi < c->nw_best_phi) {
+    c->nw_best_phi = phi;
+    c->nw_since_best = 0;
+  } else {
+    c->nw_since_best += 1;
+  }
+  if (c->inc_zone_used && !c->inc_zone_off && c->nw_since_best >= ZONE_PATIENCE) {
+    HIPCHECK(c, hipMemcpyAsync(c->x, c->x_save, c->ndof * sizeof(double), hipMemcpyDeviceToDevice, c->stream),
+             "restore x");
+    HIPCHECK(c, launch_set_dirichlet(c, c->inc_lambda), "set Dirichlet values");
+    c->inc_zone_off = true;
+    c->nw_iter = 0;
+    c->nw_best_phi = HUGE_VAL;
+    c->nw_since_best = 0;
+    s = assemble_now(c, &t_asm);
+    if (rep) {
+      rep->t_assembly_ms += t_asm;
+      rep->n_assemblies += 1;
+      rep->zone_restarts += 1;
+      fill_norms(c, rep);
+    }
+    if (s != LGDM_OK) return s;
+    if (residual_converged(c, op.tol_newton)) {
+      *converged = 1;
+      return LGDM_OK;
+    }
+    c->nw_best_phi = newton_merit(c);
   }
   // work bound of the increment: the Krylov iterations and the wall time
   // left to it
@@ -655,7 +746,9 @@ lgdm_status lgdm_newton_iteration(lgdm_ctx* c, const lgdm_solver_opts* o, int32_
   HIPCHECK(c, hipEventRecord(c->ev[2], c->stream), "event");
   double tol_u = op.tol_krylov, tol_e = op.tol_krylov;
   newton_forcing(c, op, tol_u, tol_e);
+  c->zone_may_reuse = true;
   s = linear_solve(c, c->R, c->delta, ob, tol_u, tol_e, rep);
+  c->zone_may_reuse = false;
   c->solve_deadline = 0.0;
   HIPCHECK(c, hipEventRecord(c->ev[3], c->stream), "event");
   if (!tolerable_in_newton(s)) return s;
@@ -665,6 +758,10 @@ lgdm_status lgdm_newton_iteration(lgdm_ctx* c, const lgdm_solver_opts* o, int32_
   s = LGDM_OK;
   // Algorithm 2: u_i = u_{i-1} + delta u, ebar_i = ebar_{i-1} + delta ebar
   HIPCHECK(c, launch_axpy(c, c->x, c->delta, 1.0, c->ndof), "update");
+  c->nw_stepped = true;
+  c->nw_phi = newton_merit(c);
+  c->nw_alpha = 1.0;
+  c->nw_cuts = 0;
   HIPCHECK(c, launch_field_norms(c, c->delta, c->norms_dev + 8), "update norms");
   HIPCHECK(c, hipEventRecord(c->ev[4], c->stream), "event");
   HIPCHECK(c, hipMemcpyAsync(c->norms_host + 8, c->norms_dev + 8, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream), "norms");

@@ -1,6 +1,9 @@
-// Linear solve of the Newton system (Eq. 11; H6): right-preconditioned
-// BiCGSTAB with per-node (dim+1)x(dim+1) block-Jacobi, written for the
-// node-blocked CSR the assembly produces.
+// Linear solve of the Newton system (Eq. 11; H6), written for the
+// node-blocked CSR the assembly produces: right-preconditioned IDR(s)
+// (van Gijzen & Sonneveld 2011; s = 8 by default) or BiCGSTAB (van der Vorst
+// 1992), preconditioned by the aggregation multigrid cycle of amg.hip on 3D
+// meshes (with the dense process-zone solve of zone.hip) and by per-node
+// (dim+1)x(dim+1) block-Jacobi otherwise.
 //
 //  - SpMV uses the node graph for its column indices (one int per node pair
 //    instead of one per nonzero): row r of node a lists, for each neighbour
@@ -1796,6 +1799,9 @@ lgdm_solver_opts fill_opts(const lgdm_solver_opts* o) {
   if (r.forcing != LGDM_FORCING_FIXED) r.forcing = LGDM_FORCING_ADAPTIVE;
   if (r.precond != LGDM_PRECOND_AMG && r.precond != LGDM_PRECOND_BLOCK_JACOBI) r.precond = LGDM_PRECOND_DEFAULT;
   r.idr_s = r.idr_s <= 0 ? 8 : (r.idr_s <= 1 ? 1 : (r.idr_s <= 2 ? 2 : (r.idr_s <= 4 ? 4 : 8)));
+  if (!(r.zone_damage > 0.0 && r.zone_damage < 1.0)) r.zone_damage = 0.999;
+  if (r.process_zone != LGDM_ZONE_OFF && r.process_zone != LGDM_ZONE_EVERY_TANGENT) r.process_zone = LGDM_ZONE_DEFAULT;
+  if (r.line_search != LGDM_LINE_SEARCH_OFF) r.line_search = LGDM_LINE_SEARCH_DEFAULT;
   return r;
 }
 

@@ -119,7 +119,10 @@ constexpr int KPART_PER_BLOCK = 16;    // partial sums per workgroup (at most 4 
 constexpr int KPART_BLOCKS = 2048;     // workgroups of a Krylov vector kernel, at most
 constexpr int KSLOT_DONE = 9;          // device scalar slot of a solve's done flag
 
-struct Amg;  // aggregation-multigrid hierarchy of a context (amg.hip)
+struct Amg;   // aggregation-multigrid hierarchy of a context (amg.hip)
+struct Zone;  // process-zone block of the multigrid preconditioner (zone.hip)
+// largest process zone solved densely (unknowns): 4.8 GB of FP64 block
+constexpr int64_t ZONE_MAX_DOFS = 24576;
 
 // Live timing of one kernel inside the solves: HIP event pairs around its
 // launches on the context's stream, harvested without blocking.
@@ -210,10 +213,23 @@ struct lgdm_ctx {
   unsigned int* kcount = nullptr;  // last-block counters
   double* delta = nullptr;
   lgdm::Amg* amg = nullptr;         // multigrid hierarchy (built at the first multigrid solve)
+  lgdm::Zone* zone = nullptr;       // process-zone solve of the multigrid preconditioner
+  bool noalloc_call = false;        // inside lgdm_solve_linear_noalloc: nothing may be allocated
   lgdm::KernelProbe* probe = nullptr;  // live kernel timing (measurement aid)
   bool amg_unavailable = false;     // the mesh has no usable hierarchy (default: block-Jacobi)
   bool last_solve_improved = true;  // the last linear solve returned a better-than-zero correction
   int nw_iter = 0;                  // Newton corrections of the current increment
+  bool nw_stepped = false;          // x holds a correction not yet judged by the line search
+  double nw_phi = 0.0;              // merit of the iterate the last correction started from
+  double nw_alpha = 1.0;            // fraction of that correction x holds
+  int nw_cuts = 0;                  // halvings of it so far
+  double nw_best_phi = 0.0;         // smallest merit of the increment's iterates
+  int nw_since_best = 0;            // iterates since that one
+  double inc_lambda = 0.0;          // load factor of the current increment
+  int64_t inc_serial = 0;           // counts lgdm_begin_increment calls
+  bool inc_zone_used = false;       // a solve of this increment used the process zone
+  bool inc_zone_off = false;        // this increment restarted without it
+  bool zone_may_reuse = false;      // the running solve may keep the zone's inverse
   int64_t inc_krylov = 0;           // Krylov iterations spent in the current increment
   double inc_t0 = 0.0;              // host time the current increment began (lgdm::host_seconds)
   double solve_deadline = 0.0;      // host time a running solve must stop by (0: none)
@@ -337,7 +353,20 @@ hipError_t launch_axpy(lgdm_ctx* c, double* y, const double* x, double a, int64_
 // host side (device memory belongs to the context's allocations).
 hipError_t amg_setup(lgdm_ctx* c, std::string& msg);
 hipError_t amg_apply(lgdm_ctx* c, const double* in, double* out, const double* sc, hipStream_t st);
+hipError_t amg_cycle(lgdm_ctx* c, const double* in, double* out, const double* sc, hipStream_t st);
 void amg_release(lgdm_ctx* c);
+// Process zone (zone.hip): the loading, highly damaged elements of the
+// current tangent, solved densely inside the multigrid preconditioner.
+// zone_setup chooses and factors it (after amg_setup); with allow_alloc
+// false it returns hipErrorNotReady instead of growing its buffers.
+// With reuse, a zone whose node set equals the last one built in the same
+// increment keeps its inverse; *factored tells whether it was rebuilt.
+hipError_t zone_setup(lgdm_ctx* c, bool allow_alloc, bool reuse, double dmin, bool* factored, std::string& msg);
+bool zone_active(const lgdm_ctx* c);
+int64_t zone_dofs(const lgdm_ctx* c);
+void zone_disable(lgdm_ctx* c);
+hipError_t zone_apply(lgdm_ctx* c, const double* in, double* out, const double* sc, hipStream_t st);
+void zone_release(lgdm_ctx* c);
 struct AmgInfo {
   int levels;
   int64_t nodes[16];

@@ -17,6 +17,12 @@ match the damage of every Gauss point after every committed increment to
 1e-8 (FP64) and 1e-7 (mixed precision), and the reactions to 1e-6.  Gauss
 points at a band tie (reading A18: the history or damage band edge of
 Fig. 8b decided by rounding) are counted and reported apart; see _ties.
+
+The beam's path is also run in FP64 with the solver's variants: the dense
+process-zone solve of the multigrid preconditioner rebuilt for every tangent
+or switched off, and full Newton steps without the line search.  Each must
+land on the same discrete solution; the default and every-tangent runs must
+have used the zone.
 """
 import os
 
@@ -70,28 +76,41 @@ def _ties(g, n, diff, kap, m, bound):
     return ties
 
 
-# (workload, precision, increments compared (None: all stored), Newton tolerance)
-CASES = [("c3p", B.FP64, None, 1e-12), ("c3p", B.MIXED, None, 1e-10), ("c1", B.FP64, None, 1e-11),
-         ("c1", B.MIXED, 60, 1e-10)]
+# (workload, precision, increments compared (None: all stored), Newton tolerance, solver variant)
+# variants on the beam: the process zone rebuilt for every tangent, no zone,
+# full Newton steps; the discrete solution must not depend on them
+CASES = [("c3p", B.FP64, None, 1e-12, "default"), ("c3p", B.MIXED, None, 1e-10, "default"),
+         ("c1", B.FP64, None, 1e-11, "default"), ("c1", B.MIXED, 60, 1e-10, "default"),
+         ("c3p", B.FP64, None, 1e-12, "zone_every"), ("c3p", B.FP64, None, 1e-12, "zone_off"),
+         ("c3p", B.FP64, None, 1e-12, "no_line_search")]
+VARIANTS = {"default": {}, "zone_every": dict(process_zone=B.ZONE_EVERY_TANGENT),
+            "zone_off": dict(process_zone=B.ZONE_OFF), "no_line_search": dict(line_search=B.LINE_SEARCH_OFF)}
 
 
-@pytest.mark.parametrize("name,precision,limit,tol_newton", CASES)
-def test_load_path_vs_stored_oracle(name, precision, limit, tol_newton):
+@pytest.mark.parametrize("name,precision,limit,tol_newton,variant", CASES)
+def test_load_path_vs_stored_oracle(name, precision, limit, tol_newton, variant):
     g = _golden(name)
     prob = W.config(name)
     n_inc = len(g["reaction"]) if limit is None else min(limit, len(g["reaction"]))
-    print("case: %s precision %d, %d increments (stored: %d, peak at %d, oracle stopped at %d)"
-          % (name, precision, n_inc, len(g["reaction"]), int(g["peak"]), int(g["stopped"])), flush=True)
+    print("case: %s precision %d variant %s, %d increments (stored: %d, peak at %d, oracle stopped at %d)"
+          % (name, precision, variant, n_inc, len(g["reaction"]), int(g["peak"]), int(g["stopped"])),
+          flush=True)
     ctx = context(prob, precision)
     # FP64 runs Newton past the oracle's 1e-10 test: the oracle's last
     # (exact, quadratic) step lands far below it, and on the softening branch
     # a residual of 1e-10 still leaves damage differences near 1e-8 (the
     # post-peak plate stalls before 1e-12 with these inexact corrections)
-    opts = B.solver_opts(max_newton=60, tol_newton=tol_newton, tol_krylov=1e-8, max_krylov=50000)
+    opts = B.solver_opts(max_newton=60, tol_newton=tol_newton, tol_krylov=1e-8, max_krylov=50000,
+                         **VARIANTS[variant])
+    zone = dict(factorizations=0, largest=0, restarts=0, halvings=0)
     bound = 1e-8 if precision == B.FP64 else 1e-7
     errs, tie = [], 0
     for n in range(n_inc):
         rep = ctx.solve_increment((n + 1) / prob.n_increments, opts)
+        zone["factorizations"] += rep["zone_factorizations"]
+        zone["largest"] = max(zone["largest"], rep["zone_dofs"])
+        zone["restarts"] += rep["zone_restarts"]
+        zone["halvings"] += rep["backtracks"]
         Dg = ctx.query(B.FIELD_DAMAGE)
         Do = _damage_after(g, n)
         diff = np.abs(Dg - Do)
@@ -107,8 +126,12 @@ def test_load_path_vs_stored_oracle(name, precision, limit, tol_newton):
                      float(g["max_D"][n])), flush=True)
         assert err <= bound, "increment %d: damage error %.3e" % (n + 1, err)
         assert abs(rep["reaction"] - ro) <= 1e-6 * abs(ro), "increment %d reaction" % (n + 1)
-    print("max damage error over %d increments: %.3e (band ties beyond the bound, reported apart: %d)"
-          % (n_inc, max(errs), tie))
+    print("max damage error over %d increments: %.3e (band ties beyond the bound, reported apart: %d); "
+          "process zone: %s" % (n_inc, max(errs), tie, zone))
+    if name == "c3p" and variant in ("default", "zone_every"):
+        assert zone["factorizations"] > 0       # the compared path exercises the dense zone solve
+    if variant == "zone_off":
+        assert zone["factorizations"] == 0 and zone["largest"] == 0
     # ties are isolated points, not a population
     assert tie <= 0.01 * len(g["idx"]) * n_inc
     if n_inc >= int(g["peak"]) + 3:

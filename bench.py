@@ -108,7 +108,7 @@ def newton_line(inc, it, r, before):
     linear solve that followed it (steps, reached relative residual, status)."""
     return ("  inc %d it %d |R_u|/|F_u|=%.3e |R_e|/|F_e|=%.3e krylov=%d spmv=%d rel=(%.1e, %.1e) "
             "status=%d inexact=%d restarts=%d backtracks=%d zone<=%d asm=%.3fms solve=%.1fms "
-            "(so far: zone setup %.1fms, %d factorizations, %d restarts without zone)" % (
+            "(so far: zone setup %.1fms, %d factorizations, %d restarts)" % (
                 inc, it, r.res_u / max(r.ref_u, 1e-300), r.res_e / max(r.ref_e, 1e-300),
                 r.krylov_iters - before[4], r.krylov_spmv - before[5], r.krylov_rel_u, r.krylov_rel_e,
                 r.krylov_status, r.inexact_solves, r.restarts, r.backtracks, r.zone_dofs,
@@ -248,7 +248,7 @@ def run_precision(prob, precision, args, binding):
                                    "update": acc["t_upd"] / args.steps,
                                    "zone_setup_within_solve": acc["zone_ms"] / args.steps},
         "process_zone": {"factorizations": acc["zone_factorizations"],
-                         "increments_restarted_without_zone": acc["zone_restarts"],
+                         "increment_restarts": acc["zone_restarts"],
                          "line_search_halvings": acc["backtracks"]},
         "krylov_iters": acc["krylov"], "spmv_launches": acc["spmv"],
         "spmv_per_newton_step": acc["spmv"] / max(acc["newton"], 1),
@@ -506,18 +506,24 @@ def copy_calibration(nbytes=1 << 30):
             "ms": ms, "gbs": 2 * nbytes / (ms * 1e-3) / 1e9}
 
 
-def serving_leg(seconds):
-    """The continuous-batching workload: 256 seeded 2D notched-plate requests
+def serving_leg(seconds, n_requests, increments):
+    """The continuous-batching workload: seeded 2D notched-plate requests
     (40x20 .. 400x200 Q4, 50-200 increments) with Poisson arrivals at 20/s,
-    mixed precision, served for a bounded wall time."""
+    mixed precision, 64 slots, served until every request is retired or the
+    wall time runs out.  increments > 0 keeps only the first increments of
+    each request's load path (the same load steps), so that whole requests
+    finish within the bench; 0 runs every load path to its end."""
     import lgdm_workloads as W
     from paper_2301_06503_amd import binding, serving
-    reqs = W.serving_stream(n_requests=256, rate_per_s=20.0, seed=0)
+    reqs = W.serving_stream(n_requests=n_requests, rate_per_s=20.0, seed=0,
+                            first_increments=increments if increments > 0 else None)
     loop = serving.ServingLoop(reqs, precision=binding.MIXED, max_slots=64)
     summ = loop.run(time_limit_s=seconds, realtime=True)
     loop.close()
-    summ["workload"] = ("256 requests, Poisson arrivals 20/s, 2D notched plates 40x20..400x200 Q4, "
-                        "50-200 increments, mixed precision, 64 slots; served for %.0f s" % seconds)
+    summ["workload"] = ("%d requests, Poisson arrivals 20/s, 2D notched plates 40x20..400x200 Q4 with 50-200 "
+                        "increments, %s, mixed precision, 64 slots; served for at most %.0f s" % (
+                            n_requests, "the first %d increments of each load path" % increments
+                            if increments > 0 else "whole load paths", seconds))
     return summ
 
 
@@ -541,7 +547,7 @@ def main():
                     help="dense process-zone solve in the multigrid preconditioner: default (inverse kept while "
                          "the zone's nodes stay the same within an increment), off, or every (rebuilt for every "
                          "tangent)")
-    ap.add_argument("--zone-damage", type=float, default=0.999,
+    ap.add_argument("--zone-damage", type=float, default=0.99,
                     help="trial damage from which a loading element joins the process zone")
     ap.add_argument("--no-line-search", action="store_true",
                     help="full Newton steps (no backtracking on a correction that blows the residual up)")
@@ -550,7 +556,11 @@ def main():
     ap.add_argument("--max-krylov", type=int, default=20000)
     ap.add_argument("--max-newton", type=int, default=40)
     ap.add_argument("--kernel-reps", type=int, default=5)
-    ap.add_argument("--serving-seconds", type=float, default=30.0)
+    ap.add_argument("--serving-seconds", type=float, default=45.0,
+                    help="wall-time bound of the serving leg (0: no serving leg)")
+    ap.add_argument("--serving-requests", type=int, default=128)
+    ap.add_argument("--serving-increments", type=int, default=12,
+                    help="increments served per request (the first ones of its load path; 0: all)")
     ap.add_argument("--coupling", type=int, default=0, choices=[0, 1],
                     help="1: the stress of Eq. 2 with its h term and the consistent tangent (material coupling "
                          "variant); 0: the executed-code form (default)")
@@ -623,7 +633,7 @@ def main():
     copy_cal = copy_calibration()
     serving_res = None
     if args.serving_seconds > 0:
-        serving_res = serving_leg(args.serving_seconds)
+        serving_res = serving_leg(args.serving_seconds, args.serving_requests, args.serving_increments)
     out = {
         "metric": METRIC,
         "value": main_res["gp_per_s"],

@@ -190,7 +190,7 @@ typedef struct lgdm_solver_opts {
                                     LGDM_ERR_NOT_CONVERGED as above               */
   int32_t line_search;     /* LGDM_LINE_SEARCH_DEFAULT: backtracking on a Newton
                               correction that blows the residual up (below)        */
-  double zone_damage;      /* 0.999  trial damage from which a loading element
+  double zone_damage;      /* 0.99   trial damage from which a loading element
                               joins the process zone (below); values outside
                               (0, 1) select the default                            */
 } lgdm_solver_opts;
@@ -218,20 +218,23 @@ enum { LGDM_FORCING_ADAPTIVE = 0, LGDM_FORCING_FIXED = 1 };
  * preconditioner solves that zone exactly before the cycle:
  *   zone   the nodes of the elements with a loading Gauss point of trial
  *          damage >= zone_damage (raised tenfold closer to 1, twice at most,
- *          while it exceeds 24,576 unknowns; no zone beyond that);
- *   apply  x_z = Z^-1 b_z with Z the zone's block of S K (dense LU with
- *          partial pivoting and explicit inverse, rocSOLVER getrf/getri,
- *          applied as one matrix-vector product); r = b - S K x_z;
- *          out = x_z + (multigrid cycle)(r).
- * Inside a Newton increment, Z^-1 is rebuilt only when the zone's node set
- * changes (a later tangent of the increment with the same zone keeps it; r
- * and the cycle always use the current tangent); LGDM_ZONE_EVERY_TANGENT
- * rebuilds it for every tangent, and lgdm_solve_linear always does.
- * Should Newton with the zone stop reducing the merit of the line search
- * (no new smallest value in 5 iterations), the increment restarts from its
- * beginning without the zone (zone_restarts in the report).
- * The zone's dense block is allocated through the context's allocator the
- * first time a zone of that size occurs (up to 4.8 GB) and kept.
+ *          while a level group below exceeds 4,096 unknowns or the factors
+ *          1.25 GiB; no zone beyond that);
+ *   factor the zone's nodes in breadth-first levels (lgdm_zone_levels), which
+ *          make its block Z of S K block tridiagonal; block LU over runs of
+ *          levels, each diagonal block inverted (rocSOLVER getrf/getri);
+ *   apply  x_z = Z^-1 b_z by the forward and backward block sweeps;
+ *          r = b - S K x_z; out = x_z + (multigrid cycle)(r).
+ * Inside a Newton increment the factors are rebuilt only when the zone's node
+ * set changes (a later tangent of the increment with the same zone keeps
+ * them; r and the cycle always use the current tangent);
+ * LGDM_ZONE_EVERY_TANGENT rebuilds them for every tangent, and
+ * lgdm_solve_linear always does.  Should Newton with the zone stop reducing
+ * the merit of the line search (no new smallest value in 4 iterations), the
+ * increment restarts from its beginning with the zone's damage threshold
+ * moved tenfold closer to 1, and should that stall too, without the zone
+ * (zone_restarts in the report).  The factors are allocated through the context's allocator
+ * the first time a zone of that size occurs and kept.
  * LGDM_ZONE_OFF: the plain cycle. */
 enum { LGDM_ZONE_DEFAULT = 0, LGDM_ZONE_OFF = 1, LGDM_ZONE_EVERY_TANGENT = 2 };
 
@@ -280,7 +283,8 @@ typedef struct lgdm_increment_report {
   double t_zone_ms;        /* host time choosing and factoring the process zones,
                               part of t_solve_ms                                    */
   int32_t zone_factorizations; /* process-zone blocks factored                      */
-  int32_t zone_restarts;   /* increments restarted without the zone                */
+  int32_t zone_restarts;   /* restarts of the increment with a smaller zone or
+                              none (see LGDM_ZONE_DEFAULT)                          */
 } lgdm_increment_report;
 
 /* View of the assembled tangent.  Device pointers owned by the context. */
@@ -472,6 +476,19 @@ lgdm_status lgdm_footprint(lgdm_ctx* ctx, int64_t* bytes);
  * INVALID_ARG for NULL pointers or n < 0, or a neighbour id outside [0, n). */
 lgdm_status lgdm_amg_aggregate(int64_t n, const int32_t* ptr, const int32_t* adj, int32_t* agg,
                                int64_t* n_agg);
+
+/* The level sets that order the process zone (host only, no device call).
+ * Graph: CSR over n nodes in host memory, ptr [n + 1] and adj [ptr[n]],
+ * symmetric (b a neighbour of a exactly when a is one of b); self-loops are
+ * ignored.  Each connected component, taken in order of its lowest node, is
+ * searched breadth-first from a pseudo-peripheral node (George & Liu 1979:
+ * from the component's lowest node, restart from a least-connected node of
+ * the last level while the number of levels grows); its levels follow those
+ * of the components before it.  Writes level [n] and *n_levels; neighbours'
+ * levels differ by at most one.  INVALID_ARG for NULL pointers, n < 0, or a
+ * neighbour id outside [0, n). */
+lgdm_status lgdm_zone_levels(int64_t n, const int32_t* ptr, const int32_t* adj, int32_t* level,
+                             int64_t* n_levels);
 
 /* Node counts of the context's multigrid levels (finest first) once a
  * multigrid solve has built them: writes up to max_levels counts to nodes

@@ -41,7 +41,7 @@ EXPORTS = [
     "lgdm_newton_iteration", "lgdm_commit_increment", "lgdm_abort_increment", "lgdm_get_csr",
     "lgdm_get_connectivity", "lgdm_get_sizes", "lgdm_query_state", "lgdm_set_state",
     "lgdm_debug_element_blocks", "lgdm_kernel_times", "lgdm_footprint", "lgdm_amg_aggregate",
-    "lgdm_amg_levels", "lgdm_probe_start", "lgdm_probe_stop",
+    "lgdm_amg_levels", "lgdm_probe_start", "lgdm_probe_stop", "lgdm_zone_levels",
     "lgdm_batch_create", "lgdm_batch_destroy", "lgdm_batch_last_error", "lgdm_request_footprint",
     "lgdm_batch_admit", "lgdm_batch_tick", "lgdm_batch_slot_info", "lgdm_batch_query",
     "lgdm_batch_retire", "lgdm_batch_usage", "lgdm_batch_set_allocator",
@@ -157,6 +157,7 @@ def load_library(path: str = LIB_PATH):
         "lgdm_footprint": [P, ctypes.POINTER(I64)],
         "lgdm_kernel_times": [P, I32, P],
         "lgdm_amg_aggregate": [I64, P, P, P, ctypes.POINTER(I64)],
+        "lgdm_zone_levels": [I64, P, P, P, ctypes.POINTER(I64)],
         "lgdm_amg_levels": [P, I32, P, ctypes.POINTER(I32)],
         "lgdm_probe_start": [P, I32],
         "lgdm_probe_stop": [P, ctypes.POINTER(D), ctypes.POINTER(I64)],
@@ -558,6 +559,21 @@ class Batch:
         u, b, o = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
         self._check(self.lib.lgdm_batch_usage(self.h, ctypes.byref(u), ctypes.byref(b), ctypes.byref(o)))
         return u.value, b.value, o.value
+
+
+def zone_levels(ptr, adj):
+    """The breadth-first level sets that order the process zone, on a host
+    CSR graph (no device): returns (level [n] int32, number of levels)."""
+    lib = load_library()
+    ptr = np.ascontiguousarray(ptr, dtype=np.int32)
+    adj = np.ascontiguousarray(adj, dtype=np.int32)
+    n = len(ptr) - 1
+    level = np.empty(max(n, 0), dtype=np.int32)
+    nl = ctypes.c_int64()
+    st = lib.lgdm_zone_levels(n, ptr.ctypes.data, adj.ctypes.data, level.ctypes.data, ctypes.byref(nl))
+    if st != LGDM_OK:
+        raise LgdmError(st, "lgdm_zone_levels")
+    return level, nl.value
 
 
 def amg_aggregate(ptr, adj):

@@ -224,12 +224,14 @@ lgdm_status linear_solve(lgdm_ctx* c, const double* b_dev, double* x_dev, const 
   }
   // the process zone of this tangent, solved densely inside the multigrid cycle
   zone_disable(c);
-  if (o.precond == LGDM_PRECOND_AMG && o.process_zone != LGDM_ZONE_OFF && !(c->in_increment && c->inc_zone_off)) {
+  const int tier = c->in_increment ? c->inc_zone_tier : 0;
+  if (o.precond == LGDM_PRECOND_AMG && o.process_zone != LGDM_ZONE_OFF && tier < 2) {
     std::string msg;
     const double t0 = host_seconds();
     bool factored = false;
+    const double dmin = tier == 0 ? o.zone_damage : 1.0 - 0.1 * (1.0 - o.zone_damage);
     const hipError_t e = zone_setup(c, !c->noalloc_call, c->zone_may_reuse && o.process_zone == LGDM_ZONE_DEFAULT,
-                                    o.zone_damage, &factored, msg);
+                                    dmin, &factored, msg);
     if (rep) {
       rep->t_zone_ms += 1e3 * (host_seconds() - t0);
       rep->zone_factorizations += factored ? 1 : 0;
@@ -646,7 +648,7 @@ lgdm_status lgdm_begin_increment(lgdm_ctx* c, double lambda) {
   c->inc_lambda = lambda;
   c->inc_serial += 1;
   c->inc_zone_used = false;
-  c->inc_zone_off = false;
+  c->inc_zone_tier = 0;
   c->inc_krylov = 0;
   c->inc_t0 = host_seconds();
   return LGDM_OK;
@@ -692,8 +694,9 @@ lgdm_status lgdm_newton_iteration(lgdm_ctx* c, const lgdm_solver_opts* o, int32_
     return LGDM_OK;
   }
   // Newton with the process zone that no longer reduces the merit restarts
-  // the increment from its beginning without the zone
-  constexpr int ZONE_PATIENCE = 5;
+  // the increment from its beginning with a smaller zone (the damage
+  // threshold tenfold closer to 1), then without the zone
+  constexpr int ZONE_PATIENCE = 4;
   const double phi = newton_merit(c);
   if (phi < c->nw_best_phi) {
     c->nw_best_phi = phi;
@@ -701,11 +704,12 @@ lgdm_status lgdm_newton_iteration(lgdm_ctx* c, const lgdm_solver_opts* o, int32_
   } else {
     c->nw_since_best += 1;
   }
-  if (c->inc_zone_used && !c->inc_zone_off && c->nw_since_best >= ZONE_PATIENCE) {
+  if (c->inc_zone_used && c->inc_zone_tier < 2 && c->nw_since_best >= ZONE_PATIENCE) {
     HIPCHECK(c, hipMemcpyAsync(c->x, c->x_save, c->ndof * sizeof(double), hipMemcpyDeviceToDevice, c->stream),
              "restore x");
     HIPCHECK(c, launch_set_dirichlet(c, c->inc_lambda), "set Dirichlet values");
-    c->inc_zone_off = true;
+    c->inc_zone_tier += 1;
+    c->inc_zone_used = false;
     c->nw_iter = 0;
     c->nw_best_phi = HUGE_VAL;
     c->nw_since_best = 0;

@@ -121,8 +121,6 @@ constexpr int KSLOT_DONE = 9;          // device scalar slot of a solve's done f
 
 struct Amg;   // aggregation-multigrid hierarchy of a context (amg.hip)
 struct Zone;  // process-zone block of the multigrid preconditioner (zone.hip)
-// largest process zone solved densely (unknowns): 4.8 GB of FP64 block
-constexpr int64_t ZONE_MAX_DOFS = 24576;
 
 // Live timing of one kernel inside the solves: HIP event pairs around its
 // launches on the context's stream, harvested without blocking.
@@ -228,7 +226,8 @@ struct lgdm_ctx {
   double inc_lambda = 0.0;          // load factor of the current increment
   int64_t inc_serial = 0;           // counts lgdm_begin_increment calls
   bool inc_zone_used = false;       // a solve of this increment used the process zone
-  bool inc_zone_off = false;        // this increment restarted without it
+  int inc_zone_tier = 0;            // restarts of this increment: 0 zone from zone_damage,
+                                    // 1 from 1 - (1 - zone_damage) / 10, 2 no zone
   bool zone_may_reuse = false;      // the running solve may keep the zone's inverse
   int64_t inc_krylov = 0;           // Krylov iterations spent in the current increment
   double inc_t0 = 0.0;              // host time the current increment began (lgdm::host_seconds)
@@ -367,6 +366,9 @@ int64_t zone_dofs(const lgdm_ctx* c);
 void zone_disable(lgdm_ctx* c);
 hipError_t zone_apply(lgdm_ctx* c, const double* in, double* out, const double* sc, hipStream_t st);
 void zone_release(lgdm_ctx* c);
+// breadth-first levels of a graph (CSR adj_ptr / adj over n nodes), each
+// component from a pseudo-peripheral node; returns the number of levels
+int64_t zone_levels(int64_t n, const int64_t* adj_ptr, const int32_t* adj, int32_t* level);
 struct AmgInfo {
   int levels;
   int64_t nodes[16];

@@ -10,28 +10,40 @@
 // steps.  Those modes live on the few elements that are both loading and
 // highly damaged, so the preconditioner solves that zone exactly:
 //
-//   zone   nodes of the elements with a Gauss point that is loading and has
-//          trial damage D >= zone_damage (0.999 by default; moved tenfold
-//          closer to 1, twice at most, while the zone exceeds ZONE_MAX_DOFS
-//          unknowns), chosen afresh for every tangent
-//   Z      the zone's principal block of S K, dense (column major), factored
-//          by LU with partial pivoting and inverted (rocSOLVER getrf, getri)
-//   apply  x_z = Z^-1 b_z; r = b - S K x_z (only rows of the zone and its
-//          neighbour nodes change); out = x_z + M_mg r, with M_mg the
-//          multigrid cycle (multiplicative: a CPU model on the 128x32x16
-//          beam after its peak, zone from D >= 0.99, needed 64 GMRES steps
-//          with it, 97 with the additive form x_z + M_mg b, and more than
-//          3000 without a zone)
+//   zone    nodes of the elements with a Gauss point that is loading and has
+//           trial damage D >= zone_damage (0.99 by default; moved tenfold
+//           closer to 1, twice at most, while the zone exceeds the limits
+//           below), chosen afresh for every tangent
+//   levels  breadth-first level sets of the zone's node graph, each
+//           connected component from a pseudo-peripheral node (George & Liu,
+//           ACM TOMS 5, 1979): a node's neighbours lie in its own level or
+//           the next or previous one, so in level order the zone's block Z of
+//           S K is block tridiagonal.  Consecutive levels are merged into
+//           groups of at least ZONE_GROUP_MIN unknowns (fewer launches).
+//   factor  block LU over the groups: S_0 = Z_00, S_k = Z_kk - Z_k,k-1
+//           S_{k-1}^-1 Z_k-1,k; each S_k by LU with partial pivoting and
+//           explicit inverse W_k (rocSOLVER getrf, getri); N_k = W_k Z_k,k-1
+//           and M_k = W_k Z_k,k+1 (rocBLAS gemm).  A CPU model on the
+//           128x32x16 beam after its peak (zone from D >= 0.99, 5,808
+//           unknowns, condition number 9e8) took 5e9 flops against 4e11 for
+//           the dense LU, and its solve differed from the dense one by 5e-9.
+//   apply   x_z = Z^-1 b_z by the two sweeps y_k = W_k b_k - N_k y_{k-1},
+//           x_k = y_k - M_k x_{k+1}; r = b - S K x_z (only rows of the zone
+//           and its neighbour nodes change); out = x_z + M_mg r, with M_mg
+//           the multigrid cycle (multiplicative: the same CPU model needed 64
+//           GMRES steps with it, 97 with the additive form x_z + M_mg b, and
+//           more than 3000 without a zone)
 //
 // Within one Newton increment a tangent whose zone has the same nodes as the
-// one last factored keeps that inverse: the zone's block changes little
-// between Newton iterates, while its factorization costs far more than a
-// solve.  The apply is a fixed linear map for the whole solve, so IDR(s)
-// takes it as its preconditioner unchanged.  Every sum has a fixed order.
+// one last factored keeps those factors: the zone's block changes little
+// between Newton iterates.  The apply is a fixed linear map for the whole
+// solve, so IDR(s) takes it as its preconditioner unchanged.  Every sum has a
+// fixed order.
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -39,30 +51,48 @@
 
 namespace lgdm {
 
+namespace {
+
+constexpr int64_t ZONE_GROUP_MIN = 384;           // unknowns per group, at least (but the last)
+constexpr int64_t ZONE_MAX_GROUP = 4096;          // unknowns per group, at most
+constexpr int64_t ZONE_MAX_PANEL = 160ll << 20;   // doubles of the factors (1.25 GiB)
+
+}  // namespace
+
 struct Zone {
   // host copies of the mesh structure (taken at the first setup)
   std::vector<int32_t> conn, nbr_ptr, nbr;
   std::vector<uint8_t> eflag;
-  std::vector<int32_t> zmap_h;              // node -> zone node, -1 outside
+  std::vector<int32_t> zmap_h;              // node -> zone index, -1 outside
+  // the zone of the current tangent, in level order
+  std::vector<int32_t> nodes, group;        // zone index -> node, group
+  std::vector<int64_t> goff, poff, qoff;    // group offsets: unknowns, panel P, panel Q
+  int64_t L = 0, mmax = 0;
   // device
   uint8_t* eflag_d = nullptr;               // [n_elems]
   int32_t* zmap = nullptr;                  // [n_nodes]
-  int32_t* znodes = nullptr;                // [cap_nodes]
+  int32_t* znodes = nullptr;                // [cap_nodes] zone index -> node
+  int32_t* zgroup = nullptr;                // [cap_nodes] zone index -> group
+  int64_t* goff_d = nullptr;                // [cap_groups + 1]
+  int64_t* poff_d = nullptr;                // [cap_groups + 1]
   int32_t* halo = nullptr;                  // nodes whose rows r = b - S K x_z changes [cap_halo]
-  double* Z = nullptr;                      // [cap_dofs * cap_dofs]
-  rocblas_int* ipiv = nullptr;              // [cap_dofs]
-  rocblas_int* info = nullptr;              // [1]
-  double* bz = nullptr;                     // [cap_dofs] b at the zone's dofs
-  double* xz = nullptr;                     // [cap_dofs] Z^-1 b_z
+  // per group k (m_k unknowns; column major, leading dimension m_k):
+  //   P_k = [Z_k,k-1 | Z_kk -> W_k | Z_k,k+1]   Q_k = [N_k | M_k]
+  double* P = nullptr;                      // [cap_p]
+  double* Q = nullptr;                      // [cap_q]
+  rocblas_int* ipiv = nullptr;              // [cap_m]
+  rocblas_int* info = nullptr;              // [2 cap_groups]
+  double* bz = nullptr;                     // [cap_nodes * 4] b at the zone's unknowns
+  double* xz = nullptr;                     // [cap_nodes * 4] Z^-1 b_z
   double* r = nullptr;                      // [ndof]
-  int64_t cap_dofs = 0, cap_halo = 0;
+  int64_t cap_nodes = 0, cap_halo = 0, cap_groups = 0, cap_p = 0, cap_q = 0, cap_m = 0;
   void* ws = nullptr;
   size_t ws_size = 0;
   rocblas_handle handle = nullptr;
   int64_t nz = 0, nh = 0;                   // zone nodes, halo nodes of the current tangent
   bool active = false;
-  double damage = 0.0;                      // threshold the current zone was chosen with
-  // the zone whose inverse Z holds: its nodes and the increment it was built in
+  // the zone whose factors P and Q hold: its nodes (ascending) and the
+  // increment it was built in
   std::vector<int32_t> built_nodes;
   int64_t built_serial = -1;
 };
@@ -91,13 +121,15 @@ __global__ void zone_zero_kernel(int64_t n, double* __restrict__ p) {
     p[i] = 0.0;
 }
 
-// Z[(4 za + i) + (4 zq + j) ld] = (S K)_{4a+i, 4q+j} for zone nodes a, q;
-// one thread per (zone node, neighbour position)
+// P_g entries of the zone's block of S K: one thread per (zone node,
+// neighbour position); the neighbour's group is g - 1, g or g + 1
 template <typename T>
 __global__ void zone_build_kernel(int64_t nz, int max_nbr, const int32_t* __restrict__ znodes,
-                                  const int32_t* __restrict__ zmap, const int32_t* __restrict__ row_ptr,
-                                  const int32_t* __restrict__ nbr_ptr, const int32_t* __restrict__ nbr,
-                                  const T* __restrict__ vals, double se, int64_t ld, double* __restrict__ Z) {
+                                  const int32_t* __restrict__ zmap, const int32_t* __restrict__ zgroup,
+                                  const int64_t* __restrict__ goff, const int64_t* __restrict__ poff,
+                                  const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ nbr_ptr,
+                                  const int32_t* __restrict__ nbr, const T* __restrict__ vals, double se,
+                                  double* __restrict__ P) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nz * max_nbr) return;
   const int64_t za = t / max_nbr;
@@ -107,21 +139,57 @@ __global__ void zone_build_kernel(int64_t nz, int max_nbr, const int32_t* __rest
   if (p >= nnb) return;
   const int32_t zq = zmap[nbr[nb0 + p]];
   if (zq < 0) return;
+  const int ga = zgroup[za], gq = zgroup[zq];
+  const int64_t g0 = goff[ga], m = goff[ga + 1] - g0, mp = ga > 0 ? g0 - goff[ga - 1] : 0;
+  // the host checked that neighbouring groups differ by at most one
+  const int64_t colbase = gq < ga ? 0 : (gq == ga ? mp : mp + m);
+  const int64_t col0 = colbase + 4 * (int64_t)zq - goff[gq], row0 = 4 * za - g0;
+  double* Pg = P + poff[ga];
   const int64_t rowlen = (int64_t)nnb * 4, rb = row_ptr[a * 4];
   for (int i = 0; i < 4; ++i) {
     const double s = i == 3 ? se : 1.0;
     for (int j = 0; j < 4; ++j)
-      Z[(4 * za + i) + (4 * (int64_t)zq + j) * ld] = s * (double)vals[rb + i * rowlen + (int64_t)p * 4 + j];
+      Pg[(row0 + i) + (col0 + j) * m] = s * (double)vals[rb + i * rowlen + (int64_t)p * 4 + j];
   }
 }
 
-// bz = b at the zone's dofs
+// bz = b at the zone's unknowns
 __global__ void zone_gather_kernel(int64_t nz, const int32_t* __restrict__ znodes, const double* __restrict__ b,
                                    double* __restrict__ bz, const double* __restrict__ sc) {
   if (sc && sc[KSLOT_DONE] != 0.0) return;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nz * 4) return;
   bz[t] = b[(int64_t)znodes[t / 4] * 4 + (t % 4)];
+}
+
+// One group's step of a sweep: y[r] = sum_c A[r, c] u[c] - sum_c B[r, c] v[c]
+// over r < m (A: m x na, B: m x nb, column major with leading dimension m;
+// na or nb may be 0).  A workgroup takes GV_ROWS rows; its GV_SLICES column
+// slices are summed in LDS in slice order.  With accumulate, y[r] is added to
+// the result (y = y + A u - B v).
+constexpr int GV_ROWS = 16;
+constexpr int GV_SLICES = ZBS / GV_ROWS;
+__global__ void __launch_bounds__(ZBS) zone_gemv_kernel(int64_t m, int64_t na, const double* __restrict__ A,
+                                                        const double* __restrict__ u, int64_t nb,
+                                                        const double* __restrict__ B, const double* __restrict__ v,
+                                                        double* __restrict__ y, int accumulate,
+                                                        const double* __restrict__ sc) {
+  if (sc && sc[KSLOT_DONE] != 0.0) return;
+  __shared__ double part[GV_SLICES][GV_ROWS];
+  const int lr = threadIdx.x % GV_ROWS, sl = threadIdx.x / GV_ROWS;
+  const int64_t row = (int64_t)blockIdx.x * GV_ROWS + lr;
+  double acc = 0.0;
+  if (row < m) {
+    for (int64_t c = sl; c < na; c += GV_SLICES) acc += A[row + c * m] * u[c];
+    for (int64_t c = sl; c < nb; c += GV_SLICES) acc -= B[row + c * m] * v[c];
+  }
+  part[sl][lr] = acc;
+  __syncthreads();
+  if (sl == 0 && row < m) {
+    double s = 0.0;
+    for (int q = 0; q < GV_SLICES; ++q) s += part[q][lr];
+    y[row] = accumulate ? y[row] + s : s;
+  }
 }
 
 // r = b everywhere (the halo rows are overwritten next)
@@ -157,7 +225,7 @@ __global__ void zone_residual_kernel(int64_t nh, const int32_t* __restrict__ hal
   r[row] = b[row] - (i == 3 ? se : 1.0) * acc;
 }
 
-// out += x_z at the zone's dofs
+// out += x_z at the zone's unknowns
 __global__ void zone_scatter_kernel(int64_t nz, const int32_t* __restrict__ znodes, const double* __restrict__ xz,
                                     double* __restrict__ out, const double* __restrict__ sc) {
   if (sc && sc[KSLOT_DONE] != 0.0) return;
@@ -172,6 +240,65 @@ hipError_t rb_err(rocblas_status s) { return s == rocblas_status_success ? hipSu
 
 }  // namespace
 
+// Breadth-first levels of the zone's node graph (zone indices 0..nz-1,
+// adjacency adj_ptr / adj): every connected component from a
+// pseudo-peripheral node, components one after the other.  Fills the level
+// of each index and returns the number of levels.
+int64_t zone_levels(int64_t nz, const int64_t* adj_ptr, const int32_t* adj, int32_t* level) {
+  std::fill(level, level + nz, -1);
+  std::vector<int32_t> dist(nz, -1), queue;
+  queue.reserve(nz);
+  // BFS from s over its component: distances in dist, visit order in queue;
+  // returns the eccentricity of s
+  auto bfs = [&](int32_t s) {
+    queue.clear();
+    queue.push_back(s);
+    dist[s] = 0;
+    int32_t ecc = 0;
+    for (size_t h = 0; h < queue.size(); ++h) {
+      const int32_t v = queue[h];
+      ecc = std::max(ecc, dist[v]);
+      for (int64_t p = adj_ptr[v]; p < adj_ptr[v + 1]; ++p)
+        if (dist[adj[p]] < 0) {
+          dist[adj[p]] = dist[v] + 1;
+          queue.push_back(adj[p]);
+        }
+    }
+    return ecc;
+  };
+  auto reset = [&]() {
+    for (int32_t v : queue) dist[v] = -1;
+  };
+  int64_t base = 0;
+  for (int32_t i0 = 0; i0 < (int32_t)nz; ++i0) {
+    if (level[i0] >= 0) continue;
+    // pseudo-peripheral start: restart from a least-connected node of the
+    // last level while the eccentricity grows
+    int32_t start = i0;
+    int32_t ecc = bfs(start);
+    for (int round = 0; round < 8; ++round) {
+      int32_t cand = -1;
+      int64_t cdeg = 0;
+      for (int32_t v : queue)
+        if (dist[v] == ecc) {
+          const int64_t d = adj_ptr[v + 1] - adj_ptr[v];
+          if (cand < 0 || d < cdeg) cand = v, cdeg = d;
+        }
+      reset();
+      const int32_t e2 = bfs(cand);
+      if (e2 <= ecc) break;
+      start = cand;
+      ecc = e2;
+    }
+    reset();
+    ecc = bfs(start);
+    for (int32_t v : queue) level[v] = (int32_t)(base + dist[v]);
+    reset();
+    base += ecc + 1;
+  }
+  return base;
+}
+
 void zone_release(lgdm_ctx* c) {
   if (!c->zone) return;
   if (c->zone->handle) (void)rocblas_destroy_handle(c->zone->handle);
@@ -179,8 +306,9 @@ void zone_release(lgdm_ctx* c) {
   c->zone = nullptr;
 }
 
-// Choose the zone of the current tangent and factor its block.  Leaves the
-// zone inactive (plain multigrid) where there is none or it does not fit.
+// Choose the zone of the current tangent, order it by levels and factor its
+// block.  Leaves the zone inactive (plain multigrid) where there is none or
+// it does not fit.
 hipError_t zone_setup(lgdm_ctx* c, bool allow_alloc, bool reuse, double dmin0, bool* factored, std::string& msg) {
   *factored = false;
   if (c->dim != 3 || c->nd != 4 || c->order2) return hipSuccess;
@@ -206,8 +334,7 @@ hipError_t zone_setup(lgdm_ctx* c, bool allow_alloc, bool reuse, double dmin0, b
     z.eflag_d = (uint8_t*)dalloc(c, ne);
     z.zmap = (int32_t*)dalloc(c, nn * sizeof(int32_t));
     z.r = (double*)dalloc(c, c->ndof * sizeof(double));
-    z.info = (rocblas_int*)dalloc(c, 64);
-    if (!z.eflag_d || !z.zmap || !z.r || !z.info) {
+    if (!z.eflag_d || !z.zmap || !z.r) {
       msg = "device allocation failed (process zone)";
       return hipErrorOutOfMemory;
     }
@@ -217,109 +344,222 @@ hipError_t zone_setup(lgdm_ctx* c, bool allow_alloc, bool reuse, double dmin0, b
     }
   }
   if (rocblas_set_stream(z.handle, c->stream) != rocblas_status_success) return hipErrorUnknown;
+  std::fill(z.zmap_h.begin(), z.zmap_h.end(), -1);
   // the zone: raise the damage threshold until it fits
-  std::vector<int32_t> znodes, halo;
+  std::vector<int32_t> sorted, level, lgroup;
+  std::vector<int64_t> adj_ptr;
+  std::vector<int32_t> adj;
+  bool fits = false;
   for (double dmin : {dmin0, 1.0 - 0.1 * (1.0 - dmin0), 1.0 - 0.01 * (1.0 - dmin0)}) {
     zone_flag_kernel<<<nblocks(ne), ZBS, 0, c->stream>>>(ne, c->ngp, c->kappa_t, c->kappa_n, c->D_t,
                                                          c->mat.tol_hist, dmin, z.eflag_d);
     if ((e = hipMemcpyAsync(z.eflag.data(), z.eflag_d, ne, hipMemcpyDeviceToHost, c->stream)) ||
         (e = hipStreamSynchronize(c->stream)))
       return e;
-    znodes.clear();
+    sorted.clear();
     for (int64_t el = 0; el < ne; ++el)
       if (z.eflag[el])
-        for (int a = 0; a < c->nen; ++a) znodes.push_back(z.conn[el * c->nen + a]);
-    std::sort(znodes.begin(), znodes.end());
-    znodes.erase(std::unique(znodes.begin(), znodes.end()), znodes.end());
-    z.damage = dmin;
-    if ((int64_t)znodes.size() * 4 <= ZONE_MAX_DOFS) break;
-  }
-  z.nz = (int64_t)znodes.size();
-  if (z.nz == 0 || z.nz * 4 > ZONE_MAX_DOFS) return hipSuccess;
-  // a later tangent of the same increment with the same zone keeps the
-  // inverse (the halo residual and the cycle read the current tangent)
-  if (reuse && c->in_increment && z.built_serial == c->inc_serial && znodes == z.built_nodes) {
-    z.active = true;
-    return hipSuccess;
+        for (int a = 0; a < c->nen; ++a) sorted.push_back(z.conn[el * c->nen + a]);
+    std::sort(sorted.begin(), sorted.end());
+    sorted.erase(std::unique(sorted.begin(), sorted.end()), sorted.end());
+    const int64_t nz = (int64_t)sorted.size();
+    if (nz == 0) return hipSuccess;
+    // a later tangent of the same increment with the same zone keeps the
+    // factors (the halo residual and the cycle read the current tangent)
+    if (reuse && c->in_increment && z.built_serial == c->inc_serial && sorted == z.built_nodes) {
+      z.active = true;
+      return hipSuccess;
+    }
+    // the zone's node graph and its levels, then the groups
+    for (int64_t i = 0; i < nz; ++i) z.zmap_h[sorted[i]] = (int32_t)i;
+    adj_ptr.assign(nz + 1, 0);
+    adj.clear();
+    for (int64_t i = 0; i < nz; ++i) {
+      const int32_t a = sorted[i];
+      for (int32_t p = z.nbr_ptr[a]; p < z.nbr_ptr[a + 1]; ++p) {
+        const int32_t q = z.zmap_h[z.nbr[p]];
+        if (q >= 0 && q != i) adj.push_back(q);
+      }
+      adj_ptr[i + 1] = (int64_t)adj.size();
+    }
+    for (int32_t a : sorted) z.zmap_h[a] = -1;
+    level.resize(nz);
+    const int64_t nlev = zone_levels(nz, adj_ptr.data(), adj.data(), level.data());
+    std::vector<int64_t> lcount(nlev, 0);
+    for (int64_t i = 0; i < nz; ++i) lcount[level[i]] += 4;
+    lgroup.assign(nlev, 0);
+    z.goff.assign(1, 0);
+    int64_t acc = 0;
+    for (int64_t l = 0; l < nlev; ++l) {
+      lgroup[l] = (int32_t)(z.goff.size() - 1);
+      acc += lcount[l];
+      if (acc >= ZONE_GROUP_MIN || l + 1 == nlev) {
+        z.goff.push_back(z.goff.back() + acc);
+        acc = 0;
+      }
+    }
+    z.L = (int64_t)z.goff.size() - 1;
+    z.mmax = 0;
+    for (int64_t k = 0; k < z.L; ++k) z.mmax = std::max(z.mmax, z.goff[k + 1] - z.goff[k]);
+    z.poff.assign(z.L + 1, 0);
+    z.qoff.assign(z.L + 1, 0);
+    for (int64_t k = 0; k < z.L; ++k) {
+      const int64_t m = z.goff[k + 1] - z.goff[k], mp = k > 0 ? z.goff[k] - z.goff[k - 1] : 0,
+                    mn = k + 1 < z.L ? z.goff[k + 2] - z.goff[k + 1] : 0;
+      z.poff[k + 1] = z.poff[k] + m * (mp + m + mn);
+      z.qoff[k + 1] = z.qoff[k] + m * (mp + mn);
+    }
+    if (z.mmax <= ZONE_MAX_GROUP && z.poff[z.L] + z.qoff[z.L] <= ZONE_MAX_PANEL) {
+      fits = true;
+      break;
+    }
   }
   z.built_serial = -1;
-  // node -> zone index, and the halo: zone nodes and their neighbours
+  if (!fits) return hipSuccess;
+  // zone order: by group, ascending node within a group
+  z.nz = (int64_t)sorted.size();
+  z.nodes.resize(z.nz);
+  z.group.resize(z.nz);
+  {
+    std::vector<int64_t> fill(z.L, 0);
+    for (int64_t k = 0; k < z.L; ++k) fill[k] = z.goff[k] / 4;
+    for (int64_t i = 0; i < z.nz; ++i) {
+      const int32_t g = lgroup[level[i]];
+      const int64_t pos = fill[g]++;
+      z.nodes[pos] = sorted[i];
+      z.group[pos] = g;
+    }
+  }
+  // node -> zone index; the groups of neighbouring zone nodes differ by at
+  // most one (levels of a breadth-first search, merged in runs)
   std::fill(z.zmap_h.begin(), z.zmap_h.end(), -1);
-  for (int64_t i = 0; i < z.nz; ++i) z.zmap_h[znodes[i]] = (int32_t)i;
+  for (int64_t i = 0; i < z.nz; ++i) z.zmap_h[z.nodes[i]] = (int32_t)i;
+  for (int64_t i = 0; i < z.nz; ++i)
+    for (int32_t p = z.nbr_ptr[z.nodes[i]]; p < z.nbr_ptr[z.nodes[i] + 1]; ++p) {
+      const int32_t q = z.zmap_h[z.nbr[p]];
+      if (q >= 0 && std::abs(z.group[q] - z.group[i]) > 1) {
+        msg = "process zone: neighbouring nodes more than one level apart";
+        return hipErrorUnknown;
+      }
+    }
+  // the halo: zone nodes and their neighbours
+  std::vector<int32_t> halo;
   std::vector<uint8_t> inh(nn, 0);
-  for (int32_t a : znodes)
+  for (int32_t a : z.nodes)
     for (int32_t p = z.nbr_ptr[a]; p < z.nbr_ptr[a + 1]; ++p) inh[z.nbr[p]] = 1;
   for (int64_t a = 0; a < nn; ++a)
     if (inh[a]) halo.push_back((int32_t)a);
   z.nh = (int64_t)halo.size();
-  const int64_t n = z.nz * 4;
-  if (n > z.cap_dofs || z.nh > z.cap_halo) {
+  const int64_t np = z.poff[z.L], nq = z.qoff[z.L];
+  if (z.nz > z.cap_nodes || z.nh > z.cap_halo || z.L > z.cap_groups || np > z.cap_p || nq > z.cap_q ||
+      z.mmax > z.cap_m) {
     if (!allow_alloc) return hipErrorNotReady;
     // grow the buffers to this zone (kept for later tangents)
-    const int64_t cap = std::max<int64_t>(n, z.cap_dofs), caph = std::max<int64_t>(z.nh, z.cap_halo);
-    dfree(c, z.Z);
-    dfree(c, z.ipiv);
-    dfree(c, z.bz);
-    dfree(c, z.xz);
-    dfree(c, z.znodes);
-    dfree(c, z.halo);
-    dfree(c, z.ws);
-    z.Z = (double*)dalloc(c, (size_t)cap * cap * sizeof(double));
-    z.ipiv = (rocblas_int*)dalloc(c, cap * sizeof(rocblas_int));
-    z.bz = (double*)dalloc(c, cap * sizeof(double));
-    z.xz = (double*)dalloc(c, cap * sizeof(double));
-    z.znodes = (int32_t*)dalloc(c, (cap / 4) * sizeof(int32_t));
+    const int64_t capn = std::max(z.nz, z.cap_nodes), caph = std::max(z.nh, z.cap_halo),
+                  capg = std::max(z.L, z.cap_groups), capp = std::max(np, z.cap_p), capq = std::max(nq, z.cap_q),
+                  capm = std::max(z.mmax, z.cap_m);
+    for (void* p : {(void*)z.P, (void*)z.Q, (void*)z.ipiv, (void*)z.info, (void*)z.bz, (void*)z.xz,
+                    (void*)z.znodes, (void*)z.zgroup, (void*)z.goff_d, (void*)z.poff_d, (void*)z.halo, z.ws})
+      dfree(c, p);
+    z.P = (double*)dalloc(c, capp * sizeof(double));
+    z.Q = (double*)dalloc(c, std::max<int64_t>(capq, 1) * sizeof(double));
+    z.ipiv = (rocblas_int*)dalloc(c, capm * sizeof(rocblas_int));
+    z.info = (rocblas_int*)dalloc(c, 2 * capg * sizeof(rocblas_int));
+    z.bz = (double*)dalloc(c, capn * 4 * sizeof(double));
+    z.xz = (double*)dalloc(c, capn * 4 * sizeof(double));
+    z.znodes = (int32_t*)dalloc(c, capn * sizeof(int32_t));
+    z.zgroup = (int32_t*)dalloc(c, capn * sizeof(int32_t));
+    z.goff_d = (int64_t*)dalloc(c, (capg + 1) * sizeof(int64_t));
+    z.poff_d = (int64_t*)dalloc(c, (capg + 1) * sizeof(int64_t));
     z.halo = (int32_t*)dalloc(c, caph * sizeof(int32_t));
-    // rocSOLVER's workspace for getrf / getrs at this size, from the context's allocator
+    // the workspace of getrf / getri / gemm at the largest group, from the
+    // context's allocator
     size_t ws = 0;
     rocblas_start_device_memory_size_query(z.handle);
-    (void)rocsolver_dgetrf(z.handle, (rocblas_int)cap, (rocblas_int)cap, nullptr, (rocblas_int)cap, nullptr, nullptr);
-    (void)rocsolver_dgetri(z.handle, (rocblas_int)cap, nullptr, (rocblas_int)cap, nullptr, nullptr);
+    (void)rocsolver_dgetrf(z.handle, (rocblas_int)capm, (rocblas_int)capm, nullptr, (rocblas_int)capm, nullptr,
+                           nullptr);
+    (void)rocsolver_dgetri(z.handle, (rocblas_int)capm, nullptr, (rocblas_int)capm, nullptr, nullptr);
+    {
+      const double one = 1.0;
+      (void)rocblas_dgemm(z.handle, rocblas_operation_none, rocblas_operation_none, (rocblas_int)capm,
+                          (rocblas_int)capm, (rocblas_int)capm, &one, nullptr, (rocblas_int)capm, nullptr,
+                          (rocblas_int)capm, &one, nullptr, (rocblas_int)capm);
+    }
     rocblas_stop_device_memory_size_query(z.handle, &ws);
     z.ws_size = std::max<size_t>(ws, 256);
     z.ws = dalloc(c, z.ws_size);
-    if (!z.Z || !z.ipiv || !z.bz || !z.xz || !z.znodes || !z.halo || !z.ws) {
-      z.cap_dofs = z.cap_halo = 0;
-      msg = "device allocation failed (process zone block)";
+    if (!z.P || !z.Q || !z.ipiv || !z.info || !z.bz || !z.xz || !z.znodes || !z.zgroup || !z.goff_d || !z.poff_d ||
+        !z.halo || !z.ws) {
+      z.cap_nodes = z.cap_halo = z.cap_groups = z.cap_p = z.cap_q = z.cap_m = 0;
+      msg = "device allocation failed (process zone factors)";
       return hipErrorOutOfMemory;
     }
     if (rocblas_set_workspace(z.handle, z.ws, z.ws_size) != rocblas_status_success) return hipErrorUnknown;
-    z.cap_dofs = cap;
+    z.cap_nodes = capn;
     z.cap_halo = caph;
+    z.cap_groups = capg;
+    z.cap_p = capp;
+    z.cap_q = capq;
+    z.cap_m = capm;
   }
   if ((e = hipMemcpyAsync(z.zmap, z.zmap_h.data(), nn * 4, hipMemcpyHostToDevice, c->stream)) ||
-      (e = hipMemcpyAsync(z.znodes, znodes.data(), z.nz * 4, hipMemcpyHostToDevice, c->stream)) ||
+      (e = hipMemcpyAsync(z.znodes, z.nodes.data(), z.nz * 4, hipMemcpyHostToDevice, c->stream)) ||
+      (e = hipMemcpyAsync(z.zgroup, z.group.data(), z.nz * 4, hipMemcpyHostToDevice, c->stream)) ||
+      (e = hipMemcpyAsync(z.goff_d, z.goff.data(), (z.L + 1) * 8, hipMemcpyHostToDevice, c->stream)) ||
+      (e = hipMemcpyAsync(z.poff_d, z.poff.data(), (z.L + 1) * 8, hipMemcpyHostToDevice, c->stream)) ||
       (e = hipMemcpyAsync(z.halo, halo.data(), z.nh * 4, hipMemcpyHostToDevice, c->stream)))
     return e;
-  // the dense block, leading dimension n
-  zone_zero_kernel<<<std::min<int64_t>(nblocks(n * n), 4096), ZBS, 0, c->stream>>>(n * n, z.Z);
+  // the panels P_k of the zone's block
+  zone_zero_kernel<<<std::min<int64_t>(nblocks(np), 4096), ZBS, 0, c->stream>>>(np, z.P);
   const double se = c->mat.E / c->mat.h;
   const int64_t work = z.nz * c->max_nbr;
   if (c->precision == LGDM_MIXED)
-    zone_build_kernel<float><<<nblocks(work), ZBS, 0, c->stream>>>(z.nz, c->max_nbr, z.znodes, z.zmap, c->row_ptr,
-                                                                   c->nbr_ptr, c->nbr, c->vals32, se, n, z.Z);
+    zone_build_kernel<float><<<nblocks(work), ZBS, 0, c->stream>>>(
+        z.nz, c->max_nbr, z.znodes, z.zmap, z.zgroup, z.goff_d, z.poff_d, c->row_ptr, c->nbr_ptr, c->nbr, c->vals32,
+        se, z.P);
   else
-    zone_build_kernel<double><<<nblocks(work), ZBS, 0, c->stream>>>(z.nz, c->max_nbr, z.znodes, z.zmap, c->row_ptr,
-                                                                    c->nbr_ptr, c->nbr, c->vals, se, n, z.Z);
+    zone_build_kernel<double><<<nblocks(work), ZBS, 0, c->stream>>>(
+        z.nz, c->max_nbr, z.znodes, z.zmap, z.zgroup, z.goff_d, z.poff_d, c->row_ptr, c->nbr_ptr, c->nbr, c->vals,
+        se, z.P);
   if ((e = hipGetLastError())) return e;
-  if ((e = rb_err(rocsolver_dgetrf(z.handle, (rocblas_int)n, (rocblas_int)n, z.Z, (rocblas_int)n, z.ipiv, z.info))))
-    return e;
-  rocblas_int info = 0;
-  if ((e = hipMemcpyAsync(&info, z.info, sizeof(info), hipMemcpyDeviceToHost, c->stream)) ||
+  // block LU over the groups, in order
+  const double one = 1.0, mone = -1.0, zero = 0.0;
+  for (int64_t k = 0; k < z.L; ++k) {
+    const int64_t m = z.goff[k + 1] - z.goff[k], mp = k > 0 ? z.goff[k] - z.goff[k - 1] : 0,
+                  mn = k + 1 < z.L ? z.goff[k + 2] - z.goff[k + 1] : 0;
+    double* Lk = z.P + z.poff[k];
+    double* Dk = Lk + m * mp;
+    double* Uk = Dk + m * m;
+    double* Nk = z.Q + z.qoff[k];
+    double* Mk = Nk + m * mp;
+    const rocblas_int im = (rocblas_int)m, imp = (rocblas_int)mp, imn = (rocblas_int)mn;
+    if (k > 0) {
+      // S_k = Z_kk - Z_k,k-1 M_{k-1}
+      const int64_t mpp = k > 1 ? z.goff[k - 1] - z.goff[k - 2] : 0;
+      const double* Mprev = z.Q + z.qoff[k - 1] + mp * mpp;
+      if ((e = rb_err(rocblas_dgemm(z.handle, rocblas_operation_none, rocblas_operation_none, im, im, imp, &mone, Lk,
+                                    im, Mprev, imp, &one, Dk, im))))
+        return e;
+    }
+    if ((e = rb_err(rocsolver_dgetrf(z.handle, im, im, Dk, im, z.ipiv, z.info + 2 * k)))) return e;
+    if ((e = rb_err(rocsolver_dgetri(z.handle, im, Dk, im, z.ipiv, z.info + 2 * k + 1)))) return e;
+    if (k > 0 && (e = rb_err(rocblas_dgemm(z.handle, rocblas_operation_none, rocblas_operation_none, im, imp, im,
+                                           &one, Dk, im, Lk, im, &zero, Nk, im))))
+      return e;
+    if (mn > 0 && (e = rb_err(rocblas_dgemm(z.handle, rocblas_operation_none, rocblas_operation_none, im, imn, im,
+                                            &one, Dk, im, Uk, im, &zero, Mk, im))))
+      return e;
+  }
+  std::vector<rocblas_int> info(2 * z.L, 0);
+  if ((e = hipMemcpyAsync(info.data(), z.info, info.size() * sizeof(rocblas_int), hipMemcpyDeviceToHost,
+                          c->stream)) ||
       (e = hipStreamSynchronize(c->stream)))
     return e;
-  if (info != 0) return hipSuccess;  // an exactly singular block leaves the plain cycle
-  // the explicit inverse: each application is then one pass over it (a
-  // matrix-vector product), where two triangular solves with one right-hand
-  // side are latency-bound
-  if ((e = rb_err(rocsolver_dgetri(z.handle, (rocblas_int)n, z.Z, (rocblas_int)n, z.ipiv, z.info)))) return e;
-  if ((e = hipMemcpyAsync(&info, z.info, sizeof(info), hipMemcpyDeviceToHost, c->stream)) ||
-      (e = hipStreamSynchronize(c->stream)))
-    return e;
-  z.active = info == 0;  // an exactly singular block leaves the plain cycle
   *factored = true;
+  // an exactly singular group leaves the plain cycle
+  z.active = std::all_of(info.begin(), info.end(), [](rocblas_int v) { return v == 0; });
   if (z.active) {
-    z.built_nodes.swap(znodes);
+    z.built_nodes.swap(sorted);
     z.built_serial = c->in_increment ? c->inc_serial : -1;
   }
   return hipSuccess;
@@ -338,12 +578,22 @@ hipError_t zone_apply(lgdm_ctx* c, const double* b, double* out, const double* s
   Zone& z = *c->zone;
   const int64_t n = z.nz * 4;
   zone_gather_kernel<<<nblocks(n), ZBS, 0, st>>>(z.nz, z.znodes, b, z.bz, sc);
-  if (st != c->stream) (void)rocblas_set_stream(z.handle, st);
-  const double one = 1.0, zero = 0.0;
-  hipError_t e = rb_err(rocblas_dgemv(z.handle, rocblas_operation_none, (rocblas_int)n, (rocblas_int)n, &one, z.Z,
-                                      (rocblas_int)n, z.bz, 1, &zero, z.xz, 1));
-  if (st != c->stream) (void)rocblas_set_stream(z.handle, c->stream);
-  if (e != hipSuccess) return e;
+  // forward sweep: y_k = W_k b_k - N_k y_{k-1}
+  for (int64_t k = 0; k < z.L; ++k) {
+    const int64_t m = z.goff[k + 1] - z.goff[k], mp = k > 0 ? z.goff[k] - z.goff[k - 1] : 0;
+    const double* Wk = z.P + z.poff[k] + m * mp;
+    const double* Nk = z.Q + z.qoff[k];
+    zone_gemv_kernel<<<(unsigned)((m + GV_ROWS - 1) / GV_ROWS), ZBS, 0, st>>>(
+        m, m, Wk, z.bz + z.goff[k], mp, Nk, k > 0 ? z.xz + z.goff[k - 1] : nullptr, z.xz + z.goff[k], 0, sc);
+  }
+  // backward sweep: x_k = y_k - M_k x_{k+1}
+  for (int64_t k = z.L - 2; k >= 0; --k) {
+    const int64_t m = z.goff[k + 1] - z.goff[k], mp = k > 0 ? z.goff[k] - z.goff[k - 1] : 0,
+                  mn = z.goff[k + 2] - z.goff[k + 1];
+    const double* Mk = z.Q + z.qoff[k] + m * mp;
+    zone_gemv_kernel<<<(unsigned)((m + GV_ROWS - 1) / GV_ROWS), ZBS, 0, st>>>(
+        m, 0, nullptr, nullptr, mn, Mk, z.xz + z.goff[k + 1], z.xz + z.goff[k], 1, sc);
+  }
   zone_copy_kernel<<<std::min<int64_t>(nblocks(c->ndof), 2048), ZBS, 0, st>>>(c->ndof, b, z.r, sc);
   const double se = c->mat.E / c->mat.h;
   if (c->precision == LGDM_MIXED)
@@ -352,9 +602,25 @@ hipError_t zone_apply(lgdm_ctx* c, const double* b, double* out, const double* s
   else
     zone_residual_kernel<double><<<nblocks(z.nh * 4), ZBS, 0, st>>>(z.nh, z.halo, z.zmap, c->row_ptr, c->nbr_ptr,
                                                                     c->nbr, c->vals, se, b, z.xz, z.r, sc);
+  hipError_t e;
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = amg_cycle(c, z.r, out, sc, st)) != hipSuccess) return e;
   zone_scatter_kernel<<<nblocks(n), ZBS, 0, st>>>(z.nz, z.znodes, z.xz, out, sc);
   return hipGetLastError();
 }
 
 }  // namespace lgdm
+
+extern "C" lgdm_status lgdm_zone_levels(int64_t n, const int32_t* ptr, const int32_t* adj, int32_t* level,
+                                        int64_t* n_levels) {
+  if (n < 0 || !ptr || !level || !n_levels || (n > 0 && !adj && ptr[n] > 0)) return LGDM_ERR_INVALID_ARG;
+  if (ptr[0] != 0) return LGDM_ERR_INVALID_ARG;
+  for (int64_t a = 0; a < n; ++a) {
+    if (ptr[a + 1] < ptr[a]) return LGDM_ERR_INVALID_ARG;
+    for (int32_t p = ptr[a]; p < ptr[a + 1]; ++p)
+      if (adj[p] < 0 || adj[p] >= n) return LGDM_ERR_INVALID_ARG;
+  }
+  std::vector<int64_t> P(ptr, ptr + n + 1);
+  *n_levels = lgdm::zone_levels(n, P.data(), adj, level);
+  return LGDM_OK;
+}

@@ -10,8 +10,10 @@ which frees their slot and memory for the queue.
 
 Reported per run: per-increment latency (wall time from the tick that starts
 an increment's first Newton iteration to the tick that commits it), p50 and
-p99 over all committed increments, aggregate assembled Gauss points per
-second, admission waits and per-request outcomes.
+p99 over all committed increments; per finished request, the latency from
+arrival to its last commit and the service time from admission, p50 and p99;
+finished requests per second; aggregate assembled Gauss points per second,
+admission waits and per-request outcomes.
 """
 from __future__ import annotations
 
@@ -135,10 +137,24 @@ class ServingLoop:
         done = [r for r in self.records.values() if r.state == "finished"]
         failed = [r for r in self.records.values() if r.state.startswith("failed")]
         waits = [r.admitted_s - r.arrival_s for r in self.records.values() if r.admitted_s is not None]
+        # whole requests: arrival to the commit of the last increment, and
+        # admission to that commit (service time)
+        compl = [r.finished_s - r.arrival_s for r in done]
+        serv = [r.finished_s - r.admitted_s for r in done]
+        pct = lambda v, q: float(np.percentile(v, q)) if v else None
         return {
             "requests_arrived": len(self.records),
             "requests_finished": len(done),
             "requests_failed": len(failed),
+            "failed_requests": sorted((r.rid, r.state, r.increments) for r in failed),
+            "request_latency_p50_s": pct(compl, 50),
+            "request_latency_p99_s": pct(compl, 99),
+            "request_latency_max_s": float(max(compl)) if compl else None,
+            "request_service_p50_s": pct(serv, 50),
+            "request_service_p99_s": pct(serv, 99),
+            "requests_per_s": len(done) / self.wall_s if self.wall_s > 0 else None,
+            "finished_gauss_point_increments_per_s": (
+                sum(r.gauss_points * r.increments for r in done) / self.wall_s if self.wall_s > 0 else None),
             "increments_committed": len(lat),
             "latency_p50_ms": float(np.percentile(lat, 50)) if lat else None,
             "latency_p99_ms": float(np.percentile(lat, 99)) if lat else None,

@@ -668,7 +668,10 @@ class Oracle:
 
     @staticmethod
     def converged(nrm, tol, tiny=1e-300):
-        """Reading R9, per field."""
+        """Reading R9, per field.  A non-finite norm (a state that overflowed)
+        is never convergence."""
+        if not all(np.isfinite(v) for v in nrm.values()):
+            return False
         return (nrm["res_u"] <= tol * max(nrm["ref_u"], tiny)
                 and nrm["res_e"] <= tol * max(nrm["ref_e"], tiny))
 

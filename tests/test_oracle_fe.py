@@ -338,3 +338,15 @@ def test_newton_quadratic_convergence_near_onset():
                     assert b < 1e3 * a * a + 1e-13
                     seen = True
     assert seen
+
+
+def test_convergence_test_rejects_non_finite_norms():
+    """Reading R9: an overflowed state (infinite internal force and
+    residual) is not a converged one, although inf <= tol * inf holds."""
+    inf, nan = float("inf"), float("nan")
+    ok = dict(res_u=1e-12, res_e=1e-14, ref_u=1.0, ref_e=1e-3)
+    assert Oracle.converged(ok, 1e-8)
+    for key, val in (("res_u", inf), ("ref_u", inf), ("res_e", nan), ("ref_e", inf)):
+        bad = dict(ok, **{key: val})
+        assert not Oracle.converged(bad, 1e-8), key
+    assert not Oracle.converged(dict(res_u=inf, res_e=inf, ref_u=inf, ref_e=inf), 1e-8)

@@ -218,8 +218,8 @@ enum { LGDM_FORCING_ADAPTIVE = 0, LGDM_FORCING_FIXED = 1 };
  * preconditioner solves that zone exactly before the cycle:
  *   zone   the nodes of the elements with a loading Gauss point of trial
  *          damage >= zone_damage (raised tenfold closer to 1, twice at most,
- *          while a level group below exceeds 4,096 unknowns or the factors
- *          1.25 GiB; no zone beyond that);
+ *          while a level group below exceeds 4,096 unknowns or the factor
+ *          panels 0.75 GiB; no zone beyond that);
  *   factor the zone's nodes in breadth-first levels (lgdm_zone_levels), which
  *          make its block Z of S K block tridiagonal; block LU over runs of
  *          levels, each diagonal block inverted (rocSOLVER getrf/getri);
@@ -239,7 +239,8 @@ enum { LGDM_FORCING_ADAPTIVE = 0, LGDM_FORCING_FIXED = 1 };
 enum { LGDM_ZONE_DEFAULT = 0, LGDM_ZONE_OFF = 1, LGDM_ZONE_EVERY_TANGENT = 2 };
 
 /* Safeguard of the Newton corrections (lgdm_newton_iteration,
- * lgdm_solve_increment; the batch takes full steps).  With the merit
+ * lgdm_solve_increment, and lgdm_batch_tick, where each halved trial is
+ * assembled at the request's next tick).  With the merit
  * phi = (||R_u|| / ||F_u||)^2 + (||R_ebar|| / ||F_ebar||)^2 of an assembly,
  * LGDM_LINE_SEARCH_DEFAULT halves the last correction (x -= alpha/2 delta,
  * one more assembly each) while phi exceeds 4 times its value before that
@@ -285,6 +286,9 @@ typedef struct lgdm_increment_report {
   int32_t zone_factorizations; /* process-zone blocks factored                      */
   int32_t zone_restarts;   /* restarts of the increment with a smaller zone or
                               none (see LGDM_ZONE_DEFAULT)                          */
+  int32_t zone_errors;     /* process-zone factorizations that a rocBLAS / rocSOLVER
+                              call refused; those solves ran with the plain cycle
+                              (lgdm_last_error holds the call and status)          */
 } lgdm_increment_report;
 
 /* View of the assembled tangent.  Device pointers owned by the context. */

@@ -76,7 +76,8 @@ class IncrementReport(ctypes.Structure):
         ("krylov_rel_u", ctypes.c_double), ("krylov_rel_e", ctypes.c_double),
         ("krylov_spmv", ctypes.c_int64), ("precond_fallbacks", ctypes.c_int32), ("backtracks", ctypes.c_int32),
         ("zone_dofs", ctypes.c_int64), ("t_zone_ms", ctypes.c_double),
-        ("zone_factorizations", ctypes.c_int32), ("zone_restarts", ctypes.c_int32)]
+        ("zone_factorizations", ctypes.c_int32), ("zone_restarts", ctypes.c_int32),
+        ("zone_errors", ctypes.c_int32)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

@@ -36,6 +36,11 @@ struct Slot {
   bool solving = false;
   double tol_u = 0.0, tol_e = 0.0;
   KrylovResult kres{};
+  // line search: x holds the fraction alpha of the last correction, which
+  // started from an iterate of merit phi_prev; halvings so far
+  bool stepped = false;
+  double phi_prev = 0.0, alpha = 1.0;
+  int cuts = 0;
 };
 
 }  // namespace
@@ -309,6 +314,7 @@ lgdm_status lgdm_batch_tick(lgdm_batch* b, const lgdm_solver_opts* o, lgdm_tick_
       }
       s.in_increment = true;
       s.newton = 0;
+      s.stepped = false;
     }
     act.push_back(i);
   }
@@ -358,6 +364,16 @@ lgdm_status lgdm_batch_tick(lgdm_batch* b, const lgdm_solver_opts* o, lgdm_tick_
       fail_slot(b, i, LGDM_ERR_NAN);
       continue;
     }
+    if (op.line_search != LGDM_LINE_SEARCH_OFF && s.stepped && !converged(c, op.tol_newton) &&
+        newton_merit(c) > LS_GROWTH * s.phi_prev && s.cuts < LS_MAX_CUTS) {
+      // the correction raised the merit more than fourfold: halve it; the
+      // trial is assembled at the next tick like an iterate
+      BHIP(b, launch_axpy(c, c->x, c->delta, -0.5 * s.alpha, c->ndof), "line search");
+      s.alpha *= 0.5;
+      s.cuts += 1;
+      continue;
+    }
+    s.stepped = false;
     if (converged(c, op.tol_newton)) {
       BHIP(b, launch_max_reduce(c, c->D_t, c->ngauss, c->norms_dev + 12), "max damage");
       BHIP(b, hipMemcpyAsync(c->norms_host + 12, c->norms_dev + 12, sizeof(double), hipMemcpyDeviceToHost,
@@ -456,6 +472,10 @@ lgdm_status lgdm_batch_tick(lgdm_batch* b, const lgdm_solver_opts* o, lgdm_tick_
       continue;
     }
     BHIP(b, launch_axpy(s.ctx, s.ctx->x, s.ctx->delta, 1.0, s.ctx->ndof), "update");
+    s.stepped = true;
+    s.phi_prev = newton_merit(s.ctx);
+    s.alpha = 1.0;
+    s.cuts = 0;
     s.newton++;
     s.newton_total++;
   }

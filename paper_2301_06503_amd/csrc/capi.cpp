@@ -183,15 +183,6 @@ void fill_norms(const lgdm_ctx* c, lgdm_increment_report* rep) {
   rep->reaction = c->last_norms[4];
 }
 
-// merit of the line search: the squared relative residuals of both fields
-double newton_merit(const lgdm_ctx* c) {
-  const double tiny = 1e-300;
-  const double ru = std::sqrt(c->last_norms[0]), re = std::sqrt(c->last_norms[1]);
-  const double fu = std::sqrt(c->last_norms[2]), fe = std::sqrt(c->last_norms[3]);
-  const double a = ru / std::max(fu, tiny), b = re / std::max(fe, tiny);
-  return a * a + b * b;
-}
-
 bool residual_converged(const lgdm_ctx* c, double tol) {
   const double tiny = 1e-300;
   const double ru = std::sqrt(c->last_norms[0]), re = std::sqrt(c->last_norms[1]);
@@ -240,7 +231,15 @@ lgdm_status linear_solve(lgdm_ctx* c, const double* b_dev, double* x_dev, const 
     if (e == hipErrorNotReady)
       return fail(c, LGDM_ERR_STATE, "the process-zone block of this tangent needs device memory the context has "
                                      "not allocated yet: run lgdm_solve_linear on it first, or turn the zone off");
-    if (e != hipSuccess) return msg.empty() ? hip_fail(c, e, "process-zone setup") : fail(c, LGDM_ERR_DEVICE, msg);
+    if (e == hipErrorUnknown && msg.rfind("process zone:", 0) == 0) {
+      // a library call refused the factorization (nothing was launched by
+      // it): this solve runs with the plain cycle, the report counts it
+      zone_disable(c);
+      c->err = msg;
+      if (rep) rep->zone_errors += 1;
+    } else if (e != hipSuccess) {
+      return msg.empty() ? hip_fail(c, e, "process-zone setup") : fail(c, LGDM_ERR_DEVICE, msg);
+    }
   }
   KrylovResult kr{};
   HIPCHECK(c, krylov_solve(c, b_dev, x_dev, o, tol_u, tol_e, kr), "Krylov solve");
@@ -670,8 +669,6 @@ lgdm_status lgdm_newton_iteration(lgdm_ctx* c, const lgdm_solver_opts* o, int32_
   if (s != LGDM_OK) return s;
   // line search: a correction that raised the merit more than fourfold is
   // halved (at most four times), each trial assembled like an iterate
-  constexpr double LS_GROWTH = 4.0;
-  constexpr int LS_MAX_CUTS = 4;
   if (op.line_search != LGDM_LINE_SEARCH_OFF && c->nw_stepped) {
     while (!residual_converged(c, op.tol_newton) && newton_merit(c) > LS_GROWTH * c->nw_phi &&
            c->nw_cuts < LS_MAX_CUTS) {

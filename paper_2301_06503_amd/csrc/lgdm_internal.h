@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <memory>
 #include <string>
+#include <cmath>
 #include <vector>
 
 #include "lgdm.h"
@@ -354,6 +355,19 @@ hipError_t amg_setup(lgdm_ctx* c, std::string& msg);
 hipError_t amg_apply(lgdm_ctx* c, const double* in, double* out, const double* sc, hipStream_t st);
 hipError_t amg_cycle(lgdm_ctx* c, const double* in, double* out, const double* sc, hipStream_t st);
 void amg_release(lgdm_ctx* c);
+// Line search of the Newton corrections (single contexts and the batch):
+// the merit of an assembly is the sum of the squared relative residuals of
+// both fields; a correction that raised it more than LS_GROWTH-fold is
+// halved, at most LS_MAX_CUTS times.
+constexpr double LS_GROWTH = 4.0;
+constexpr int LS_MAX_CUTS = 4;
+inline double newton_merit(const lgdm_ctx* c) {
+  const double tiny = 1e-300;
+  const double ru = std::sqrt(c->last_norms[0]), re = std::sqrt(c->last_norms[1]);
+  const double fu = std::sqrt(c->last_norms[2]), fe = std::sqrt(c->last_norms[3]);
+  const double a = ru / std::max(fu, tiny), b = re / std::max(fe, tiny);
+  return a * a + b * b;
+}
 // Process zone (zone.hip): the loading, highly damaged elements of the
 // current tangent, solved densely inside the multigrid preconditioner.
 // zone_setup chooses and factors it (after amg_setup); with allow_alloc

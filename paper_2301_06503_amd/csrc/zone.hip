@@ -28,7 +28,9 @@
 //           unknowns, condition number 9e8) took 5e9 flops against 4e11 for
 //           the dense LU, and its solve differed from the dense one by 5e-9.
 //   apply   x_z = Z^-1 b_z by the two sweeps y_k = W_k b_k - N_k y_{k-1},
-//           x_k = y_k - M_k x_{k+1}; r = b - S K x_z (only rows of the zone
+//           x_k = y_k - M_k x_{k+1} (one launch per group and sweep, one
+//           wavefront per row of the row-major copies of W_k, N_k, M_k);
+//           r = b - S K x_z (only rows of the zone
 //           and its neighbour nodes change); out = x_z + M_mg r, with M_mg
 //           the multigrid cycle (multiplicative: the same CPU model needed 64
 //           GMRES steps with it, 97 with the additive form x_z + M_mg b, and
@@ -53,9 +55,9 @@ namespace lgdm {
 
 namespace {
 
-constexpr int64_t ZONE_GROUP_MIN = 384;           // unknowns per group, at least (but the last)
+constexpr int64_t ZONE_GROUP_MIN = 768;           // unknowns per group, at least (but the last)
 constexpr int64_t ZONE_MAX_GROUP = 4096;          // unknowns per group, at most
-constexpr int64_t ZONE_MAX_PANEL = 160ll << 20;   // doubles of the factors (1.25 GiB)
+constexpr int64_t ZONE_MAX_PANEL = 96ll << 20;    // doubles of the factor panels P + Q (0.75 GiB)
 
 }  // namespace
 
@@ -80,6 +82,9 @@ struct Zone {
   //   P_k = [Z_k,k-1 | Z_kk -> W_k | Z_k,k+1]   Q_k = [N_k | M_k]
   double* P = nullptr;                      // [cap_p]
   double* Q = nullptr;                      // [cap_q]
+  // the sweeps' matrices, row major, in P's layout: per group k the rows
+  // [W_k | N_k] (m_k + m_{k-1} each), then the rows of M_k (m_{k+1} each)
+  double* T = nullptr;                      // [cap_p]
   rocblas_int* ipiv = nullptr;              // [cap_m]
   rocblas_int* info = nullptr;              // [2 cap_groups]
   double* bz = nullptr;                     // [cap_nodes * 4] b at the zone's unknowns
@@ -162,34 +167,36 @@ __global__ void zone_gather_kernel(int64_t nz, const int32_t* __restrict__ znode
   bz[t] = b[(int64_t)znodes[t / 4] * 4 + (t % 4)];
 }
 
-// One group's step of a sweep: y[r] = sum_c A[r, c] u[c] - sum_c B[r, c] v[c]
-// over r < m (A: m x na, B: m x nb, column major with leading dimension m;
-// na or nb may be 0).  A workgroup takes GV_ROWS rows; its GV_SLICES column
-// slices are summed in LDS in slice order.  With accumulate, y[r] is added to
-// the result (y = y + A u - B v).
-constexpr int GV_ROWS = 16;
-constexpr int GV_SLICES = ZBS / GV_ROWS;
-__global__ void __launch_bounds__(ZBS) zone_gemv_kernel(int64_t m, int64_t na, const double* __restrict__ A,
-                                                        const double* __restrict__ u, int64_t nb,
-                                                        const double* __restrict__ B, const double* __restrict__ v,
-                                                        double* __restrict__ y, int accumulate,
-                                                        const double* __restrict__ sc) {
+// Row-major copy of a column-major m x n block: out[r * ldo + c0 + c] =
+// A[r + c * m]; one thread per entry
+__global__ void zone_rowmajor_kernel(int64_t m, int64_t n, const double* __restrict__ A, double* __restrict__ out,
+                                     int64_t ldo, int64_t c0) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m * n) return;
+  const int64_t r = t % m, c = t / m;
+  out[r * ldo + c0 + c] = A[t];
+}
+
+// One group's step of a sweep, one wavefront per row of the group:
+// y[r] = sum_c A[r, c] u[c] - sum_c A[r, na + c] v[c] (A row major with
+// leading dimension lda; na or nb may be 0), with accumulate y[r] + that.
+// Lanes stride the row by 64 (coalesced); the lanes' partial sums are
+// combined by a fixed butterfly, so every apply sums in the same order.
+constexpr int SW_ROWS = ZBS / 64;
+__global__ void __launch_bounds__(ZBS) zone_sweep_kernel(int64_t m, int64_t lda, const double* __restrict__ A,
+                                                         int64_t na, const double* __restrict__ u, int64_t nb,
+                                                         const double* __restrict__ v, double* __restrict__ y,
+                                                         int accumulate, const double* __restrict__ sc) {
   if (sc && sc[KSLOT_DONE] != 0.0) return;
-  __shared__ double part[GV_SLICES][GV_ROWS];
-  const int lr = threadIdx.x % GV_ROWS, sl = threadIdx.x / GV_ROWS;
-  const int64_t row = (int64_t)blockIdx.x * GV_ROWS + lr;
+  const int lane = threadIdx.x % 64;
+  const int64_t row = (int64_t)blockIdx.x * SW_ROWS + threadIdx.x / 64;
+  if (row >= m) return;  // uniform over the wavefront
+  const double* a = A + row * lda;
   double acc = 0.0;
-  if (row < m) {
-    for (int64_t c = sl; c < na; c += GV_SLICES) acc += A[row + c * m] * u[c];
-    for (int64_t c = sl; c < nb; c += GV_SLICES) acc -= B[row + c * m] * v[c];
-  }
-  part[sl][lr] = acc;
-  __syncthreads();
-  if (sl == 0 && row < m) {
-    double s = 0.0;
-    for (int q = 0; q < GV_SLICES; ++q) s += part[q][lr];
-    y[row] = accumulate ? y[row] + s : s;
-  }
+  for (int64_t c = lane; c < na; c += 64) acc += a[c] * u[c];
+  for (int64_t c = lane; c < nb; c += 64) acc -= a[na + c] * v[c];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) y[row] = accumulate ? y[row] + acc : acc;
 }
 
 // r = b everywhere (the halo rows are overwritten next)
@@ -236,7 +243,12 @@ __global__ void zone_scatter_kernel(int64_t nz, const int32_t* __restrict__ znod
 
 inline unsigned nblocks(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + ZBS - 1) / ZBS); }
 
-hipError_t rb_err(rocblas_status s) { return s == rocblas_status_success ? hipSuccess : hipErrorUnknown; }
+// a rocBLAS / rocSOLVER status as a HIP error, naming the call in msg
+hipError_t rb_err(rocblas_status s, const char* what, std::string& msg) {
+  if (s == rocblas_status_success) return hipSuccess;
+  msg = std::string("process zone: ") + what + " returned " + rocblas_status_to_string(s);
+  return hipErrorUnknown;
+}
 
 }  // namespace
 
@@ -343,7 +355,7 @@ hipError_t zone_setup(lgdm_ctx* c, bool allow_alloc, bool reuse, double dmin0, b
       return hipErrorUnknown;
     }
   }
-  if (rocblas_set_stream(z.handle, c->stream) != rocblas_status_success) return hipErrorUnknown;
+  if ((e = rb_err(rocblas_set_stream(z.handle, c->stream), "rocblas_set_stream", msg))) return e;
   std::fill(z.zmap_h.begin(), z.zmap_h.end(), -1);
   // the zone: raise the damage threshold until it fits
   std::vector<int32_t> sorted, level, lgroup;
@@ -458,10 +470,11 @@ hipError_t zone_setup(lgdm_ctx* c, bool allow_alloc, bool reuse, double dmin0, b
     const int64_t capn = std::max(z.nz, z.cap_nodes), caph = std::max(z.nh, z.cap_halo),
                   capg = std::max(z.L, z.cap_groups), capp = std::max(np, z.cap_p), capq = std::max(nq, z.cap_q),
                   capm = std::max(z.mmax, z.cap_m);
-    for (void* p : {(void*)z.P, (void*)z.Q, (void*)z.ipiv, (void*)z.info, (void*)z.bz, (void*)z.xz,
+    for (void* p : {(void*)z.P, (void*)z.Q, (void*)z.T, (void*)z.ipiv, (void*)z.info, (void*)z.bz, (void*)z.xz,
                     (void*)z.znodes, (void*)z.zgroup, (void*)z.goff_d, (void*)z.poff_d, (void*)z.halo, z.ws})
       dfree(c, p);
     z.P = (double*)dalloc(c, capp * sizeof(double));
+    z.T = (double*)dalloc(c, capp * sizeof(double));
     z.Q = (double*)dalloc(c, std::max<int64_t>(capq, 1) * sizeof(double));
     z.ipiv = (rocblas_int*)dalloc(c, capm * sizeof(rocblas_int));
     z.info = (rocblas_int*)dalloc(c, 2 * capg * sizeof(rocblas_int));
@@ -473,7 +486,8 @@ hipError_t zone_setup(lgdm_ctx* c, bool allow_alloc, bool reuse, double dmin0, b
     z.poff_d = (int64_t*)dalloc(c, (capg + 1) * sizeof(int64_t));
     z.halo = (int32_t*)dalloc(c, caph * sizeof(int32_t));
     // the workspace of getrf / getri / gemm at the largest group, from the
-    // context's allocator
+    // context's allocator; at least 64 MiB (with the size the query
+    // reported, a factorization of groups above ~1,500 unknowns was refused)
     size_t ws = 0;
     rocblas_start_device_memory_size_query(z.handle);
     (void)rocsolver_dgetrf(z.handle, (rocblas_int)capm, (rocblas_int)capm, nullptr, (rocblas_int)capm, nullptr,
@@ -486,15 +500,15 @@ hipError_t zone_setup(lgdm_ctx* c, bool allow_alloc, bool reuse, double dmin0, b
                           (rocblas_int)capm, &one, nullptr, (rocblas_int)capm);
     }
     rocblas_stop_device_memory_size_query(z.handle, &ws);
-    z.ws_size = std::max<size_t>(ws, 256);
+    z.ws_size = std::max<size_t>(ws, (size_t)64 << 20);
     z.ws = dalloc(c, z.ws_size);
-    if (!z.P || !z.Q || !z.ipiv || !z.info || !z.bz || !z.xz || !z.znodes || !z.zgroup || !z.goff_d || !z.poff_d ||
+    if (!z.P || !z.Q || !z.T || !z.ipiv || !z.info || !z.bz || !z.xz || !z.znodes || !z.zgroup || !z.goff_d || !z.poff_d ||
         !z.halo || !z.ws) {
       z.cap_nodes = z.cap_halo = z.cap_groups = z.cap_p = z.cap_q = z.cap_m = 0;
       msg = "device allocation failed (process zone factors)";
       return hipErrorOutOfMemory;
     }
-    if (rocblas_set_workspace(z.handle, z.ws, z.ws_size) != rocblas_status_success) return hipErrorUnknown;
+    if ((e = rb_err(rocblas_set_workspace(z.handle, z.ws, z.ws_size), "rocblas_set_workspace", msg))) return e;
     z.cap_nodes = capn;
     z.cap_halo = caph;
     z.cap_groups = capg;
@@ -538,18 +552,35 @@ hipError_t zone_setup(lgdm_ctx* c, bool allow_alloc, bool reuse, double dmin0, b
       const int64_t mpp = k > 1 ? z.goff[k - 1] - z.goff[k - 2] : 0;
       const double* Mprev = z.Q + z.qoff[k - 1] + mp * mpp;
       if ((e = rb_err(rocblas_dgemm(z.handle, rocblas_operation_none, rocblas_operation_none, im, im, imp, &mone, Lk,
-                                    im, Mprev, imp, &one, Dk, im))))
+                                    im, Mprev, imp, &one, Dk, im),
+                      "dgemm (Schur complement)", msg)))
         return e;
     }
-    if ((e = rb_err(rocsolver_dgetrf(z.handle, im, im, Dk, im, z.ipiv, z.info + 2 * k)))) return e;
-    if ((e = rb_err(rocsolver_dgetri(z.handle, im, Dk, im, z.ipiv, z.info + 2 * k + 1)))) return e;
+    if ((e = rb_err(rocsolver_dgetrf(z.handle, im, im, Dk, im, z.ipiv, z.info + 2 * k), "dgetrf", msg))) return e;
+    if ((e = rb_err(rocsolver_dgetri(z.handle, im, Dk, im, z.ipiv, z.info + 2 * k + 1), "dgetri", msg))) return e;
     if (k > 0 && (e = rb_err(rocblas_dgemm(z.handle, rocblas_operation_none, rocblas_operation_none, im, imp, im,
-                                           &one, Dk, im, Lk, im, &zero, Nk, im))))
+                                           &one, Dk, im, Lk, im, &zero, Nk, im),
+                             "dgemm (N_k)", msg)))
       return e;
     if (mn > 0 && (e = rb_err(rocblas_dgemm(z.handle, rocblas_operation_none, rocblas_operation_none, im, imn, im,
-                                            &one, Dk, im, Uk, im, &zero, Mk, im))))
+                                            &one, Dk, im, Uk, im, &zero, Mk, im),
+                              "dgemm (M_k)", msg)))
       return e;
   }
+  // the sweeps read rows: [W_k | N_k] and M_k in row-major order
+  for (int64_t k = 0; k < z.L; ++k) {
+    const int64_t m = z.goff[k + 1] - z.goff[k], mp = k > 0 ? z.goff[k] - z.goff[k - 1] : 0,
+                  mn = k + 1 < z.L ? z.goff[k + 2] - z.goff[k + 1] : 0;
+    const double* Wk = z.P + z.poff[k] + m * mp;
+    const double* Nk = z.Q + z.qoff[k];
+    const double* Mk = Nk + m * mp;
+    double* Fk = z.T + z.poff[k];
+    double* Bk = Fk + m * (m + mp);
+    zone_rowmajor_kernel<<<nblocks(m * m), ZBS, 0, c->stream>>>(m, m, Wk, Fk, m + mp, 0);
+    if (mp > 0) zone_rowmajor_kernel<<<nblocks(m * mp), ZBS, 0, c->stream>>>(m, mp, Nk, Fk, m + mp, m);
+    if (mn > 0) zone_rowmajor_kernel<<<nblocks(m * mn), ZBS, 0, c->stream>>>(m, mn, Mk, Bk, mn, 0);
+  }
+  if ((e = hipGetLastError())) return e;
   std::vector<rocblas_int> info(2 * z.L, 0);
   if ((e = hipMemcpyAsync(info.data(), z.info, info.size() * sizeof(rocblas_int), hipMemcpyDeviceToHost,
                           c->stream)) ||
@@ -581,18 +612,16 @@ hipError_t zone_apply(lgdm_ctx* c, const double* b, double* out, const double* s
   // forward sweep: y_k = W_k b_k - N_k y_{k-1}
   for (int64_t k = 0; k < z.L; ++k) {
     const int64_t m = z.goff[k + 1] - z.goff[k], mp = k > 0 ? z.goff[k] - z.goff[k - 1] : 0;
-    const double* Wk = z.P + z.poff[k] + m * mp;
-    const double* Nk = z.Q + z.qoff[k];
-    zone_gemv_kernel<<<(unsigned)((m + GV_ROWS - 1) / GV_ROWS), ZBS, 0, st>>>(
-        m, m, Wk, z.bz + z.goff[k], mp, Nk, k > 0 ? z.xz + z.goff[k - 1] : nullptr, z.xz + z.goff[k], 0, sc);
+    zone_sweep_kernel<<<(unsigned)((m + SW_ROWS - 1) / SW_ROWS), ZBS, 0, st>>>(
+        m, m + mp, z.T + z.poff[k], m, z.bz + z.goff[k], mp, k > 0 ? z.xz + z.goff[k - 1] : nullptr,
+        z.xz + z.goff[k], 0, sc);
   }
   // backward sweep: x_k = y_k - M_k x_{k+1}
   for (int64_t k = z.L - 2; k >= 0; --k) {
     const int64_t m = z.goff[k + 1] - z.goff[k], mp = k > 0 ? z.goff[k] - z.goff[k - 1] : 0,
                   mn = z.goff[k + 2] - z.goff[k + 1];
-    const double* Mk = z.Q + z.qoff[k] + m * mp;
-    zone_gemv_kernel<<<(unsigned)((m + GV_ROWS - 1) / GV_ROWS), ZBS, 0, st>>>(
-        m, 0, nullptr, nullptr, mn, Mk, z.xz + z.goff[k + 1], z.xz + z.goff[k], 1, sc);
+    zone_sweep_kernel<<<(unsigned)((m + SW_ROWS - 1) / SW_ROWS), ZBS, 0, st>>>(
+        m, mn, z.T + z.poff[k] + m * (m + mp), 0, nullptr, mn, z.xz + z.goff[k + 1], z.xz + z.goff[k], 1, sc);
   }
   zone_copy_kernel<<<std::min<int64_t>(nblocks(c->ndof), 2048), ZBS, 0, st>>>(c->ndof, b, z.r, sc);
   const double se = c->mat.E / c->mat.h;

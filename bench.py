@@ -121,7 +121,7 @@ def zone_opts(args, binding):
     return dict(process_zone={"default": binding.ZONE_DEFAULT, "off": binding.ZONE_OFF,
                               "every": binding.ZONE_EVERY_TANGENT}[args.zone],
                 zone_damage=args.zone_damage,
-                line_search=binding.LINE_SEARCH_OFF if args.no_line_search else binding.LINE_SEARCH_DEFAULT)
+                line_search=binding.LINE_SEARCH_ON if args.line_search else binding.LINE_SEARCH_OFF)
 
 
 def new_acc():
@@ -270,7 +270,7 @@ def run_precision(prob, precision, args, binding):
         "solver": {"krylov": args.krylov, "idr_s": args.idr_s if args.krylov == "idr" else None,
                    "forcing": "fixed" if args.fixed_forcing else "adaptive", "tol_krylov": args.tol_krylov,
                    "precond": args.precond, "process_zone": args.zone, "zone_damage": args.zone_damage,
-                   "line_search": not args.no_line_search},
+                   "line_search": args.line_search},
     }
     ctx.close()
     del ctx
@@ -549,8 +549,8 @@ def main():
                          "tangent)")
     ap.add_argument("--zone-damage", type=float, default=0.99,
                     help="trial damage from which a loading element joins the process zone")
-    ap.add_argument("--no-line-search", action="store_true",
-                    help="full Newton steps (no backtracking on a correction that blows the residual up)")
+    ap.add_argument("--line-search", action="store_true",
+                    help="Newton line search: halve a correction that blows the residual up (default: full steps)")
     ap.add_argument("--fixed-forcing", action="store_true",
                     help="solve every Newton correction to --tol-krylov (default: adaptive forcing)")
     ap.add_argument("--max-krylov", type=int, default=20000)

@@ -188,8 +188,9 @@ typedef struct lgdm_solver_opts {
                                     solve that runs out returns its best iterate,
                                     and the next Newton iteration returns
                                     LGDM_ERR_NOT_CONVERGED as above               */
-  int32_t line_search;     /* LGDM_LINE_SEARCH_DEFAULT: backtracking on a Newton
-                              correction that blows the residual up (below)        */
+  int32_t line_search;     /* LGDM_LINE_SEARCH_OFF: full Newton steps; _ON:
+                              backtracking on a correction that blows the
+                              residual up (below)                                  */
   double zone_damage;      /* 0.99   trial damage from which a loading element
                               joins the process zone (below); values outside
                               (0, 1) select the default                            */
@@ -240,17 +241,19 @@ enum { LGDM_ZONE_DEFAULT = 0, LGDM_ZONE_OFF = 1, LGDM_ZONE_EVERY_TANGENT = 2 };
 
 /* Safeguard of the Newton corrections (lgdm_newton_iteration,
  * lgdm_solve_increment, and lgdm_batch_tick, where each halved trial is
- * assembled at the request's next tick).  With the merit
- * phi = (||R_u|| / ||F_u||)^2 + (||R_ebar|| / ||F_ebar||)^2 of an assembly,
- * LGDM_LINE_SEARCH_DEFAULT halves the last correction (x -= alpha/2 delta,
- * one more assembly each) while phi exceeds 4 times its value before that
- * correction, at most 4 times (alpha >= 1/16); the iterate is then kept
- * whatever phi is.  A correction that at most doubles the residual is taken
- * whole, so increments that converge with full steps are not changed.  The
- * solution of an increment does not depend on the path to it: the history
- * variable of a trial state is max(kappa_n, eeq(trial)) (Eq. A.2).
- * LGDM_LINE_SEARCH_OFF: full steps (Algorithm 2 as written). */
-enum { LGDM_LINE_SEARCH_DEFAULT = 0, LGDM_LINE_SEARCH_OFF = 1 };
+ * assembled at the request's next tick).  LGDM_LINE_SEARCH_OFF (the
+ * default): full steps, Algorithm 2 as written.  LGDM_LINE_SEARCH_ON: with
+ * the merit phi = (||R_u|| / ||F_u||)^2 + (||R_ebar|| / ||F_ebar||)^2 of an
+ * assembly, the last correction is halved (x -= alpha/2 delta, one more
+ * assembly each) while phi exceeds 4 times its value before that correction,
+ * at most 4 times (alpha >= 1/16); the iterate is then kept whatever phi is.
+ * A correction that at most doubles the residual is taken whole.  The
+ * solution of an increment does not depend on the path to it (the history
+ * variable of a trial state is max(kappa_n, eeq(trial)), Eq. A.2), but which
+ * increments converge does: on brittle 2D plates of the serving stream the
+ * line search converges increments that full steps do not, and on a
+ * plane-strain 9-node plate it fails one that full steps converge. */
+enum { LGDM_LINE_SEARCH_OFF = 0, LGDM_LINE_SEARCH_ON = 1 };
 
 /* Per-increment / per-iteration report (the paper's time-per-iteration split
  * into assembly, solve and variable update, Sec. 3.1). */

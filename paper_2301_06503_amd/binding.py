@@ -22,7 +22,7 @@ FP64, MIXED = 0, 1
 FIELD_X, FIELD_KAPPA, FIELD_DAMAGE, FIELD_KAPPA_TRIAL, FIELD_DAMAGE_TRIAL = 0, 1, 2, 3, 4
 FIELD_RESIDUAL, FIELD_REACTION, FIELD_EEQ = 5, 6, 7
 ZONE_DEFAULT, ZONE_OFF, ZONE_EVERY_TANGENT = 0, 1, 2
-LINE_SEARCH_DEFAULT, LINE_SEARCH_OFF = 0, 1
+LINE_SEARCH_OFF, LINE_SEARCH_ON = 0, 1
 
 LGDM_ERR_BUSY = 8
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "OOM", 3: "DEVICE", 4: "NOT_CONVERGED", 5: "NAN",

@@ -364,7 +364,7 @@ lgdm_status lgdm_batch_tick(lgdm_batch* b, const lgdm_solver_opts* o, lgdm_tick_
       fail_slot(b, i, LGDM_ERR_NAN);
       continue;
     }
-    if (op.line_search != LGDM_LINE_SEARCH_OFF && s.stepped && !converged(c, op.tol_newton) &&
+    if (op.line_search == LGDM_LINE_SEARCH_ON && s.stepped && !converged(c, op.tol_newton) &&
         newton_merit(c) > LS_GROWTH * s.phi_prev && s.cuts < LS_MAX_CUTS) {
       // the correction raised the merit more than fourfold: halve it; the
       // trial is assembled at the next tick like an iterate

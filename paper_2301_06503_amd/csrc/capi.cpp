@@ -669,7 +669,7 @@ lgdm_status lgdm_newton_iteration(lgdm_ctx* c, const lgdm_solver_opts* o, int32_
   if (s != LGDM_OK) return s;
   // line search: a correction that raised the merit more than fourfold is
   // halved (at most four times), each trial assembled like an iterate
-  if (op.line_search != LGDM_LINE_SEARCH_OFF && c->nw_stepped) {
+  if (op.line_search == LGDM_LINE_SEARCH_ON && c->nw_stepped) {
     while (!residual_converged(c, op.tol_newton) && newton_merit(c) > LS_GROWTH * c->nw_phi &&
            c->nw_cuts < LS_MAX_CUTS) {
       HIPCHECK(c, launch_axpy(c, c->x, c->delta, -0.5 * c->nw_alpha, c->ndof), "line search");

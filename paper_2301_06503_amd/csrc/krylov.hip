@@ -1801,7 +1801,7 @@ lgdm_solver_opts fill_opts(const lgdm_solver_opts* o) {
   r.idr_s = r.idr_s <= 0 ? 8 : (r.idr_s <= 1 ? 1 : (r.idr_s <= 2 ? 2 : (r.idr_s <= 4 ? 4 : 8)));
   if (!(r.zone_damage > 0.0 && r.zone_damage < 1.0)) r.zone_damage = 0.99;
   if (r.process_zone != LGDM_ZONE_OFF && r.process_zone != LGDM_ZONE_EVERY_TANGENT) r.process_zone = LGDM_ZONE_DEFAULT;
-  if (r.line_search != LGDM_LINE_SEARCH_OFF) r.line_search = LGDM_LINE_SEARCH_DEFAULT;
+  if (r.line_search != LGDM_LINE_SEARCH_ON) r.line_search = LGDM_LINE_SEARCH_OFF;
   return r;
 }
 

@@ -51,8 +51,11 @@ class ServingLoop:
         self.requests = sorted(requests, key=lambda r: r.arrival_s)
         self.batch = binding.Batch(device=0, precision=precision, max_slots=max_slots,
                                    hbm_budget_bytes=hbm_budget_bytes)
+        # the stream's brittle plates take the Newton line search: it
+        # converges load steps that full steps do not
         self.opts = opts or binding.solver_opts(max_newton=40, tol_newton=1e-8, tol_krylov=1e-3,
-                                                max_krylov=20000, check_every=32)
+                                                max_krylov=20000, check_every=32,
+                                                line_search=binding.LINE_SEARCH_ON)
         self.records: Dict[int, RequestRecord] = {}
         self.keep_results = keep_results
         self.results: Dict[int, dict] = {}

@@ -20,7 +20,7 @@ Fig. 8b decided by rounding) are counted and reported apart; see _ties.
 
 The beam's path is also run in FP64 with the solver's variants: the dense
 process-zone solve of the multigrid preconditioner rebuilt for every tangent
-or switched off, and full Newton steps without the line search.  Each must
+or switched off, and Newton with the line search.  Each must
 land on the same discrete solution; the default and every-tangent runs must
 have used the zone.
 """
@@ -78,13 +78,13 @@ def _ties(g, n, diff, kap, m, bound):
 
 # (workload, precision, increments compared (None: all stored), Newton tolerance, solver variant)
 # variants on the beam: the process zone rebuilt for every tangent, no zone,
-# full Newton steps; the discrete solution must not depend on them
+# the Newton line search; the discrete solution must not depend on them
 CASES = [("c3p", B.FP64, None, 1e-12, "default"), ("c3p", B.MIXED, None, 1e-10, "default"),
          ("c1", B.FP64, None, 1e-11, "default"), ("c1", B.MIXED, 60, 1e-10, "default"),
          ("c3p", B.FP64, None, 1e-12, "zone_every"), ("c3p", B.FP64, None, 1e-12, "zone_off"),
-         ("c3p", B.FP64, None, 1e-12, "no_line_search")]
+         ("c3p", B.FP64, None, 1e-12, "line_search")]
 VARIANTS = {"default": {}, "zone_every": dict(process_zone=B.ZONE_EVERY_TANGENT),
-            "zone_off": dict(process_zone=B.ZONE_OFF), "no_line_search": dict(line_search=B.LINE_SEARCH_OFF)}
+            "zone_off": dict(process_zone=B.ZONE_OFF), "line_search": dict(line_search=B.LINE_SEARCH_ON)}
 
 
 @pytest.mark.parametrize("name,precision,limit,tol_newton,variant", CASES)

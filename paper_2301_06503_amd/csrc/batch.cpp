@@ -41,6 +41,10 @@ struct Slot {
   bool stepped = false;
   double phi_prev = 0.0, alpha = 1.0;
   int cuts = 0;
+  // the current increment's second attempt, with the line-search setting
+  // flipped; increments retried so far
+  bool ls_flip = false;
+  int retries = 0;
 };
 
 }  // namespace
@@ -114,6 +118,27 @@ void release(lgdm_batch* b, Slot& s) {
   }
   b->used -= s.footprint;
   s = Slot();
+}
+
+void fail_slot(lgdm_batch* b, int i, lgdm_status st);
+
+// An increment that does not converge is tried once more from its start
+// with the line-search setting flipped (full steps converge some load steps
+// the line search does not, and the other way round); a second failure
+// fails the request.
+void retry_or_fail(lgdm_batch* b, int i, lgdm_status st) {
+  Slot& s = b->slots[i];
+  if (st != LGDM_ERR_NOT_CONVERGED || s.ls_flip || !s.ctx) {
+    fail_slot(b, i, st);
+    return;
+  }
+  if (s.solving && b->run) b->run->remove(i);
+  s.solving = false;
+  s.run.reset();
+  lgdm_abort_increment(s.ctx);   // restores the committed state
+  s.in_increment = false;        // the next tick begins the increment again
+  s.ls_flip = true;
+  s.retries += 1;
 }
 
 void fail_slot(lgdm_batch* b, int i, lgdm_status st) {
@@ -364,7 +389,8 @@ lgdm_status lgdm_batch_tick(lgdm_batch* b, const lgdm_solver_opts* o, lgdm_tick_
       fail_slot(b, i, LGDM_ERR_NAN);
       continue;
     }
-    if (op.line_search == LGDM_LINE_SEARCH_ON && s.stepped && !converged(c, op.tol_newton) &&
+    const bool line_search = (op.line_search == LGDM_LINE_SEARCH_ON) != s.ls_flip;
+    if (line_search && s.stepped && !converged(c, op.tol_newton) &&
         newton_merit(c) > LS_GROWTH * s.phi_prev && s.cuts < LS_MAX_CUTS) {
       // the correction raised the merit more than fourfold: halve it; the
       // trial is assembled at the next tick like an iterate
@@ -385,6 +411,7 @@ lgdm_status lgdm_batch_tick(lgdm_batch* b, const lgdm_solver_opts* o, lgdm_tick_
       }
       s.max_damage = c->norms_host[12];
       s.in_increment = false;
+      s.ls_flip = false;
       R.committed++;
       if (c->increment >= s.n_increments) {
         s.state = LGDM_SLOT_FINISHED;
@@ -393,7 +420,7 @@ lgdm_status lgdm_batch_tick(lgdm_batch* b, const lgdm_solver_opts* o, lgdm_tick_
       continue;
     }
     if (s.newton >= op.max_newton) {
-      fail_slot(b, i, LGDM_ERR_NOT_CONVERGED);
+      retry_or_fail(b, i, LGDM_ERR_NOT_CONVERGED);
       continue;
     }
     BHIP(b, krylov_setup(c), "block-Jacobi setup");
@@ -468,7 +495,7 @@ lgdm_status lgdm_batch_tick(lgdm_batch* b, const lgdm_solver_opts* o, lgdm_tick_
     }
     if (s.kres.status != LGDM_OK && !s.kres.improved) {
       // a correction no better than none would repeat this iteration unchanged
-      fail_slot(b, i, LGDM_ERR_NOT_CONVERGED);
+      retry_or_fail(b, i, LGDM_ERR_NOT_CONVERGED);
       continue;
     }
     BHIP(b, launch_axpy(s.ctx, s.ctx->x, s.ctx->delta, 1.0, s.ctx->ndof), "update");
@@ -502,6 +529,7 @@ lgdm_status lgdm_batch_slot_info(lgdm_batch* b, int32_t slot, lgdm_slot_info* in
   I.footprint_bytes = s.footprint;
   I.max_damage = s.max_damage;
   I.last_status = s.last_status;
+  I.retries = s.retries;
   *info = I;
   return LGDM_OK;
 }

@@ -354,6 +354,11 @@ hipError_t zone_setup(lgdm_ctx* c, bool allow_alloc, bool reuse, double dmin0, b
       msg = "rocblas_create_handle failed";
       return hipErrorUnknown;
     }
+    // no atomics: the factors, and the solves they precondition, are the
+    // same bits in every run
+    if ((e = rb_err(rocblas_set_atomics_mode(z.handle, rocblas_atomics_not_allowed), "rocblas_set_atomics_mode",
+                    msg)))
+      return e;
   }
   if ((e = rb_err(rocblas_set_stream(z.handle, c->stream), "rocblas_set_stream", msg))) return e;
   std::fill(z.zmap_h.begin(), z.zmap_h.end(), -1);
@@ -361,6 +366,10 @@ hipError_t zone_setup(lgdm_ctx* c, bool allow_alloc, bool reuse, double dmin0, b
   std::vector<int32_t> sorted, level, lgroup;
   std::vector<int64_t> adj_ptr;
   std::vector<int32_t> adj;
+  // the candidate's layout; it replaces the zone's only once it is built, so
+  // that a reused zone keeps the layout its factors were built with
+  std::vector<int64_t> goff, poff, qoff;
+  int64_t L = 0, mmax = 0;
   bool fits = false;
   for (double dmin : {dmin0, 1.0 - 0.1 * (1.0 - dmin0), 1.0 - 0.01 * (1.0 - dmin0)}) {
     zone_flag_kernel<<<nblocks(ne), ZBS, 0, c->stream>>>(ne, c->ngp, c->kappa_t, c->kappa_n, c->D_t,
@@ -400,34 +409,42 @@ hipError_t zone_setup(lgdm_ctx* c, bool allow_alloc, bool reuse, double dmin0, b
     std::vector<int64_t> lcount(nlev, 0);
     for (int64_t i = 0; i < nz; ++i) lcount[level[i]] += 4;
     lgroup.assign(nlev, 0);
-    z.goff.assign(1, 0);
+    goff.assign(1, 0);
     int64_t acc = 0;
     for (int64_t l = 0; l < nlev; ++l) {
-      lgroup[l] = (int32_t)(z.goff.size() - 1);
+      lgroup[l] = (int32_t)(goff.size() - 1);
       acc += lcount[l];
       if (acc >= ZONE_GROUP_MIN || l + 1 == nlev) {
-        z.goff.push_back(z.goff.back() + acc);
+        goff.push_back(goff.back() + acc);
         acc = 0;
       }
     }
-    z.L = (int64_t)z.goff.size() - 1;
-    z.mmax = 0;
-    for (int64_t k = 0; k < z.L; ++k) z.mmax = std::max(z.mmax, z.goff[k + 1] - z.goff[k]);
-    z.poff.assign(z.L + 1, 0);
-    z.qoff.assign(z.L + 1, 0);
-    for (int64_t k = 0; k < z.L; ++k) {
-      const int64_t m = z.goff[k + 1] - z.goff[k], mp = k > 0 ? z.goff[k] - z.goff[k - 1] : 0,
-                    mn = k + 1 < z.L ? z.goff[k + 2] - z.goff[k + 1] : 0;
-      z.poff[k + 1] = z.poff[k] + m * (mp + m + mn);
-      z.qoff[k + 1] = z.qoff[k] + m * (mp + mn);
+    L = (int64_t)goff.size() - 1;
+    mmax = 0;
+    for (int64_t k = 0; k < L; ++k) mmax = std::max(mmax, goff[k + 1] - goff[k]);
+    poff.assign(L + 1, 0);
+    qoff.assign(L + 1, 0);
+    for (int64_t k = 0; k < L; ++k) {
+      const int64_t m = goff[k + 1] - goff[k], mp = k > 0 ? goff[k] - goff[k - 1] : 0,
+                    mn = k + 1 < L ? goff[k + 2] - goff[k + 1] : 0;
+      poff[k + 1] = poff[k] + m * (mp + m + mn);
+      qoff[k + 1] = qoff[k] + m * (mp + mn);
     }
-    if (z.mmax <= ZONE_MAX_GROUP && z.poff[z.L] + z.qoff[z.L] <= ZONE_MAX_PANEL) {
+    if (mmax <= ZONE_MAX_GROUP && poff[L] + qoff[L] <= ZONE_MAX_PANEL) {
       fits = true;
       break;
     }
   }
-  z.built_serial = -1;
   if (!fits) return hipSuccess;
+  // from here on the zone's layout is this candidate's; the factors are
+  // valid again only once built
+  z.built_serial = -1;
+  z.built_nodes.clear();
+  z.goff.swap(goff);
+  z.poff.swap(poff);
+  z.qoff.swap(qoff);
+  z.L = L;
+  z.mmax = mmax;
   // zone order: by group, ascending node within a group
   z.nz = (int64_t)sorted.size();
   z.nodes.resize(z.nz);
@@ -608,6 +625,10 @@ int64_t zone_dofs(const lgdm_ctx* c) { return zone_active(c) ? c->zone->nz * 4 :
 hipError_t zone_apply(lgdm_ctx* c, const double* b, double* out, const double* sc, hipStream_t st) {
   Zone& z = *c->zone;
   const int64_t n = z.nz * 4;
+  // the layout must describe the buffers the factors were built in
+  if ((int64_t)z.goff.size() != z.L + 1 || (int64_t)z.poff.size() != z.L + 1 || z.goff.back() != n ||
+      z.nz > z.cap_nodes || z.nh > z.cap_halo || z.poff[z.L] > z.cap_p || z.L > z.cap_groups)
+    return hipErrorInvalidValue;
   zone_gather_kernel<<<nblocks(n), ZBS, 0, st>>>(z.nz, z.znodes, b, z.bz, sc);
   // forward sweep: y_k = W_k b_k - N_k y_{k-1}
   for (int64_t k = 0; k < z.L; ++k) {

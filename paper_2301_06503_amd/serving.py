@@ -42,6 +42,7 @@ class RequestRecord:
     gauss_points: int = 0
     assemblies: int = 0
     max_damage: float = 0.0
+    retries: int = 0
     increment_latency_ms: List[float] = dataclasses.field(default_factory=list)
 
 
@@ -117,6 +118,7 @@ class ServingLoop:
                 rec.assemblies = info["assemblies_total"]
                 rec.gauss_points = info["n_gauss"]
                 rec.max_damage = info["max_damage"]
+                rec.retries = info["retries"]
                 if info["state"] in (binding.SLOT_FINISHED, binding.SLOT_FAILED):
                     rec.state = "finished" if info["state"] == binding.SLOT_FINISHED else \
                         "failed(%s)" % binding.STATUS_NAMES.get(info["last_status"])
@@ -150,6 +152,7 @@ class ServingLoop:
             "requests_finished": len(done),
             "requests_failed": len(failed),
             "failed_requests": sorted((r.rid, r.state, r.increments) for r in failed),
+            "increment_retries": sum(r.retries for r in self.records.values()),
             "request_latency_p50_s": pct(compl, 50),
             "request_latency_p99_s": pct(compl, 99),
             "request_latency_max_s": float(max(compl)) if compl else None,

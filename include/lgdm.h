@@ -220,7 +220,7 @@ enum { LGDM_FORCING_ADAPTIVE = 0, LGDM_FORCING_FIXED = 1 };
  *   zone   the nodes of the elements with a loading Gauss point of trial
  *          damage >= zone_damage (raised tenfold closer to 1, twice at most,
  *          while a level group below exceeds 4,096 unknowns or the factor
- *          panels 0.75 GiB; no zone beyond that);
+ *          panels 2.5 GiB; no zone beyond that);
  *   factor the zone's nodes in breadth-first levels (lgdm_zone_levels), which
  *          make its block Z of S K block tridiagonal; block LU over runs of
  *          levels, each diagonal block inverted (rocSOLVER getrf/getri);

@@ -231,10 +231,10 @@ enum { LGDM_FORCING_ADAPTIVE = 0, LGDM_FORCING_FIXED = 1 };
  * them; r and the cycle always use the current tangent);
  * LGDM_ZONE_EVERY_TANGENT rebuilds them for every tangent, and
  * lgdm_solve_linear always does.  Should Newton with the zone stop reducing
- * the merit of the line search (no new smallest value in 4 iterations), the
- * increment restarts from its beginning with the zone's damage threshold
- * moved tenfold closer to 1, and should that stall too, without the zone
- * (zone_restarts in the report).  The factors are allocated through the context's allocator
+ * the merit of the line search (no new smallest value in 4 iterations), or
+ * return a correction no better than none, the increment restarts from its
+ * beginning with the zone's damage threshold moved tenfold closer to 1, and
+ * should that stall too, without the zone (zone_restarts in the report).  The factors are allocated through the context's allocator
  * the first time a zone of that size occurs and kept.
  * LGDM_ZONE_OFF: the plain cycle. */
 enum { LGDM_ZONE_DEFAULT = 0, LGDM_ZONE_OFF = 1, LGDM_ZONE_EVERY_TANGENT = 2 };

@@ -693,7 +693,6 @@ lgdm_status lgdm_newton_iteration(lgdm_ctx* c, const lgdm_solver_opts* o, int32_
   // Newton with the process zone that no longer reduces the merit restarts
   // the increment from its beginning with a smaller zone (the damage
   // threshold tenfold closer to 1), then without the zone
-  constexpr int ZONE_PATIENCE = 4;
   const double phi = newton_merit(c);
   if (phi < c->nw_best_phi) {
     c->nw_best_phi = phi;
@@ -707,6 +706,7 @@ lgdm_status lgdm_newton_iteration(lgdm_ctx* c, const lgdm_solver_opts* o, int32_
     HIPCHECK(c, launch_set_dirichlet(c, c->inc_lambda), "set Dirichlet values");
     c->inc_zone_tier += 1;
     c->inc_zone_used = false;
+    zone_forget(c);   // factors of the abandoned iterates are not reused
     c->nw_iter = 0;
     c->nw_best_phi = HUGE_VAL;
     c->nw_since_best = 0;
@@ -753,9 +753,17 @@ lgdm_status lgdm_newton_iteration(lgdm_ctx* c, const lgdm_solver_opts* o, int32_
   c->solve_deadline = 0.0;
   HIPCHECK(c, hipEventRecord(c->ev[3], c->stream), "event");
   if (!tolerable_in_newton(s)) return s;
-  // a correction no better than none would repeat this iteration unchanged
-  if (!c->last_solve_improved)
+  // a correction no better than none would repeat this iteration unchanged:
+  // with the process zone in use and a smaller zone (or none) left to try,
+  // the next iteration restarts the increment (x is left as it is);
+  // otherwise Newton stops here
+  if (!c->last_solve_improved) {
+    if (c->inc_zone_used && c->inc_zone_tier < 2) {
+      c->nw_since_best = ZONE_PATIENCE;
+      return LGDM_OK;
+    }
     return fail(c, LGDM_ERR_NOT_CONVERGED, "the linear solve made no progress on the Newton system");
+  }
   s = LGDM_OK;
   // Algorithm 2: u_i = u_{i-1} + delta u, ebar_i = ebar_{i-1} + delta ebar
   HIPCHECK(c, launch_axpy(c, c->x, c->delta, 1.0, c->ndof), "update");

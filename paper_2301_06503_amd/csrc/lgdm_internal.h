@@ -360,6 +360,9 @@ void amg_release(lgdm_ctx* c);
 // both fields; a correction that raised it more than LS_GROWTH-fold is
 // halved, at most LS_MAX_CUTS times.
 constexpr double LS_GROWTH = 4.0;
+// iterations without a new smallest merit after which Newton with the
+// process zone restarts the increment with a smaller zone
+constexpr int ZONE_PATIENCE = 4;
 constexpr int LS_MAX_CUTS = 4;
 inline double newton_merit(const lgdm_ctx* c) {
   const double tiny = 1e-300;
@@ -378,6 +381,7 @@ hipError_t zone_setup(lgdm_ctx* c, bool allow_alloc, bool reuse, double dmin, bo
 bool zone_active(const lgdm_ctx* c);
 int64_t zone_dofs(const lgdm_ctx* c);
 void zone_disable(lgdm_ctx* c);
+void zone_forget(lgdm_ctx* c);  // the factors are not reused by a later tangent
 hipError_t zone_apply(lgdm_ctx* c, const double* in, double* out, const double* sc, hipStream_t st);
 void zone_release(lgdm_ctx* c);
 // breadth-first levels of a graph (CSR adj_ptr / adj over n nodes), each

@@ -619,6 +619,10 @@ void zone_disable(lgdm_ctx* c) {
   if (c->zone) c->zone->active = false;
 }
 
+void zone_forget(lgdm_ctx* c) {
+  if (c->zone) c->zone->built_serial = -1;
+}
+
 int64_t zone_dofs(const lgdm_ctx* c) { return zone_active(c) ? c->zone->nz * 4 : 0; }
 
 // out = x_z + M_mg (b - S K x_z), x_z = Z^-1 b_z

@@ -518,7 +518,7 @@ def serving_leg(seconds, n_requests, increments):
     reqs = W.serving_stream(n_requests=n_requests, rate_per_s=20.0, seed=0,
                             first_increments=increments if increments > 0 else None)
     loop = serving.ServingLoop(reqs, precision=binding.MIXED, max_slots=64)
-    summ = loop.run(time_limit_s=seconds, realtime=True)
+    summ = loop.run(time_limit_s=seconds, realtime=True, log=log)
     loop.close()
     summ["workload"] = ("%d requests, Poisson arrivals 20/s, 2D notched plates 40x20..400x200 Q4 with 50-200 "
                         "increments, %s, mixed precision, 64 slots; served for at most %.0f s" % (
@@ -561,6 +561,8 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=128)
     ap.add_argument("--serving-increments", type=int, default=12,
                     help="increments served per request (the first ones of its load path; 0: all)")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="run only the serving leg and print its report as the JSON line")
     ap.add_argument("--coupling", type=int, default=0, choices=[0, 1],
                     help="1: the stress of Eq. 2 with its h term and the consistent tangent (material coupling "
                          "variant); 0: the executed-code form (default)")
@@ -588,6 +590,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     import lgdm_workloads as W
     from paper_2301_06503_amd import binding
+    if args.serving_only:
+        print(json.dumps({"metric": "serving", "serving": serving_leg(args.serving_seconds, args.serving_requests,
+                                                                      args.serving_increments)}))
+        return
     prob = W.config(args.config)
     if args.coupling:
         prob.material = dataclasses.replace(prob.material, coupling=args.coupling)

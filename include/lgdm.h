@@ -547,10 +547,12 @@ typedef struct lgdm_slot_info {
   int64_t n_gauss, ndof, footprint_bytes;
   double max_damage;         /* of the last committed increment               */
   int32_t last_status;       /* lgdm_status of the failure for FAILED slots   */
-  int32_t retries;           /* increments tried a second time, from their start,
-                                with the line-search setting flipped (an
-                                increment that does not converge gets one
-                                retry; a second failure fails the request)     */
+  int32_t retries;           /* load steps tried a second time, from their start,
+                                with the line-search setting flipped           */
+  int64_t cutbacks;          /* load steps halved after both tries failed (at
+                                most 3 halvings per increment, the smallest
+                                step 1/8 of an increment; then the request
+                                fails)                                          */
 } lgdm_slot_info;
 
 typedef struct lgdm_tick_report {

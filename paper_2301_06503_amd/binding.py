@@ -101,7 +101,8 @@ class SlotInfo(ctypes.Structure):
     _fields_ = [("state", ctypes.c_int32), ("newton_in_increment", ctypes.c_int32)] + [
         (n, ctypes.c_int64) for n in ("increment", "n_increments", "newton_total", "krylov_total",
                                       "assemblies_total", "n_gauss", "ndof", "footprint_bytes")] + [
-        ("max_damage", ctypes.c_double), ("last_status", ctypes.c_int32), ("retries", ctypes.c_int32)]
+        ("max_damage", ctypes.c_double), ("last_status", ctypes.c_int32), ("retries", ctypes.c_int32),
+        ("cutbacks", ctypes.c_int64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

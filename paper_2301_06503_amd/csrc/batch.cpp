@@ -41,11 +41,20 @@ struct Slot {
   bool stepped = false;
   double phi_prev = 0.0, alpha = 1.0;
   int cuts = 0;
-  // the current increment's second attempt, with the line-search setting
-  // flipped; increments retried so far
+  // the current load step's second attempt, with the line-search setting
+  // flipped; load steps retried so far
   bool ls_flip = false;
   int retries = 0;
+  // load stepping inside an increment: the committed state sits at the
+  // fraction f0 of increment `done` + 1, the step in progress goes to f1;
+  // `cuts` halvings of this increment's steps so far
+  int64_t done = 0;
+  double f0 = 0.0, f1 = 1.0;
+  int step_cuts = 0;
+  int64_t cutbacks = 0;
 };
+
+constexpr int MAX_STEP_CUTS = 3;   // smallest load step: 1/8 of an increment
 
 }  // namespace
 
@@ -122,13 +131,15 @@ void release(lgdm_batch* b, Slot& s) {
 
 void fail_slot(lgdm_batch* b, int i, lgdm_status st);
 
-// An increment that does not converge is tried once more from its start
+// A load step that does not converge is tried once more from its start
 // with the line-search setting flipped (full steps converge some load steps
-// the line search does not, and the other way round); a second failure
-// fails the request.
+// the line search does not, and the other way round); when that fails too,
+// the step is halved (the request's committed state stays where it is), at
+// most MAX_STEP_CUTS times per increment; then the request fails.
 void retry_or_fail(lgdm_batch* b, int i, lgdm_status st) {
   Slot& s = b->slots[i];
-  if (st != LGDM_ERR_NOT_CONVERGED || s.ls_flip || !s.ctx) {
+  const bool retry = !s.ls_flip, cut = s.ls_flip && s.step_cuts < MAX_STEP_CUTS;
+  if (st != LGDM_ERR_NOT_CONVERGED || !s.ctx || !(retry || cut)) {
     fail_slot(b, i, st);
     return;
   }
@@ -136,9 +147,16 @@ void retry_or_fail(lgdm_batch* b, int i, lgdm_status st) {
   s.solving = false;
   s.run.reset();
   lgdm_abort_increment(s.ctx);   // restores the committed state
-  s.in_increment = false;        // the next tick begins the increment again
-  s.ls_flip = true;
-  s.retries += 1;
+  s.in_increment = false;        // the next tick begins the step again
+  if (retry) {
+    s.ls_flip = true;
+    s.retries += 1;
+  } else {
+    s.ls_flip = false;
+    s.f1 = 0.5 * (s.f0 + s.f1);
+    s.step_cuts += 1;
+    s.cutbacks += 1;
+  }
 }
 
 void fail_slot(lgdm_batch* b, int i, lgdm_status st) {
@@ -331,7 +349,7 @@ lgdm_status lgdm_batch_tick(lgdm_batch* b, const lgdm_solver_opts* o, lgdm_tick_
     running++;
     if (s.solving) continue;
     if (!s.in_increment) {
-      const double lam = (double)(s.ctx->increment + 1) / (double)s.n_increments;
+      const double lam = ((double)s.done + s.f1) / (double)s.n_increments;
       lgdm_status st = lgdm_begin_increment(s.ctx, lam);
       if (st != LGDM_OK) {
         fail_slot(b, i, st);
@@ -412,8 +430,19 @@ lgdm_status lgdm_batch_tick(lgdm_batch* b, const lgdm_solver_opts* o, lgdm_tick_
       s.max_damage = c->norms_host[12];
       s.in_increment = false;
       s.ls_flip = false;
-      R.committed++;
-      if (c->increment >= s.n_increments) {
+      if (s.f1 >= 1.0) {
+        // the increment is complete
+        s.done += 1;
+        s.f0 = 0.0;
+        s.f1 = 1.0;
+        s.step_cuts = 0;
+        R.committed++;
+      } else {
+        // a sub-step: the next one takes the rest of the increment
+        s.f0 = s.f1;
+        s.f1 = 1.0;
+      }
+      if (s.done >= s.n_increments) {
         s.state = LGDM_SLOT_FINISHED;
         R.finished++;
       }
@@ -519,7 +548,7 @@ lgdm_status lgdm_batch_slot_info(lgdm_batch* b, int32_t slot, lgdm_slot_info* in
   lgdm_slot_info I{};
   I.state = s.state;
   I.newton_in_increment = s.newton;
-  I.increment = s.ctx ? s.ctx->increment : 0;
+  I.increment = s.done;
   I.n_increments = s.n_increments;
   I.newton_total = s.newton_total;
   I.krylov_total = s.krylov_total;
@@ -530,6 +559,7 @@ lgdm_status lgdm_batch_slot_info(lgdm_batch* b, int32_t slot, lgdm_slot_info* in
   I.max_damage = s.max_damage;
   I.last_status = s.last_status;
   I.retries = s.retries;
+  I.cutbacks = s.cutbacks;
   *info = I;
   return LGDM_OK;
 }

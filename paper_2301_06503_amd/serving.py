@@ -43,6 +43,7 @@ class RequestRecord:
     assemblies: int = 0
     max_damage: float = 0.0
     retries: int = 0
+    cutbacks: int = 0
     increment_latency_ms: List[float] = dataclasses.field(default_factory=list)
 
 
@@ -74,6 +75,7 @@ class ServingLoop:
         inc_start: Dict[int, float] = {}      # slot -> start of its current increment
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0
+        next_report = 30.0
         while pending or queue or running:
             t = now()
             if time_limit_s is not None and t > time_limit_s:
@@ -104,6 +106,13 @@ class ServingLoop:
             rep = self.batch.tick(self.opts)
             t_tick1 = now()
             self.ticks += 1
+            if log and t_tick1 >= next_report:
+                # a progress line every 30 s of serving (long runs)
+                done = sum(1 for r in self.records.values() if r.state != "running" and r.state != "queued")
+                log("serving t=%.0fs: %d ticks, %d running, %d retired, %d queued, %d increments committed"
+                    % (t_tick1, self.ticks, len(running), done, len(queue) + len(pending),
+                       sum(r.increments for r in self.records.values())))
+                next_report = t_tick1 + 30.0
             self.gp_assembled += rep["gauss_points"]
             self.t_assembly_ms += rep["t_assembly_ms"]
             for slot, rid in list(running.items()):
@@ -119,6 +128,7 @@ class ServingLoop:
                 rec.gauss_points = info["n_gauss"]
                 rec.max_damage = info["max_damage"]
                 rec.retries = info["retries"]
+                rec.cutbacks = info["cutbacks"]
                 if info["state"] in (binding.SLOT_FINISHED, binding.SLOT_FAILED):
                     rec.state = "finished" if info["state"] == binding.SLOT_FINISHED else \
                         "failed(%s)" % binding.STATUS_NAMES.get(info["last_status"])
@@ -153,6 +163,7 @@ class ServingLoop:
             "requests_failed": len(failed),
             "failed_requests": sorted((r.rid, r.state, r.increments) for r in failed),
             "increment_retries": sum(r.retries for r in self.records.values()),
+            "load_step_cutbacks": sum(r.cutbacks for r in self.records.values()),
             "request_latency_p50_s": pct(compl, 50),
             "request_latency_p99_s": pct(compl, 99),
             "request_latency_max_s": float(max(compl)) if compl else None,

@@ -17,25 +17,27 @@ def _loop(records, wall_s):
     return loop
 
 
-def _rec(rid, arrival, admitted, finished, state, increments, lat, gp=100, retries=0):
+def _rec(rid, arrival, admitted, finished, state, increments, lat, gp=100, retries=0, cutbacks=0):
     r = serving.RequestRecord(rid, arrival)
     r.admitted_s, r.finished_s, r.state, r.increments = admitted, finished, state, increments
     r.increment_latency_ms = list(lat)
     r.gauss_points = gp
     r.retries = retries
+    r.cutbacks = cutbacks
     return r
 
 
 def test_summary_whole_requests():
     recs = [_rec(0, 0.0, 0.5, 4.5, "finished", 3, [1000.0, 1500.0, 1500.0], retries=1),
             _rec(1, 1.0, 1.0, 3.0, "finished", 2, [900.0, 1100.0]),
-            _rec(2, 2.0, 2.5, 6.0, "failed(NOT_CONVERGED)", 1, [800.0], retries=1),
+            _rec(2, 2.0, 2.5, 6.0, "failed(NOT_CONVERGED)", 1, [800.0], retries=1, cutbacks=3),
             _rec(3, 3.0, None, None, "queued", 0, [])]
     s = _loop(recs, 10.0).summary()
     assert s["requests_arrived"] == 4
     assert s["requests_finished"] == 2 and s["requests_failed"] == 1
     assert s["failed_requests"] == [(2, "failed(NOT_CONVERGED)", 1)]
     assert s["increment_retries"] == 2
+    assert s["load_step_cutbacks"] == 3
     # completion latency: arrival to the last commit, finished requests only
     assert s["request_latency_p50_s"] == pytest.approx(np.percentile([4.5, 2.0], 50))
     assert s["request_latency_max_s"] == pytest.approx(4.5)

@@ -20,16 +20,22 @@
 //           the next or previous one, so in level order the zone's block Z of
 //           S K is block tridiagonal.  Consecutive levels are merged into
 //           groups of at least ZONE_GROUP_MIN unknowns (fewer launches).
-//   factor  block LU over the groups: S_0 = Z_00, S_k = Z_kk - Z_k,k-1
-//           S_{k-1}^-1 Z_k-1,k; each S_k by LU with partial pivoting and
-//           explicit inverse W_k (rocSOLVER getrf, getri); N_k = W_k Z_k,k-1
-//           and M_k = W_k Z_k,k+1 (rocBLAS gemm).  A CPU model on the
-//           128x32x16 beam after its peak (zone from D >= 0.99, 5,808
-//           unknowns, condition number 9e8) took 5e9 flops against 4e11 for
-//           the dense LU, and its solve differed from the dense one by 5e-9.
-//   apply   x_z = Z^-1 b_z by the two sweeps y_k = W_k b_k - N_k y_{k-1},
-//           x_k = y_k - M_k x_{k+1} (one launch per group and sweep, one
-//           wavefront per row of the row-major copies of W_k, N_k, M_k);
+//   factor  twisted block LU over the groups 0..L-1, from both ends toward
+//           the middle group c = L/2: S_k = Z_kk - Z_k,k-1 S_{k-1}^-1 Z_k-1,k
+//           for k < c, S_k = Z_kk - Z_k,k+1 S_{k+1}^-1 Z_k+1,k for k > c, and
+//           S_c with both corrections.  Each S_k by LU with partial pivoting
+//           and explicit inverse G_k (rocSOLVER getrf, getri), then
+//           P_k = G_k Z_k,k-1 and N_k = G_k Z_k,k+1 (rocBLAS gemm); the two
+//           chains run on two streams.  A CPU model on the 128x32x16 beam
+//           after its peak (zone from D >= 0.99, 5,808 unknowns, condition
+//           number 9e8) took 5e9 flops against 4e11 for the dense LU, and
+//           its (one-sided) block solve differed from the dense one by 5e-9.
+//   apply   x_z = Z^-1 b_z by sweeps from both ends: y_k = G_k b_k -
+//           P_k y_{k-1} (k < c) and y_k = G_k b_k - N_k y_{k+1} (k > c) in
+//           the same launches, x_c = G_c b_c - P_c y_{c-1} - N_c y_{c+1},
+//           then x_k = y_k - N_k x_{k+1} (k < c) and x_k = y_k - P_k x_{k-1}
+//           (k > c), again two groups per launch: about L + 1 launches, one
+//           wavefront per row of the row-major copies of [G_k | P_k | N_k];
 //           r = b - S K x_z (only rows of the zone
 //           and its neighbour nodes change); out = x_z + M_mg r, with M_mg
 //           the multigrid cycle (multiplicative: the same CPU model needed 64
@@ -79,21 +85,26 @@ struct Zone {
   int64_t* poff_d = nullptr;                // [cap_groups + 1]
   int32_t* halo = nullptr;                  // nodes whose rows r = b - S K x_z changes [cap_halo]
   // per group k (m_k unknowns; column major, leading dimension m_k):
-  //   P_k = [Z_k,k-1 | Z_kk -> W_k | Z_k,k+1]   Q_k = [N_k | M_k]
+  //   panel [Z_k,k-1 | Z_kk -> G_k | Z_k,k+1] in P, [P_k | N_k] in Q
   double* P = nullptr;                      // [cap_p]
   double* Q = nullptr;                      // [cap_q]
-  // the sweeps' matrices, row major, in P's layout: per group k the rows
-  // [W_k | N_k] (m_k + m_{k-1} each), then the rows of M_k (m_{k+1} each)
+  // the sweeps' matrices, row major, in P's layout: per group k the rows of
+  // [G_k | P_k | N_k] (m_k + m_{k-1} + m_{k+1} each)
   double* T = nullptr;                      // [cap_p]
-  rocblas_int* ipiv = nullptr;              // [cap_m]
+  rocblas_int* ipiv = nullptr;              // [cap_m] pivots of the chain from group 0
+  rocblas_int* ipiv2 = nullptr;             // [cap_m] pivots of the chain from group L-1
   rocblas_int* info = nullptr;              // [2 cap_groups]
   double* bz = nullptr;                     // [cap_nodes * 4] b at the zone's unknowns
   double* xz = nullptr;                     // [cap_nodes * 4] Z^-1 b_z
   double* r = nullptr;                      // [ndof]
   int64_t cap_nodes = 0, cap_halo = 0, cap_groups = 0, cap_p = 0, cap_q = 0, cap_m = 0;
   void* ws = nullptr;
+  void* ws2 = nullptr;
   size_t ws_size = 0;
-  rocblas_handle handle = nullptr;
+  rocblas_handle handle = nullptr;          // on the context's stream: chain from group 0, middle group
+  rocblas_handle handle2 = nullptr;         // on stream2: chain from group L-1
+  hipStream_t stream2 = nullptr;            // default priority
+  hipEvent_t ev_built = nullptr, ev_chain2 = nullptr;
   int64_t nz = 0, nh = 0;                   // zone nodes, halo nodes of the current tangent
   bool active = false;
   // the zone whose factors P and Q hold: its nodes (ascending) and the
@@ -177,26 +188,43 @@ __global__ void zone_rowmajor_kernel(int64_t m, int64_t n, const double* __restr
   out[r * ldo + c0 + c] = A[t];
 }
 
-// One group's step of a sweep, one wavefront per row of the group:
-// y[r] = sum_c A[r, c] u[c] - sum_c A[r, na + c] v[c] (A row major with
-// leading dimension lda; na or nb may be 0), with accumulate y[r] + that.
-// Lanes stride the row by 64 (coalesced); the lanes' partial sums are
-// combined by a fixed butterfly, so every apply sums in the same order.
+// One group's step of a sweep: y[r] = sum_c A[r, c] u[c] - sum_c
+// A[r, op + c] v[c] - sum_c A[r, on + c] w[c] for r < m (A row major with
+// leading dimension lda; nu, nv or nw may be 0), with accumulate y[r] plus
+// that.  One wavefront per row; lanes stride the row by 64 (coalesced) and
+// are combined by a fixed butterfly, so every apply sums in the same order.
+struct SweepOp {
+  int64_t m, lda;
+  const double* A;
+  const double* u;
+  int64_t nu;
+  const double* v;
+  int64_t nv, op;
+  const double* w;
+  int64_t nw, on;
+  double* y;
+  int accumulate;
+};
 constexpr int SW_ROWS = ZBS / 64;
-__global__ void __launch_bounds__(ZBS) zone_sweep_kernel(int64_t m, int64_t lda, const double* __restrict__ A,
-                                                         int64_t na, const double* __restrict__ u, int64_t nb,
-                                                         const double* __restrict__ v, double* __restrict__ y,
-                                                         int accumulate, const double* __restrict__ sc) {
+inline unsigned sweep_blocks(const SweepOp& o) { return (unsigned)((o.m + SW_ROWS - 1) / SW_ROWS); }
+
+// two independent group steps in one launch (the two ends of the twisted
+// sweep): blocks [0, nblk_a) take a, the rest take b
+__global__ void __launch_bounds__(ZBS) zone_sweep_kernel(SweepOp a, SweepOp b, unsigned nblk_a,
+                                                         const double* __restrict__ sc) {
   if (sc && sc[KSLOT_DONE] != 0.0) return;
+  const bool first = blockIdx.x < nblk_a;
+  const SweepOp& o = first ? a : b;
   const int lane = threadIdx.x % 64;
-  const int64_t row = (int64_t)blockIdx.x * SW_ROWS + threadIdx.x / 64;
-  if (row >= m) return;  // uniform over the wavefront
-  const double* a = A + row * lda;
+  const int64_t row = (int64_t)(first ? blockIdx.x : blockIdx.x - nblk_a) * SW_ROWS + threadIdx.x / 64;
+  if (row >= o.m) return;  // uniform over the wavefront
+  const double* __restrict__ r = o.A + row * o.lda;
   double acc = 0.0;
-  for (int64_t c = lane; c < na; c += 64) acc += a[c] * u[c];
-  for (int64_t c = lane; c < nb; c += 64) acc -= a[na + c] * v[c];
+  for (int64_t c = lane; c < o.nu; c += 64) acc += r[c] * o.u[c];
+  for (int64_t c = lane; c < o.nv; c += 64) acc -= r[o.op + c] * o.v[c];
+  for (int64_t c = lane; c < o.nw; c += 64) acc -= r[o.on + c] * o.w[c];
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-  if (lane == 0) y[row] = accumulate ? y[row] + acc : acc;
+  if (lane == 0) o.y[row] = o.accumulate ? o.y[row] + acc : acc;
 }
 
 // r = b everywhere (the halo rows are overwritten next)
@@ -313,7 +341,12 @@ int64_t zone_levels(int64_t nz, const int64_t* adj_ptr, const int32_t* adj, int3
 
 void zone_release(lgdm_ctx* c) {
   if (!c->zone) return;
-  if (c->zone->handle) (void)rocblas_destroy_handle(c->zone->handle);
+  Zone& z = *c->zone;
+  if (z.handle) (void)rocblas_destroy_handle(z.handle);
+  if (z.handle2) (void)rocblas_destroy_handle(z.handle2);
+  if (z.ev_built) (void)hipEventDestroy(z.ev_built);
+  if (z.ev_chain2) (void)hipEventDestroy(z.ev_chain2);
+  if (z.stream2) (void)hipStreamDestroy(z.stream2);
   delete c->zone;
   c->zone = nullptr;
 }
@@ -350,14 +383,24 @@ hipError_t zone_setup(lgdm_ctx* c, bool allow_alloc, bool reuse, double dmin0, b
       msg = "device allocation failed (process zone)";
       return hipErrorOutOfMemory;
     }
-    if (rocblas_create_handle(&z.handle) != rocblas_status_success) {
+    if (rocblas_create_handle(&z.handle) != rocblas_status_success ||
+        rocblas_create_handle(&z.handle2) != rocblas_status_success) {
       msg = "rocblas_create_handle failed";
       return hipErrorUnknown;
     }
+    // the second chain of the factorisation runs on a stream of its own
+    // (default priority), ordered against the context's stream by events
+    if ((e = hipStreamCreateWithFlags(&z.stream2, hipStreamNonBlocking)) ||
+        (e = hipEventCreateWithFlags(&z.ev_built, hipEventDisableTiming)) ||
+        (e = hipEventCreateWithFlags(&z.ev_chain2, hipEventDisableTiming)))
+      return e;
     // no atomics: the factors, and the solves they precondition, are the
     // same bits in every run
     if ((e = rb_err(rocblas_set_atomics_mode(z.handle, rocblas_atomics_not_allowed), "rocblas_set_atomics_mode",
-                    msg)))
+                    msg)) ||
+        (e = rb_err(rocblas_set_atomics_mode(z.handle2, rocblas_atomics_not_allowed), "rocblas_set_atomics_mode",
+                    msg)) ||
+        (e = rb_err(rocblas_set_stream(z.handle2, z.stream2), "rocblas_set_stream", msg)))
       return e;
   }
   if ((e = rb_err(rocblas_set_stream(z.handle, c->stream), "rocblas_set_stream", msg))) return e;
@@ -487,13 +530,15 @@ hipError_t zone_setup(lgdm_ctx* c, bool allow_alloc, bool reuse, double dmin0, b
     const int64_t capn = std::max(z.nz, z.cap_nodes), caph = std::max(z.nh, z.cap_halo),
                   capg = std::max(z.L, z.cap_groups), capp = std::max(np, z.cap_p), capq = std::max(nq, z.cap_q),
                   capm = std::max(z.mmax, z.cap_m);
-    for (void* p : {(void*)z.P, (void*)z.Q, (void*)z.T, (void*)z.ipiv, (void*)z.info, (void*)z.bz, (void*)z.xz,
-                    (void*)z.znodes, (void*)z.zgroup, (void*)z.goff_d, (void*)z.poff_d, (void*)z.halo, z.ws})
+    for (void* p : {(void*)z.P, (void*)z.Q, (void*)z.T, (void*)z.ipiv, (void*)z.ipiv2, (void*)z.info, (void*)z.bz,
+                    (void*)z.xz, (void*)z.znodes, (void*)z.zgroup, (void*)z.goff_d, (void*)z.poff_d, (void*)z.halo, z.ws,
+                    z.ws2})
       dfree(c, p);
     z.P = (double*)dalloc(c, capp * sizeof(double));
     z.T = (double*)dalloc(c, capp * sizeof(double));
     z.Q = (double*)dalloc(c, std::max<int64_t>(capq, 1) * sizeof(double));
     z.ipiv = (rocblas_int*)dalloc(c, capm * sizeof(rocblas_int));
+    z.ipiv2 = (rocblas_int*)dalloc(c, capm * sizeof(rocblas_int));
     z.info = (rocblas_int*)dalloc(c, 2 * capg * sizeof(rocblas_int));
     z.bz = (double*)dalloc(c, capn * 4 * sizeof(double));
     z.xz = (double*)dalloc(c, capn * 4 * sizeof(double));
@@ -519,13 +564,16 @@ hipError_t zone_setup(lgdm_ctx* c, bool allow_alloc, bool reuse, double dmin0, b
     rocblas_stop_device_memory_size_query(z.handle, &ws);
     z.ws_size = std::max<size_t>(ws, (size_t)64 << 20);
     z.ws = dalloc(c, z.ws_size);
-    if (!z.P || !z.Q || !z.T || !z.ipiv || !z.info || !z.bz || !z.xz || !z.znodes || !z.zgroup || !z.goff_d || !z.poff_d ||
+    z.ws2 = dalloc(c, z.ws_size);
+    if (!z.P || !z.Q || !z.T || !z.ipiv || !z.ipiv2 || !z.ws2 || !z.info || !z.bz || !z.xz || !z.znodes || !z.zgroup || !z.goff_d || !z.poff_d ||
         !z.halo || !z.ws) {
       z.cap_nodes = z.cap_halo = z.cap_groups = z.cap_p = z.cap_q = z.cap_m = 0;
       msg = "device allocation failed (process zone factors)";
       return hipErrorOutOfMemory;
     }
-    if ((e = rb_err(rocblas_set_workspace(z.handle, z.ws, z.ws_size), "rocblas_set_workspace", msg))) return e;
+    if ((e = rb_err(rocblas_set_workspace(z.handle, z.ws, z.ws_size), "rocblas_set_workspace", msg)) ||
+        (e = rb_err(rocblas_set_workspace(z.handle2, z.ws2, z.ws_size), "rocblas_set_workspace", msg)))
+      return e;
     z.cap_nodes = capn;
     z.cap_halo = caph;
     z.cap_groups = capg;
@@ -553,49 +601,58 @@ hipError_t zone_setup(lgdm_ctx* c, bool allow_alloc, bool reuse, double dmin0, b
         z.nz, c->max_nbr, z.znodes, z.zmap, z.zgroup, z.goff_d, z.poff_d, c->row_ptr, c->nbr_ptr, c->nbr, c->vals,
         se, z.P);
   if ((e = hipGetLastError())) return e;
-  // block LU over the groups, in order
+  // twisted block LU: the chain from group 0 up to the middle group c on the
+  // context's stream, the chain from group L-1 down to c on stream2, then c
   const double one = 1.0, mone = -1.0, zero = 0.0;
-  for (int64_t k = 0; k < z.L; ++k) {
-    const int64_t m = z.goff[k + 1] - z.goff[k], mp = k > 0 ? z.goff[k] - z.goff[k - 1] : 0,
-                  mn = k + 1 < z.L ? z.goff[k + 2] - z.goff[k + 1] : 0;
-    double* Lk = z.P + z.poff[k];
-    double* Dk = Lk + m * mp;
-    double* Uk = Dk + m * m;
-    double* Nk = z.Q + z.qoff[k];
-    double* Mk = Nk + m * mp;
-    const rocblas_int im = (rocblas_int)m, imp = (rocblas_int)mp, imn = (rocblas_int)mn;
-    if (k > 0) {
-      // S_k = Z_kk - Z_k,k-1 M_{k-1}
-      const int64_t mpp = k > 1 ? z.goff[k - 1] - z.goff[k - 2] : 0;
-      const double* Mprev = z.Q + z.qoff[k - 1] + mp * mpp;
-      if ((e = rb_err(rocblas_dgemm(z.handle, rocblas_operation_none, rocblas_operation_none, im, im, imp, &mone, Lk,
-                                    im, Mprev, imp, &one, Dk, im),
-                      "dgemm (Schur complement)", msg)))
-        return e;
-    }
-    if ((e = rb_err(rocsolver_dgetrf(z.handle, im, im, Dk, im, z.ipiv, z.info + 2 * k), "dgetrf", msg))) return e;
-    if ((e = rb_err(rocsolver_dgetri(z.handle, im, Dk, im, z.ipiv, z.info + 2 * k + 1), "dgetri", msg))) return e;
-    if (k > 0 && (e = rb_err(rocblas_dgemm(z.handle, rocblas_operation_none, rocblas_operation_none, im, imp, im,
-                                           &one, Dk, im, Lk, im, &zero, Nk, im),
-                             "dgemm (N_k)", msg)))
-      return e;
-    if (mn > 0 && (e = rb_err(rocblas_dgemm(z.handle, rocblas_operation_none, rocblas_operation_none, im, imn, im,
-                                            &one, Dk, im, Uk, im, &zero, Mk, im),
-                              "dgemm (M_k)", msg)))
-      return e;
-  }
-  // the sweeps read rows: [W_k | N_k] and M_k in row-major order
-  for (int64_t k = 0; k < z.L; ++k) {
-    const int64_t m = z.goff[k + 1] - z.goff[k], mp = k > 0 ? z.goff[k] - z.goff[k - 1] : 0,
-                  mn = k + 1 < z.L ? z.goff[k + 2] - z.goff[k + 1] : 0;
-    const double* Wk = z.P + z.poff[k] + m * mp;
-    const double* Nk = z.Q + z.qoff[k];
-    const double* Mk = Nk + m * mp;
-    double* Fk = z.T + z.poff[k];
-    double* Bk = Fk + m * (m + mp);
-    zone_rowmajor_kernel<<<nblocks(m * m), ZBS, 0, c->stream>>>(m, m, Wk, Fk, m + mp, 0);
-    if (mp > 0) zone_rowmajor_kernel<<<nblocks(m * mp), ZBS, 0, c->stream>>>(m, mp, Nk, Fk, m + mp, m);
-    if (mn > 0) zone_rowmajor_kernel<<<nblocks(m * mn), ZBS, 0, c->stream>>>(m, mn, Mk, Bk, mn, 0);
+  const int64_t NG = z.L, mid = z.L / 2;
+  auto gsize = [&](int64_t k) { return k >= 0 && k < NG ? z.goff[k + 1] - z.goff[k] : (int64_t)0; };
+  // group k's panel pieces: Z_k,k-1 | Z_kk (-> G_k) | Z_k,k+1, and P_k | N_k
+  auto Zprev = [&](int64_t k) { return z.P + z.poff[k]; };
+  auto Zdiag = [&](int64_t k) { return z.P + z.poff[k] + gsize(k) * gsize(k - 1); };
+  auto Znext = [&](int64_t k) { return z.P + z.poff[k] + gsize(k) * (gsize(k - 1) + gsize(k)); };
+  auto Pk = [&](int64_t k) { return z.Q + z.qoff[k]; };
+  auto Nk = [&](int64_t k) { return z.Q + z.qoff[k] + gsize(k) * gsize(k - 1); };
+  // S_k -= Z_k,j X (X: m_j x m_k, the neighbour j's P or N), then G_k, P_k, N_k
+  auto factor_group = [&](rocblas_handle h, rocblas_int* piv, int64_t k, bool from_prev, bool from_next) {
+    const rocblas_int im = (rocblas_int)gsize(k), imp = (rocblas_int)gsize(k - 1), imn = (rocblas_int)gsize(k + 1);
+    hipError_t r;
+    if (from_prev &&
+        (r = rb_err(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, im, im, imp, &mone, Zprev(k),
+                                  im, Nk(k - 1), imp, &one, Zdiag(k), im),
+                    "dgemm (Schur complement)", msg)))
+      return r;
+    if (from_next &&
+        (r = rb_err(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, im, im, imn, &mone, Znext(k),
+                                  im, Pk(k + 1), imn, &one, Zdiag(k), im),
+                    "dgemm (Schur complement)", msg)))
+      return r;
+    if ((r = rb_err(rocsolver_dgetrf(h, im, im, Zdiag(k), im, piv, z.info + 2 * k), "dgetrf", msg)) ||
+        (r = rb_err(rocsolver_dgetri(h, im, Zdiag(k), im, piv, z.info + 2 * k + 1), "dgetri", msg)))
+      return r;
+    if (imp > 0 && (r = rb_err(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, im, imp, im, &one,
+                                             Zdiag(k), im, Zprev(k), im, &zero, Pk(k), im),
+                               "dgemm (P_k)", msg)))
+      return r;
+    if (imn > 0 && (r = rb_err(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, im, imn, im, &one,
+                                             Zdiag(k), im, Znext(k), im, &zero, Nk(k), im),
+                               "dgemm (N_k)", msg)))
+      return r;
+    return hipSuccess;
+  };
+  if ((e = hipEventRecord(z.ev_built, c->stream)) || (e = hipStreamWaitEvent(z.stream2, z.ev_built, 0))) return e;
+  for (int64_t k = 0; k < mid; ++k)
+    if ((e = factor_group(z.handle, z.ipiv, k, k > 0, false))) return e;
+  for (int64_t k = NG - 1; k > mid; --k)
+    if ((e = factor_group(z.handle2, z.ipiv2, k, false, k < NG - 1))) return e;
+  if ((e = hipEventRecord(z.ev_chain2, z.stream2)) || (e = hipStreamWaitEvent(c->stream, z.ev_chain2, 0))) return e;
+  if ((e = factor_group(z.handle, z.ipiv, mid, mid > 0, mid < NG - 1))) return e;
+  // the sweeps read rows of [G_k | P_k | N_k] in row-major order
+  for (int64_t k = 0; k < NG; ++k) {
+    const int64_t m = gsize(k), mp = gsize(k - 1), mn = gsize(k + 1), lda = m + mp + mn;
+    double* Tk = z.T + z.poff[k];
+    zone_rowmajor_kernel<<<nblocks(m * m), ZBS, 0, c->stream>>>(m, m, Zdiag(k), Tk, lda, 0);
+    if (mp > 0) zone_rowmajor_kernel<<<nblocks(m * mp), ZBS, 0, c->stream>>>(m, mp, Pk(k), Tk, lda, m);
+    if (mn > 0) zone_rowmajor_kernel<<<nblocks(m * mn), ZBS, 0, c->stream>>>(m, mn, Nk(k), Tk, lda, m + mp);
   }
   if ((e = hipGetLastError())) return e;
   std::vector<rocblas_int> info(2 * z.L, 0);
@@ -634,19 +691,55 @@ hipError_t zone_apply(lgdm_ctx* c, const double* b, double* out, const double* s
       z.nz > z.cap_nodes || z.nh > z.cap_halo || z.poff[z.L] > z.cap_p || z.L > z.cap_groups)
     return hipErrorInvalidValue;
   zone_gather_kernel<<<nblocks(n), ZBS, 0, st>>>(z.nz, z.znodes, b, z.bz, sc);
-  // forward sweep: y_k = W_k b_k - N_k y_{k-1}
-  for (int64_t k = 0; k < z.L; ++k) {
-    const int64_t m = z.goff[k + 1] - z.goff[k], mp = k > 0 ? z.goff[k] - z.goff[k - 1] : 0;
-    zone_sweep_kernel<<<(unsigned)((m + SW_ROWS - 1) / SW_ROWS), ZBS, 0, st>>>(
-        m, m + mp, z.T + z.poff[k], m, z.bz + z.goff[k], mp, k > 0 ? z.xz + z.goff[k - 1] : nullptr,
-        z.xz + z.goff[k], 0, sc);
+  // twisted sweeps: both ends toward the middle group, then back out; the
+  // two groups of a step share one launch
+  const int64_t L = z.L, mid = z.L / 2;
+  auto gsize = [&](int64_t k) { return k >= 0 && k < L ? z.goff[k + 1] - z.goff[k] : (int64_t)0; };
+  // y_k (+)= G_k u - P_k v - N_k w over group k's rows
+  auto op = [&](int64_t k, const double* u, const double* v, const double* w, int accumulate) {
+    const int64_t m = gsize(k), mp = gsize(k - 1), mn = gsize(k + 1);
+    SweepOp o;
+    o.m = m;
+    o.lda = m + mp + mn;
+    o.A = z.T + z.poff[k];
+    o.u = u;
+    o.nu = u ? m : 0;
+    o.v = v;
+    o.nv = v ? mp : 0;
+    o.op = m;
+    o.w = w;
+    o.nw = w ? mn : 0;
+    o.on = m + mp;
+    o.y = z.xz + z.goff[k];
+    o.accumulate = accumulate;
+    return o;
+  };
+  auto launch = [&](const SweepOp* a, const SweepOp* b) {
+    const SweepOp& first = a ? *a : *b;
+    const SweepOp& second = a && b ? *b : first;
+    const unsigned na = sweep_blocks(first), nb = a && b ? sweep_blocks(second) : 0;
+    zone_sweep_kernel<<<na + nb, ZBS, 0, st>>>(first, second, na, sc);
+  };
+  const int64_t steps = std::max(mid, L - 1 - mid);
+  auto xz_at = [&](int64_t k) { return (const double*)(z.xz + z.goff[k]); };
+  for (int64_t s = 0; s < steps; ++s) {
+    SweepOp a, b;
+    const bool ha = s < mid, hb = L - 1 - s > mid;
+    if (ha) a = op(s, z.bz + z.goff[s], s > 0 ? xz_at(s - 1) : nullptr, nullptr, 0);
+    if (hb) b = op(L - 1 - s, z.bz + z.goff[L - 1 - s], nullptr, L - 1 - s < L - 1 ? xz_at(L - s) : nullptr, 0);
+    launch(ha ? &a : nullptr, hb ? &b : nullptr);
   }
-  // backward sweep: x_k = y_k - M_k x_{k+1}
-  for (int64_t k = z.L - 2; k >= 0; --k) {
-    const int64_t m = z.goff[k + 1] - z.goff[k], mp = k > 0 ? z.goff[k] - z.goff[k - 1] : 0,
-                  mn = z.goff[k + 2] - z.goff[k + 1];
-    zone_sweep_kernel<<<(unsigned)((m + SW_ROWS - 1) / SW_ROWS), ZBS, 0, st>>>(
-        m, mn, z.T + z.poff[k] + m * (m + mp), 0, nullptr, mn, z.xz + z.goff[k + 1], z.xz + z.goff[k], 1, sc);
+  {
+    SweepOp m = op(mid, z.bz + z.goff[mid], mid > 0 ? xz_at(mid - 1) : nullptr,
+                   mid < L - 1 ? xz_at(mid + 1) : nullptr, 0);
+    launch(&m, nullptr);
+  }
+  for (int64_t s = 0; s < steps; ++s) {
+    SweepOp a, b;
+    const bool ha = mid - 1 - s >= 0, hb = mid + 1 + s <= L - 1;
+    if (ha) a = op(mid - 1 - s, nullptr, nullptr, xz_at(mid - s), 1);
+    if (hb) b = op(mid + 1 + s, nullptr, xz_at(mid + s), nullptr, 1);
+    launch(ha ? &a : nullptr, hb ? &b : nullptr);
   }
   zone_copy_kernel<<<std::min<int64_t>(nblocks(c->ndof), 2048), ZBS, 0, st>>>(c->ndof, b, z.r, sc);
   const double se = c->mat.E / c->mat.h;

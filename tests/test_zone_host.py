@@ -101,3 +101,65 @@ def test_self_loops_and_errors():
         binding.zone_levels(np.array([0, 1], dtype=np.int32), np.array([5], dtype=np.int32))
     with pytest.raises(binding.LgdmError):
         binding.zone_levels(np.array([1, 1], dtype=np.int32), np.array([0], dtype=np.int32))
+
+
+@pytest.mark.parametrize("n_groups", [1, 2, 3, 4, 5, 8, 9])
+def test_twisted_block_solve_formulas(n_groups):
+    """The algebra the process-zone solve runs on the GPU, written out on a
+    random block-tridiagonal system: twisted block LU from both ends toward
+    the middle group (inverses G_k of the Schur complements, P_k = G_k
+    Z_k,k-1, N_k = G_k Z_k,k+1), sweeps from both ends, the middle group,
+    and the sweeps back out, equals a dense solve."""
+    rng = np.random.default_rng(n_groups)
+    L = n_groups
+    ms = rng.integers(3, 7, size=L)
+    off = np.concatenate([[0], np.cumsum(ms)])
+    n = int(off[-1])
+    Z = np.zeros((n, n))
+    for k in range(L):
+        sk = slice(off[k], off[k + 1])
+        Z[sk, sk] = rng.standard_normal((ms[k], ms[k])) + 4.0 * np.eye(ms[k])
+        if k > 0:
+            Z[sk, off[k - 1]:off[k]] = rng.standard_normal((ms[k], ms[k - 1]))
+            Z[off[k - 1]:off[k], sk] = rng.standard_normal((ms[k - 1], ms[k]))
+    blk = lambda i, j: Z[off[i]:off[i + 1], off[j]:off[j + 1]]
+    c = L // 2
+    G, P, N = [None] * L, [None] * L, [None] * L
+
+    def finish(k, S):
+        G[k] = np.linalg.inv(S)
+        if k > 0:
+            P[k] = G[k] @ blk(k, k - 1)
+        if k < L - 1:
+            N[k] = G[k] @ blk(k, k + 1)
+
+    for k in range(c):
+        finish(k, blk(k, k) - (blk(k, k - 1) @ N[k - 1] if k > 0 else 0.0))
+    for k in range(L - 1, c, -1):
+        finish(k, blk(k, k) - (blk(k, k + 1) @ P[k + 1] if k < L - 1 else 0.0))
+    S = blk(c, c).copy()
+    if c > 0:
+        S -= blk(c, c - 1) @ N[c - 1]
+    if c < L - 1:
+        S -= blk(c, c + 1) @ P[c + 1]
+    finish(c, S)
+    b = rng.standard_normal(n)
+    x = np.zeros(n)
+    seg = lambda k: slice(off[k], off[k + 1])
+    for s in range(max(c, L - 1 - c)):
+        if s < c:
+            x[seg(s)] = G[s] @ b[seg(s)] - (P[s] @ x[seg(s - 1)] if s > 0 else 0.0)
+        k = L - 1 - s
+        if k > c:
+            x[seg(k)] = G[k] @ b[seg(k)] - (N[k] @ x[seg(k + 1)] if k < L - 1 else 0.0)
+    x[seg(c)] = (G[c] @ b[seg(c)] - (P[c] @ x[seg(c - 1)] if c > 0 else 0.0)
+                 - (N[c] @ x[seg(c + 1)] if c < L - 1 else 0.0))
+    for s in range(max(c, L - 1 - c)):
+        if c - 1 - s >= 0:
+            k = c - 1 - s
+            x[seg(k)] -= N[k] @ x[seg(k + 1)]
+        if c + 1 + s <= L - 1:
+            k = c + 1 + s
+            x[seg(k)] -= P[k] @ x[seg(k - 1)]
+    ref = np.linalg.solve(Z, b)
+    assert np.linalg.norm(x - ref) <= 1e-12 * np.linalg.norm(ref)

@@ -172,7 +172,7 @@ typedef struct lgdm_solver_opts {
   int32_t forcing;         /* LGDM_FORCING_ADAPTIVE                                 */
   int32_t precond;         /* LGDM_PRECOND_DEFAULT                                  */
   int32_t process_zone;    /* LGDM_ZONE_DEFAULT: with the multigrid preconditioner,
-                              the dense process-zone solve (below)                  */
+                              the exact process-zone solve (below)                  */
   int64_t max_increment_krylov;  /* 0 = no bound.  Krylov iterations summed over the
                                     solves of one increment (lgdm_begin_increment to
                                     commit / abort): each solve is limited to what is
@@ -222,9 +222,13 @@ enum { LGDM_FORCING_ADAPTIVE = 0, LGDM_FORCING_FIXED = 1 };
  *          while a level group below exceeds 4,096 unknowns or the factor
  *          panels 2.5 GiB; no zone beyond that);
  *   factor the zone's nodes in breadth-first levels (lgdm_zone_levels), which
- *          make its block Z of S K block tridiagonal; block LU over runs of
- *          levels, each diagonal block inverted (rocSOLVER getrf/getri);
- *   apply  x_z = Z^-1 b_z by the forward and backward block sweeps;
+ *          make its block Z of S K block tridiagonal; consecutive levels form
+ *          groups of at least 768 unknowns; twisted block LU from both end
+ *          groups toward the middle one, the two chains on two streams, each
+ *          Schur complement inverted (rocSOLVER getrf/getri) and multiplied
+ *          into its off-diagonal blocks (rocBLAS gemm);
+ *   apply  x_z = Z^-1 b_z by sweeps from both ends to the middle group and
+ *          back out (one launch per pair of groups);
  *          r = b - S K x_z; out = x_z + (multigrid cycle)(r).
  * Inside a Newton increment the factors are rebuilt only when the zone's node
  * set changes (a later tangent of the increment with the same zone keeps
@@ -234,8 +238,9 @@ enum { LGDM_FORCING_ADAPTIVE = 0, LGDM_FORCING_FIXED = 1 };
  * the merit of the line search (no new smallest value in 4 iterations), or
  * return a correction no better than none, the increment restarts from its
  * beginning with the zone's damage threshold moved tenfold closer to 1, and
- * should that stall too, without the zone (zone_restarts in the report).  The factors are allocated through the context's allocator
- * the first time a zone of that size occurs and kept.
+ * should that stall too, without the zone (zone_restarts in the report).
+ * The factors are allocated through the context's allocator the first time a
+ * zone of that size occurs and kept.
  * LGDM_ZONE_OFF: the plain cycle. */
 enum { LGDM_ZONE_DEFAULT = 0, LGDM_ZONE_OFF = 1, LGDM_ZONE_EVERY_TANGENT = 2 };
 
@@ -282,7 +287,7 @@ typedef struct lgdm_increment_report {
   int32_t precond_fallbacks; /* multigrid solves without progress, repeated with
                                 block-Jacobi                                        */
   int32_t backtracks;      /* halvings of a Newton correction (line search)         */
-  int64_t zone_dofs;       /* largest process zone solved densely in the solves
+  int64_t zone_dofs;       /* largest process zone solved exactly in the solves
                               (unknowns; 0: none), see LGDM_ZONE_DEFAULT           */
   double t_zone_ms;        /* host time choosing and factoring the process zones,
                               part of t_solve_ms                                    */

@@ -536,9 +536,10 @@ def main():
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--tol-krylov", type=float, default=1e-3,
+    ap.add_argument("--tol-krylov", type=float, default=3e-4,
                     help="relative tolerance of the Newton corrections far from convergence (the last "
-                         "ones solve only as far as the Newton test needs)")
+                         "ones solve only as far as the Newton test needs); 3e-4 converges the 128x32x16 "
+                         "beam's whole load path, where 1e-3 stops in the softening branch")
     ap.add_argument("--krylov", default="idr", choices=["idr", "bicgstab"])
     ap.add_argument("--idr-s", type=int, default=8)
     ap.add_argument("--precond", default="default", choices=["default", "bj", "amg"],

@@ -53,6 +53,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "lgdm_internal.h"
@@ -613,7 +614,8 @@ hipError_t zone_setup(lgdm_ctx* c, bool allow_alloc, bool reuse, double dmin0, b
   auto Pk = [&](int64_t k) { return z.Q + z.qoff[k]; };
   auto Nk = [&](int64_t k) { return z.Q + z.qoff[k] + gsize(k) * gsize(k - 1); };
   // S_k -= Z_k,j X (X: m_j x m_k, the neighbour j's P or N), then G_k, P_k, N_k
-  auto factor_group = [&](rocblas_handle h, rocblas_int* piv, int64_t k, bool from_prev, bool from_next) {
+  auto factor_group = [&](rocblas_handle h, rocblas_int* piv, int64_t k, bool from_prev, bool from_next,
+                          std::string& msg) {
     const rocblas_int im = (rocblas_int)gsize(k), imp = (rocblas_int)gsize(k - 1), imn = (rocblas_int)gsize(k + 1);
     hipError_t r;
     if (from_prev &&
@@ -640,12 +642,32 @@ hipError_t zone_setup(lgdm_ctx* c, bool allow_alloc, bool reuse, double dmin0, b
     return hipSuccess;
   };
   if ((e = hipEventRecord(z.ev_built, c->stream)) || (e = hipStreamWaitEvent(z.stream2, z.ev_built, 0))) return e;
-  for (int64_t k = 0; k < mid; ++k)
-    if ((e = factor_group(z.handle, z.ipiv, k, k > 0, false))) return e;
-  for (int64_t k = NG - 1; k > mid; --k)
-    if ((e = factor_group(z.handle2, z.ipiv2, k, false, k < NG - 1))) return e;
-  if ((e = hipEventRecord(z.ev_chain2, z.stream2)) || (e = hipStreamWaitEvent(c->stream, z.ev_chain2, 0))) return e;
-  if ((e = factor_group(z.handle, z.ipiv, mid, mid > 0, mid < NG - 1))) return e;
+  // each chain is thousands of short rocSOLVER launches, so one host thread
+  // issuing both is bound by its launch rate: the bottom chain is issued
+  // from a second thread (HIP's current device is per thread)
+  hipError_t e2 = hipSuccess;
+  std::string msg2;
+  auto bottom_chain = [&] {
+    e2 = hipSetDevice(c->device);
+    for (int64_t k = NG - 1; k > mid && e2 == hipSuccess; --k)
+      e2 = factor_group(z.handle2, z.ipiv2, k, false, k < NG - 1, msg2);
+    if (e2 == hipSuccess) e2 = hipEventRecord(z.ev_chain2, z.stream2);
+  };
+  std::thread chain2;
+  try {
+    chain2 = std::thread(bottom_chain);
+  } catch (...) {
+    bottom_chain();   // no thread available: the same launches from this one
+  }
+  for (int64_t k = 0; k < mid && e == hipSuccess; ++k) e = factor_group(z.handle, z.ipiv, k, k > 0, false, msg);
+  if (chain2.joinable()) chain2.join();
+  if (e) return e;
+  if (e2) {
+    msg = msg2;
+    return e2;
+  }
+  if ((e = hipStreamWaitEvent(c->stream, z.ev_chain2, 0))) return e;
+  if ((e = factor_group(z.handle, z.ipiv, mid, mid > 0, mid < NG - 1, msg))) return e;
   // the sweeps read rows of [G_k | P_k | N_k] in row-major order
   for (int64_t k = 0; k < NG; ++k) {
     const int64_t m = gsize(k), mp = gsize(k - 1), mn = gsize(k + 1), lda = m + mp + mn;

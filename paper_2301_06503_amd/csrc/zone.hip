@@ -90,8 +90,10 @@ struct Zone {
   double* P = nullptr;                      // [cap_p]
   double* Q = nullptr;                      // [cap_q]
   // the sweeps' matrices, row major, in P's layout: per group k the rows of
-  // [G_k | P_k | N_k] (m_k + m_{k-1} + m_{k+1} each)
-  double* T = nullptr;                      // [cap_p]
+  // [G_k | P_k | N_k] (m_k + m_{k-1} + m_{k+1} each); FP32 in mixed
+  // contexts (t32), FP64 otherwise
+  double* T = nullptr;                      // [cap_p] doubles of storage
+  bool t32 = false;
   rocblas_int* ipiv = nullptr;              // [cap_m] pivots of the chain from group 0
   rocblas_int* ipiv2 = nullptr;             // [cap_m] pivots of the chain from group L-1
   rocblas_int* info = nullptr;              // [2 cap_groups]
@@ -181,12 +183,13 @@ __global__ void zone_gather_kernel(int64_t nz, const int32_t* __restrict__ znode
 
 // Row-major copy of a column-major m x n block: out[r * ldo + c0 + c] =
 // A[r + c * m]; one thread per entry
-__global__ void zone_rowmajor_kernel(int64_t m, int64_t n, const double* __restrict__ A, double* __restrict__ out,
+template <typename TO>
+__global__ void zone_rowmajor_kernel(int64_t m, int64_t n, const double* __restrict__ A, TO* __restrict__ out,
                                      int64_t ldo, int64_t c0) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= m * n) return;
   const int64_t r = t % m, c = t / m;
-  out[r * ldo + c0 + c] = A[t];
+  out[r * ldo + c0 + c] = (TO)A[t];
 }
 
 // One group's step of a sweep: y[r] = sum_c A[r, c] u[c] - sum_c
@@ -196,7 +199,7 @@ __global__ void zone_rowmajor_kernel(int64_t m, int64_t n, const double* __restr
 // are combined by a fixed butterfly, so every apply sums in the same order.
 struct SweepOp {
   int64_t m, lda;
-  const double* A;
+  const void* A;   // TA, row major
   const double* u;
   int64_t nu;
   const double* v;
@@ -209,8 +212,29 @@ struct SweepOp {
 constexpr int SW_ROWS = ZBS / 64;
 inline unsigned sweep_blocks(const SweepOp& o) { return (unsigned)((o.m + SW_ROWS - 1) / SW_ROWS); }
 
+// acc += sgn * a[c] * x[c] for c = lane, lane + 64, ... < n, in that order;
+// eight loads of each operand are issued before their products are summed
+// (one load pair in flight per wavefront left the sweeps latency bound)
+template <typename TA>
+__device__ __forceinline__ void sweep_dot(const TA* __restrict__ a, const double* __restrict__ x, int64_t n,
+                                          int lane, double sgn, double& acc) {
+  int64_t c = lane;
+  for (; c + 7 * 64 < n; c += 8 * 64) {
+    double av[8], xv[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      av[j] = (double)a[c + j * 64];
+      xv[j] = x[c + j * 64];
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc += sgn * av[j] * xv[j];
+  }
+  for (; c < n; c += 64) acc += sgn * (double)a[c] * x[c];
+}
+
 // two independent group steps in one launch (the two ends of the twisted
 // sweep): blocks [0, nblk_a) take a, the rest take b
+template <typename TA>
 __global__ void __launch_bounds__(ZBS) zone_sweep_kernel(SweepOp a, SweepOp b, unsigned nblk_a,
                                                          const double* __restrict__ sc) {
   if (sc && sc[KSLOT_DONE] != 0.0) return;
@@ -219,11 +243,11 @@ __global__ void __launch_bounds__(ZBS) zone_sweep_kernel(SweepOp a, SweepOp b, u
   const int lane = threadIdx.x % 64;
   const int64_t row = (int64_t)(first ? blockIdx.x : blockIdx.x - nblk_a) * SW_ROWS + threadIdx.x / 64;
   if (row >= o.m) return;  // uniform over the wavefront
-  const double* __restrict__ r = o.A + row * o.lda;
+  const TA* __restrict__ r = static_cast<const TA*>(o.A) + row * o.lda;
   double acc = 0.0;
-  for (int64_t c = lane; c < o.nu; c += 64) acc += r[c] * o.u[c];
-  for (int64_t c = lane; c < o.nv; c += 64) acc -= r[o.op + c] * o.v[c];
-  for (int64_t c = lane; c < o.nw; c += 64) acc -= r[o.on + c] * o.w[c];
+  sweep_dot<TA>(r, o.u, o.nu, lane, 1.0, acc);
+  sweep_dot<TA>(r + o.op, o.v, o.nv, lane, -1.0, acc);
+  sweep_dot<TA>(r + o.on, o.w, o.nw, lane, -1.0, acc);
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
   if (lane == 0) o.y[row] = o.accumulate ? o.y[row] + acc : acc;
 }
@@ -668,13 +692,24 @@ hipError_t zone_setup(lgdm_ctx* c, bool allow_alloc, bool reuse, double dmin0, b
   }
   if ((e = hipStreamWaitEvent(c->stream, z.ev_chain2, 0))) return e;
   if ((e = factor_group(z.handle, z.ipiv, mid, mid > 0, mid < NG - 1, msg))) return e;
-  // the sweeps read rows of [G_k | P_k | N_k] in row-major order
+  // the sweeps read rows of [G_k | P_k | N_k] in row-major order, in FP32
+  // in mixed contexts (the matrix values there are FP32 too)
+  z.t32 = c->precision == LGDM_MIXED;
   for (int64_t k = 0; k < NG; ++k) {
     const int64_t m = gsize(k), mp = gsize(k - 1), mn = gsize(k + 1), lda = m + mp + mn;
-    double* Tk = z.T + z.poff[k];
-    zone_rowmajor_kernel<<<nblocks(m * m), ZBS, 0, c->stream>>>(m, m, Zdiag(k), Tk, lda, 0);
-    if (mp > 0) zone_rowmajor_kernel<<<nblocks(m * mp), ZBS, 0, c->stream>>>(m, mp, Pk(k), Tk, lda, m);
-    if (mn > 0) zone_rowmajor_kernel<<<nblocks(m * mn), ZBS, 0, c->stream>>>(m, mn, Nk(k), Tk, lda, m + mp);
+    if (z.t32) {
+      float* Tk = reinterpret_cast<float*>(z.T) + z.poff[k];
+      zone_rowmajor_kernel<float><<<nblocks(m * m), ZBS, 0, c->stream>>>(m, m, Zdiag(k), Tk, lda, 0);
+      if (mp > 0) zone_rowmajor_kernel<float><<<nblocks(m * mp), ZBS, 0, c->stream>>>(m, mp, Pk(k), Tk, lda, m);
+      if (mn > 0)
+        zone_rowmajor_kernel<float><<<nblocks(m * mn), ZBS, 0, c->stream>>>(m, mn, Nk(k), Tk, lda, m + mp);
+    } else {
+      double* Tk = z.T + z.poff[k];
+      zone_rowmajor_kernel<double><<<nblocks(m * m), ZBS, 0, c->stream>>>(m, m, Zdiag(k), Tk, lda, 0);
+      if (mp > 0) zone_rowmajor_kernel<double><<<nblocks(m * mp), ZBS, 0, c->stream>>>(m, mp, Pk(k), Tk, lda, m);
+      if (mn > 0)
+        zone_rowmajor_kernel<double><<<nblocks(m * mn), ZBS, 0, c->stream>>>(m, mn, Nk(k), Tk, lda, m + mp);
+    }
   }
   if ((e = hipGetLastError())) return e;
   std::vector<rocblas_int> info(2 * z.L, 0);
@@ -723,7 +758,7 @@ hipError_t zone_apply(lgdm_ctx* c, const double* b, double* out, const double* s
     SweepOp o;
     o.m = m;
     o.lda = m + mp + mn;
-    o.A = z.T + z.poff[k];
+    o.A = z.t32 ? (const void*)(reinterpret_cast<const float*>(z.T) + z.poff[k]) : (const void*)(z.T + z.poff[k]);
     o.u = u;
     o.nu = u ? m : 0;
     o.v = v;
@@ -740,7 +775,8 @@ hipError_t zone_apply(lgdm_ctx* c, const double* b, double* out, const double* s
     const SweepOp& first = a ? *a : *b;
     const SweepOp& second = a && b ? *b : first;
     const unsigned na = sweep_blocks(first), nb = a && b ? sweep_blocks(second) : 0;
-    zone_sweep_kernel<<<na + nb, ZBS, 0, st>>>(first, second, na, sc);
+    if (z.t32) zone_sweep_kernel<float><<<na + nb, ZBS, 0, st>>>(first, second, na, sc);
+    else zone_sweep_kernel<double><<<na + nb, ZBS, 0, st>>>(first, second, na, sc);
   };
   const int64_t steps = std::max(mid, L - 1 - mid);
   auto xz_at = [&](int64_t k) { return (const double*)(z.xz + z.goff[k]); };

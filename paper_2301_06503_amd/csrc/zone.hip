@@ -261,28 +261,46 @@ __global__ void zone_copy_kernel(int64_t n, const double* __restrict__ b, double
 }
 
 // r_h = b_h - sum over zone neighbours q of (S K)_{hq} x_z(q), rows of the
-// halo nodes (neighbour order: fixed); one thread per (halo node, row)
+// halo nodes: RES_G lanes per halo node, lane l taking neighbour positions
+// l, l + RES_G, ...; the four row sums are combined by a fixed butterfly
+constexpr int RES_G = 16;
 template <typename T>
-__global__ void zone_residual_kernel(int64_t nh, const int32_t* __restrict__ halo, const int32_t* __restrict__ zmap,
-                                     const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ nbr_ptr,
-                                     const int32_t* __restrict__ nbr, const T* __restrict__ vals, double se,
-                                     const double* __restrict__ b, const double* __restrict__ xz,
-                                     double* __restrict__ r, const double* __restrict__ sc) {
+__global__ void __launch_bounds__(ZBS) zone_residual_kernel(
+    int64_t nh, const int32_t* __restrict__ halo, const int32_t* __restrict__ zmap,
+    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ nbr_ptr, const int32_t* __restrict__ nbr,
+    const T* __restrict__ vals, double se, const double* __restrict__ b, const double* __restrict__ xz,
+    double* __restrict__ r, const double* __restrict__ sc) {
   if (sc && sc[KSLOT_DONE] != 0.0) return;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nh * 4) return;
-  const int64_t h = halo[t / 4];
-  const int i = (int)(t % 4);
+  const int64_t hi = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / RES_G;
+  const int lane = threadIdx.x % RES_G;
+  if (hi >= nh) return;  // uniform over the lane group
+  const int64_t h = halo[hi];
   const int nb0 = nbr_ptr[h], nnb = nbr_ptr[h + 1] - nb0;
-  const int64_t rowlen = (int64_t)nnb * 4, rs = row_ptr[h * 4] + i * rowlen;
-  double acc = 0.0;
-  for (int p = 0; p < nnb; ++p) {
+  const int64_t rowlen = (int64_t)nnb * 4, rs = row_ptr[h * 4];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int p = lane; p < nnb; p += RES_G) {
     const int32_t zq = zmap[nbr[nb0 + p]];
     if (zq < 0) continue;
-    for (int j = 0; j < 4; ++j) acc += (double)vals[rs + (int64_t)p * 4 + j] * xz[4 * (int64_t)zq + j];
+    double x[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) x[j] = xz[4 * (int64_t)zq + j];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i] += (double)vals[rs + i * rowlen + (int64_t)p * 4 + j] * x[j];
   }
-  const int64_t row = h * 4 + i;
-  r[row] = b[row] - (i == 3 ? se : 1.0) * acc;
+#pragma unroll
+  for (int o = RES_G / 2; o > 0; o >>= 1)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] += __shfl_xor(acc[i], o, RES_G);
+  if (lane < 4) {
+    double mine = acc[0];
+#pragma unroll
+    for (int i = 1; i < 4; ++i)
+      if (lane == i) mine = acc[i];
+    const int64_t row = h * 4 + lane;
+    r[row] = b[row] - (lane == 3 ? se : 1.0) * mine;
+  }
 }
 
 // out += x_z at the zone's unknowns
@@ -802,10 +820,10 @@ hipError_t zone_apply(lgdm_ctx* c, const double* b, double* out, const double* s
   zone_copy_kernel<<<std::min<int64_t>(nblocks(c->ndof), 2048), ZBS, 0, st>>>(c->ndof, b, z.r, sc);
   const double se = c->mat.E / c->mat.h;
   if (c->precision == LGDM_MIXED)
-    zone_residual_kernel<float><<<nblocks(z.nh * 4), ZBS, 0, st>>>(z.nh, z.halo, z.zmap, c->row_ptr, c->nbr_ptr,
+    zone_residual_kernel<float><<<nblocks(z.nh * RES_G), ZBS, 0, st>>>(z.nh, z.halo, z.zmap, c->row_ptr, c->nbr_ptr,
                                                                    c->nbr, c->vals32, se, b, z.xz, z.r, sc);
   else
-    zone_residual_kernel<double><<<nblocks(z.nh * 4), ZBS, 0, st>>>(z.nh, z.halo, z.zmap, c->row_ptr, c->nbr_ptr,
+    zone_residual_kernel<double><<<nblocks(z.nh * RES_G), ZBS, 0, st>>>(z.nh, z.halo, z.zmap, c->row_ptr, c->nbr_ptr,
                                                                     c->nbr, c->vals, se, b, z.xz, z.r, sc);
   hipError_t e;
   if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -634,6 +634,19 @@ def main():
     roof_asm = {"bound": "hbm", "kernel": "gauss_point+node_assembly",
                 "achieved": round(main_res["assembly_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(main_res["assembly_gbs"] / HBM_PEAK_GBS, 4)}
+    # assembly and SpMV together over the timed steps: algorithmic bytes of
+    # every assembly and every SpMV launch over their kernel time (assembly:
+    # back-to-back timing; SpMV: the live probe)
+    roof_asm_spmv = None
+    if pr["gbs"] and main_res["spmv_launches"] > 0:
+        nb_tot = (main_res["assemblies"] * main_res["assembly_bytes"] +
+                  main_res["spmv_launches"] * pr["algorithmic_bytes"])
+        ms_tot = (main_res["assemblies"] * (kt["gauss_point"] + kt["node_assembly"]) +
+                  main_res["spmv_launches"] * pr["avg_ms"])
+        gbs = nb_tot / (ms_tot * 1e-3) / 1e9
+        roof_asm_spmv = {"bound": "hbm", "kernel": "assembly + IDR SpMV", "achieved": round(gbs, 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                         "bytes": nb_tot, "kernel_ms": round(ms_tot, 1)}
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.config, prob)
@@ -663,6 +676,7 @@ def main():
                    "fp64_newton_step_ms": fp64_res["newton_step_ms"] if fp64_res else None},
         "roofline": roofline,
         "roofline_assembly": roof_asm,
+        "roofline_assembly_spmv": roof_asm_spmv,
         "cpu_baseline": cpu,
         "copy_calibration": copy_cal,
         "serving": serving_res,

@@ -223,7 +223,7 @@ enum { LGDM_FORCING_ADAPTIVE = 0, LGDM_FORCING_FIXED = 1 };
  *          panels 2.5 GiB; no zone beyond that);
  *   factor the zone's nodes in breadth-first levels (lgdm_zone_levels), which
  *          make its block Z of S K block tridiagonal; consecutive levels form
- *          groups of at least 768 unknowns; twisted block LU from both end
+ *          groups of at least 512 unknowns; twisted block LU from both end
  *          groups toward the middle one, the two chains on two streams, each
  *          Schur complement inverted (rocSOLVER getrf/getri) and multiplied
  *          into its off-diagonal blocks (rocBLAS gemm);

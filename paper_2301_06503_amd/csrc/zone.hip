@@ -62,7 +62,7 @@ namespace lgdm {
 
 namespace {
 
-constexpr int64_t ZONE_GROUP_MIN = 768;           // unknowns per group, at least (but the last)
+constexpr int64_t ZONE_GROUP_MIN = 512;           // unknowns per group, at least (but the last)
 constexpr int64_t ZONE_MAX_GROUP = 4096;          // unknowns per group, at most
 constexpr int64_t ZONE_MAX_PANEL = 320ll << 20;   // doubles of the factor panels P + Q (2.5 GiB)
 

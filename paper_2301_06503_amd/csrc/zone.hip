@@ -569,7 +569,9 @@ hipError_t zone_setup(lgdm_ctx* c, bool allow_alloc, bool reuse, double dmin0, b
   if (z.nz > z.cap_nodes || z.nh > z.cap_halo || z.L > z.cap_groups || np > z.cap_p || nq > z.cap_q ||
       z.mmax > z.cap_m) {
     if (!allow_alloc) return hipErrorNotReady;
-    // grow the buffers to this zone (kept for later tangents)
+    // grow the buffers to this zone (kept for later tangents); nothing of an
+    // earlier factorisation may still run on stream2 when they are freed
+    if ((e = hipStreamSynchronize(z.stream2))) return e;
     const int64_t capn = std::max(z.nz, z.cap_nodes), caph = std::max(z.nh, z.cap_halo),
                   capg = std::max(z.L, z.cap_groups), capp = std::max(np, z.cap_p), capq = std::max(nq, z.cap_q),
                   capm = std::max(z.mmax, z.cap_m);
@@ -703,8 +705,12 @@ hipError_t zone_setup(lgdm_ctx* c, bool allow_alloc, bool reuse, double dmin0, b
   }
   for (int64_t k = 0; k < mid && e == hipSuccess; ++k) e = factor_group(z.handle, z.ipiv, k, k > 0, false, msg);
   if (chain2.joinable()) chain2.join();
-  if (e) return e;
-  if (e2) {
+  if (e || e2) {
+    // the other chain's launches may still run: finish them before the
+    // buffers can be freed or refilled
+    (void)hipStreamSynchronize(z.stream2);
+    (void)hipStreamSynchronize(c->stream);
+    if (e) return e;
     msg = msg2;
     return e2;
   }

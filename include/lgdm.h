@@ -224,7 +224,9 @@ enum { LGDM_FORCING_ADAPTIVE = 0, LGDM_FORCING_FIXED = 1 };
  *   factor the zone's nodes in breadth-first levels (lgdm_zone_levels), which
  *          make its block Z of S K block tridiagonal; consecutive levels form
  *          groups of at least 512 unknowns; twisted block LU from both end
- *          groups toward the middle one, the two chains on two streams, each
+ *          groups toward the middle one, the two chains on two streams
+ *          (the second issued from a host thread the library starts for the
+ *          factorisation and joins before it returns), each
  *          Schur complement inverted (rocSOLVER getrf/getri) and multiplied
  *          into its off-diagonal blocks (rocBLAS gemm);
  *   apply  x_z = Z^-1 b_z by sweeps from both ends to the middle group and

@@ -29,12 +29,12 @@ def _whole_mesh_zone_state(prob):
     return x, kn
 
 
-@pytest.mark.parametrize("nx", [40, 96])
-def test_zone_covering_the_mesh_solves_exactly(nx):
+@pytest.mark.parametrize("nx,precision", [(40, 0), (96, 0), (96, 1)])
+def test_zone_covering_the_mesh_solves_exactly(nx, precision):
     import scipy.sparse.linalg as spla
     from paper_2301_06503_amd import binding
     prob = W.beam3d(nx=nx, ny=2, nz=2, lx=2.0 * nx, ly=4.0, lz=4.0, u_load=-0.02, n_increments=20)
-    print("case: slender beam %dx2x2, whole-mesh process zone" % nx, flush=True)
+    print("case: slender beam %dx2x2, whole-mesh process zone, precision %d" % (nx, precision), flush=True)
     x, kn = _whole_mesh_zone_state(prob)
     st = Oracle(prob).eval_state(x, kn)
     # the premise: every point loads, with damage above the threshold
@@ -42,14 +42,14 @@ def test_zone_covering_the_mesh_solves_exactly(nx):
     assert st["D"].min() >= ZONE_DAMAGE, st["D"].min()
     # more than one level group of at least 512 unknowns (about 3 and 7)
     assert prob.ndof >= 2 * 512
-    ctx = context(prob)
+    ctx = context(prob, precision)
     ctx.set_state(x, kn)
     view, R = ctx.assemble()
     # the GPU's own tangent (its values against the oracle's: the assembly
     # parity tests)
     import scipy.sparse as sp
     rp, ci = ctx.csr_pattern()
-    Kg = sp.csr_matrix((ctx.csr_values(view), ci, rp), shape=(prob.ndof, prob.ndof))
+    Kg = sp.csr_matrix((ctx.csr_values(view).astype(np.float64), ci, rp), shape=(prob.ndof, prob.ndof))
     b = R.cpu().numpy()
     opts = binding.solver_opts(tol_krylov=1e-12, max_krylov=2000, precond=binding.PRECOND_AMG,
                                process_zone=binding.ZONE_DEFAULT, zone_damage=ZONE_DAMAGE)
@@ -71,11 +71,19 @@ def test_zone_covering_the_mesh_solves_exactly(nx):
     # ~5e12), so two solutions with residuals at rounding level differ by up
     # to ~1e-3: the solve is judged by its true residual and by the step
     # count of an exact preconditioner
-    assert ru <= 1e-10 and re <= 1e-10, (ru, re)
-    assert rep["krylov_iters"] <= 4, rep["krylov_iters"]             # measured: 2
-    # the direct LU of the oracle's tangent agrees far inside that bound
-    # (measured ~1e-7)
-    assert max(fieldwise_error(d, ref, nd).values()) <= 1e-5
+    # (mixed: the residual of the FP64-valued tangent; the solve ran on its
+    # FP32 rounding, which moves it by ~5e-10 on this tangent)
+    bound = 1e-10 if precision == 0 else 1e-8
+    assert ru <= bound and re <= bound, (ru, re)
+    if precision == 0:
+        assert rep["krylov_iters"] <= 4, rep["krylov_iters"]         # measured: 2
+        # the direct LU of the oracle's tangent agrees far inside that bound
+        # (measured ~1e-7)
+        assert max(fieldwise_error(d, ref, nd).values()) <= 1e-5
+    else:
+        # FP32 tangent values and FP32 factor rows: the zone solve is exact
+        # to single precision, so a few more steps reach the same residual
+        assert rep["krylov_iters"] <= 16, rep["krylov_iters"]
     assert np.all(d[Oracle(prob).bc_dofs] == 0.0)
     # the same system without the zone, to a looser tolerance: the cycle alone
     # needs far more steps (measured 424 and 1,741), or does not get there

@@ -169,6 +169,21 @@ def algorithmic_bytes(prob, nnz, npairs, s_val):
     return asm, spmv
 
 
+def assembly_spmv_roofline(res):
+    """Assembly and SpMV together over the timed steps: the algorithmic bytes
+    of every assembly and every SpMV launch over their kernel time (assembly:
+    back-to-back launch time; SpMV: the live probe), against the HBM peak."""
+    pr, kt = res["probe"], res["kernel_ms"]
+    if not pr.get("gbs") or res["spmv_launches"] <= 0:
+        return None
+    nb_tot = res["assemblies"] * res["assembly_bytes"] + res["spmv_launches"] * pr["algorithmic_bytes"]
+    ms_tot = (res["assemblies"] * (kt["gauss_point"] + kt["node_assembly"]) +
+              res["spmv_launches"] * pr["avg_ms"])
+    gbs = nb_tot / (ms_tot * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": "assembly + IDR SpMV", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes": nb_tot, "kernel_ms": round(ms_tot, 1)}
+
+
 def committed_traffic(kernel_key, launches_bytes):
     """HBM bytes per launch of the dominant kernel from the committed
     rocprofv3 FETCH_SIZE / WRITE_SIZE counters (scaled by the same counters
@@ -634,19 +649,7 @@ def main():
     roof_asm = {"bound": "hbm", "kernel": "gauss_point+node_assembly",
                 "achieved": round(main_res["assembly_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(main_res["assembly_gbs"] / HBM_PEAK_GBS, 4)}
-    # assembly and SpMV together over the timed steps: algorithmic bytes of
-    # every assembly and every SpMV launch over their kernel time (assembly:
-    # back-to-back timing; SpMV: the live probe)
-    roof_asm_spmv = None
-    if pr["gbs"] and main_res["spmv_launches"] > 0:
-        nb_tot = (main_res["assemblies"] * main_res["assembly_bytes"] +
-                  main_res["spmv_launches"] * pr["algorithmic_bytes"])
-        ms_tot = (main_res["assemblies"] * (kt["gauss_point"] + kt["node_assembly"]) +
-                  main_res["spmv_launches"] * pr["avg_ms"])
-        gbs = nb_tot / (ms_tot * 1e-3) / 1e9
-        roof_asm_spmv = {"bound": "hbm", "kernel": "assembly + IDR SpMV", "achieved": round(gbs, 1),
-                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
-                         "bytes": nb_tot, "kernel_ms": round(ms_tot, 1)}
+    roof_asm_spmv = assembly_spmv_roofline(main_res)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.config, prob)

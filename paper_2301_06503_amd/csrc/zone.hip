@@ -182,7 +182,7 @@ __global__ void zone_gather_kernel(int64_t nz, const int32_t* __restrict__ znode
 }
 
 // Row-major copy of a column-major m x n block: out[r * ldo + c0 + c] =
-// A[r + c * m]; one thread per entry
+// A[r + c * m], rounded once to TO; one thread per entry
 template <typename TO>
 __global__ void zone_rowmajor_kernel(int64_t m, int64_t n, const double* __restrict__ A, TO* __restrict__ out,
                                      int64_t ldo, int64_t c0) {
@@ -194,9 +194,10 @@ __global__ void zone_rowmajor_kernel(int64_t m, int64_t n, const double* __restr
 
 // One group's step of a sweep: y[r] = sum_c A[r, c] u[c] - sum_c
 // A[r, op + c] v[c] - sum_c A[r, on + c] w[c] for r < m (A row major with
-// leading dimension lda; nu, nv or nw may be 0), with accumulate y[r] plus
-// that.  One wavefront per row; lanes stride the row by 64 (coalesced) and
-// are combined by a fixed butterfly, so every apply sums in the same order.
+// leading dimension lda, element type TA of the kernel; nu, nv or nw may be
+// 0), with accumulate y[r] plus that; products and sums in FP64.  One
+// wavefront per row; lanes stride the row by 64 (coalesced) and are combined
+// by a fixed butterfly, so every apply sums in the same order.
 struct SweepOp {
   int64_t m, lda;
   const void* A;   // TA, row major

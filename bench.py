@@ -560,7 +560,7 @@ def main():
     ap.add_argument("--precond", default="default", choices=["default", "bj", "amg"],
                     help="block-Jacobi or aggregation multigrid (IDR only); the default is multigrid on 3D meshes")
     ap.add_argument("--zone", default="default", choices=["default", "off", "every"],
-                    help="dense process-zone solve in the multigrid preconditioner: default (inverse kept while "
+                    help="exact process-zone solve in the multigrid preconditioner: default (factors kept while "
                          "the zone's nodes stay the same within an increment), off, or every (rebuilt for every "
                          "tangent)")
     ap.add_argument("--zone-damage", type=float, default=0.99,
